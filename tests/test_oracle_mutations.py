@@ -1,0 +1,103 @@
+"""Planted mistakes in the oracle (on the CPU): each plausible error in a step
+of Algorithms 1-3 must make at least one pin fail.  This shows the pins are
+sensitive enough to trust the oracle they accept."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle.ozaki2 as oz
+from pins import all_pins
+from workload import gemm_inputs
+
+
+def _const_mut(monkeypatch, fn):
+    real = oz.constants
+
+    def patched(N, b=64):
+        return fn(real(N, b))
+    monkeypatch.setattr(oz, "constants", patched)
+
+
+def m_s2_sign(mp):
+    _const_mut(mp, lambda c: dataclasses.replace(c, s2=tuple(-v for v in c.s2)))
+
+
+def m_drop_P2(mp):
+    _const_mut(mp, lambda c: dataclasses.replace(c, P2=0.0))
+
+
+def m_wrong_q(mp):
+    def f(c):
+        q = tuple((v % (p - 1)) + 1 if p > 2 else v for v, p in zip(c.q, c.p))
+        q = (q[0],) + (q[1] % (c.p[1] - 1) + 1,) + q[2:]
+        x = tuple((c.P // p) * v for p, v in zip(c.p, q))
+        return dataclasses.replace(c, q=q, x=x)
+    _const_mut(mp, f)
+
+
+def m_shift_plus_one(mp):
+    real = oz.shift
+    mp.setattr(oz, "shift", lambda a, b, c: real(a, b, c) + 1)
+
+
+def m_floor_mod(mp):
+    mp.setattr(oz, "mod_sym", lambda X, p: np.asarray(np.mod(X, p)).astype(np.int64))
+
+
+def m_transposed_operand(mp):
+    real = oz.exact_int_matmul
+
+    def f(X, Y, bound):
+        if bound == 128.0 * 128.0 * max(X.shape[1], 1):
+            return real(X, Y.T.copy(), bound)
+        return real(X, Y, bound)
+    mp.setattr(oz, "exact_int_matmul", f)
+
+
+def m_floor_instead_of_ceil(mp):
+    def f(absX, shift):
+        v = np.floor(np.ldexp(absX, shift.astype(np.int32)))
+        return v.astype(np.int64)
+    mp.setattr(oz, "ceil_scaled", f)
+
+
+def m_unscale_sign(mp):
+    real = oz.unscale
+    mp.setattr(oz, "unscale", lambda C, mu, nu, b: real(C, -mu + 2 * mu.min(), nu, b))
+
+
+def m_drop_C2(mp):
+    real = oz.crt_reconstruct
+
+    def f(W, const):
+        out = real(W, const)
+        if const.b == 64:
+            out = dict(out)
+            out["C2"] = np.zeros_like(out["C2"])
+        return out
+    mp.setattr(oz, "crt_reconstruct", f)
+
+
+MUTATIONS = [m_s2_sign, m_drop_P2, m_wrong_q, m_shift_plus_one, m_floor_mod,
+             m_transposed_operand, m_floor_instead_of_ceil, m_unscale_sign]
+
+
+@pytest.mark.parametrize("mutation", MUTATIONS, ids=lambda f: f.__name__)
+def test_planted_mistake_is_caught(monkeypatch, mutation):
+    mutation(monkeypatch)
+    A, B = gemm_inputs(6, 6, 6, phi=1.0, seed=21)
+    try:
+        _, st = oz.os_ii(A, B, 14, stages=True)
+    except AssertionError:
+        return          # the oracle's own run-time assertions caught it
+    assert all_pins(A, B, st) != []
+
+
+def test_dropping_C2_is_caught(monkeypatch):
+    # C'(2) carries only the low part of the CRT sum; dropping it must break
+    # Lemma 2 (and Lemma 4) at N = 14.
+    m_drop_C2(monkeypatch)
+    A, B = gemm_inputs(6, 6, 6, phi=1.0, seed=22)
+    _, st = oz.os_ii(A, B, 14, stages=True)
+    assert all_pins(A, B, st) != []

@@ -1,0 +1,54 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds no arithmetic of the method: it only draws matrices.
+
+Recipe (the paper's experimental setup, Section 5): every entry is
+(rand - 0.5) * exp(phi * randn), rand uniform, randn standard normal;
+phi controls the exponent spread.  numpy's PCG64 generator
+(``default_rng(seed)``) draws, per matrix, first the uniform array then the
+normal array, in row-major order of the matrix's logical shape; A is drawn
+before B.  FP32 inputs are the FP64 draws rounded to nearest.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def draw_matrix(rng: np.random.Generator, shape, phi: float) -> np.ndarray:
+    U = rng.random(shape)
+    Z = rng.standard_normal(shape)
+    return (U - 0.5) * np.exp(phi * Z)
+
+
+def gemm_inputs(m: int, n: int, k: int, phi: float = 0.5, seed: int = 0,
+                dtype=np.float64):
+    """A (m x k) and B (k x n) for one emulated GEMM."""
+    rng = np.random.default_rng(seed)
+    A = draw_matrix(rng, (m, k), phi)
+    B = draw_matrix(rng, (k, n), phi)
+    return A.astype(dtype), B.astype(dtype)
+
+
+def batched_shapes(count: int = 512, lo: int = 64, hi: int = 2048, seed: int = 0):
+    """(m, n, k) per problem, each log-uniform in [lo, hi], drawn in the order
+    m, n, k per problem before any matrix.  Returns (rng, shapes) so that the
+    caller can continue drawing the matrices from the same stream."""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for _ in range(count):
+        mnk = [int(round(math.exp(rng.uniform(math.log(lo), math.log(hi))))) for _ in range(3)]
+        shapes.append(tuple(mnk))
+    return rng, shapes
+
+
+def batched_inputs(count: int = 512, phi: float = 1.0, seed: int = 0, dtype=np.float64):
+    """Uneven batch: list of (A, B) pairs, shapes from batched_shapes."""
+    rng, shapes = batched_shapes(count, seed=seed)
+    out = []
+    for (m, n, k) in shapes:
+        A = draw_matrix(rng, (m, k), phi).astype(dtype)
+        B = draw_matrix(rng, (k, n), phi).astype(dtype)
+        out.append((A, B))
+    return shapes, out
