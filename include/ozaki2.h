@@ -1,0 +1,171 @@
+/*
+ * ozaki2.h - C ABI of the MI355X (gfx950) Ozaki-II emulated GEMM library.
+ *
+ * The library computes C ~= A*B for FP64 (DGEMM emulation) or FP32 (SGEMM
+ * emulation) matrices with the accurate-mode Ozaki-II scheme of
+ * Uchino, Ozaki and Imamura, "Error Analysis of Matrix Multiplication
+ * Emulation Using Ozaki-II Scheme" (arXiv 2602.02549):
+ *   Algorithm 2 (Scaling): per-row / per-column power-of-two shifts mu, nu
+ *     chosen from an INT8 product of 6-bit magnitude bounds, then truncation
+ *     A' = trunc(diag(2^mu) A), B' = trunc(B diag(2^nu));
+ *   Algorithm 3 (CRT): INT8 residues A'_l = mod(A', p_l), B'_l = mod(B', p_l)
+ *     for the first N moduli of the fixed list of Section 3.1, N exact
+ *     INT8 x INT8 -> INT32 products C'_l = A'_l B'_l on the matrix cores,
+ *     W_l = mod(C'_l, p_l), and the double-double CRT reduction to C'';
+ *   Algorithm 1: C = diag(2^-mu) C'' diag(2^-nu).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major (BLAS): element (i, j) of an m x n matrix X
+ *     with leading dimension ldx is X[i + (size_t)j * ldx].  C := A*B
+ *     (alpha = 1, beta = 0).
+ *   - Every matrix pointer is a DEVICE pointer on the current HIP device.
+ *     The caller owns A, B and C; A and B are only read, C is only written.
+ *   - Work is enqueued on the stream set with ozaki2_set_stream (default:
+ *     the null stream) and the calls return without waiting for it.
+ *     Argument errors are detected on the host before anything is enqueued.
+ *   - Errors are negative ozaki2_status values.  Data-dependent conditions
+ *     found on the device (non-finite input) are reported by
+ *     ozaki2_sync_status.
+ *   - The library keeps one workspace per device, grown on demand with
+ *     hipMalloc unless the caller installs its own with ozaki2_set_workspace.
+ *     Calls that overlap on one device race on that workspace; the library
+ *     is meant to be driven from one host thread per device.
+ */
+#ifndef OZAKI2_H
+#define OZAKI2_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OZAKI2_OK = 0,
+  OZAKI2_ERR_INVALID_ARG = -1, /* m,n,k < 0; lda < max(1,m); ldb < max(1,k); ldc < max(1,m);
+                                  NULL pointer for a matrix with a nonzero extent            */
+  OZAKI2_ERR_N_RANGE = -2,     /* N outside [2, 49] (FP64) or [2, 16] (FP32)                  */
+  OZAKI2_ERR_K_RANGE = -3,     /* k > 2^17 (the analysis of Sections 3-4 assumes k <= 2^17)   */
+  OZAKI2_ERR_WORKSPACE = -4,   /* caller-installed workspace smaller than required            */
+  OZAKI2_ERR_UNREACHABLE = -5, /* required_moduli: no admissible N meets eps                  */
+  OZAKI2_ERR_NONFINITE = -6,   /* an input entry was Inf or NaN (reported by sync_status)     */
+  OZAKI2_ERR_HIP = -7,         /* a HIP runtime call failed                                   */
+  OZAKI2_ERR_INIT = -8         /* constant tables could not be built                          */
+} ozaki2_status;
+
+/*
+ * ozaki2_gemm - FP64 C := A*B by Algorithm 1 with b = 64 and moduli p_1..p_N.
+ *   m, n, k : sizes; A is m x k, B is k x n, C is m x n (column-major).
+ *   N       : number of moduli, 2 <= N <= 49 (Algorithms 1-3 preconditions).
+ * Accuracy: |AB - C| obeys Theorem 1 (eq. thm:err-1) entrywise.
+ * k == 0 writes C = 0; m == 0 or n == 0 does nothing.
+ * If an input entry is non-finite every entry of C is set to NaN and
+ * ozaki2_sync_status later returns OZAKI2_ERR_NONFINITE.
+ * Returns OZAKI2_OK or an argument / HIP error.
+ */
+int ozaki2_gemm(int m, int n, int k, const double *A, int lda, const double *B, int ldb,
+                double *C, int ldc, int N);
+
+/*
+ * ozaki2_sgemm - FP32 C := A*B by Algorithm 1 with b = 32 (s_l2 = P2 = 0,
+ * C'' rounded to FP32 before the inverse scaling, Algorithm 3 last step).
+ *   N : 2 <= N <= 16, so that single(C'') cannot overflow (|A'B'| < P/2 by
+ *       Lemma 0 and P/2 < 2^128 up to N = 16).
+ * Other arguments and behaviour as ozaki2_gemm.
+ */
+int ozaki2_sgemm(int m, int n, int k, const float *A, int lda, const float *B, int ldb,
+                 float *C, int ldc, int N);
+
+/*
+ * ozaki2_required_moduli - smallest N for which the N-dependent part of the
+ * Theorem 1 bound (eq. thm:err-2 without the N-independent output rounding)
+ * is at most eps times (|A||B|)_ij for every entry (i, j) with a nonzero
+ * (|A||B|)_ij.  Section 5 and the conclusion state that the bound tells how
+ * many moduli a target accuracy needs; this call applies it.
+ *   prec  : 64 (A, B are const double*) or 32 (const float*).
+ *   A, B  : device matrices as in ozaki2_gemm / ozaki2_sgemm.
+ *   eps   : target (> 0).
+ *   N_out : HOST pointer; receives N (or the largest admissible N when the
+ *           target is unreachable, with OZAKI2_ERR_UNREACHABLE returned).
+ * (|A||B|)_ij is replaced by a certified lower bound, which can only raise N.
+ * Synchronises the stream (N is returned to the host).
+ */
+int ozaki2_required_moduli(int prec, int m, int n, int k, const void *A, int lda, const void *B,
+                           int ldb, double eps, int *N_out);
+
+/* Work queue: every later call on this host thread enqueues on `stream`
+ * (a hipStream_t; NULL = the null stream). */
+int ozaki2_set_stream(void *stream);
+
+/* Bytes of device workspace a call with these sizes needs (prec 64 or 32). */
+size_t ozaki2_workspace_bytes(int prec, int m, int n, int k, int N);
+
+/* Install a caller-owned device workspace for the current device (NULL, 0
+ * returns to the library-managed one).  The buffer must stay valid while
+ * calls that use it are in flight. */
+int ozaki2_set_workspace(void *dptr, size_t bytes);
+
+/* Wait for the stream, then return OZAKI2_OK or the first data-dependent
+ * status recorded since the previous ozaki2_sync_status (and clear it). */
+int ozaki2_sync_status(void);
+
+/*
+ * ozaki2_gemm_batched - `count` independent emulated GEMMs in one persistent
+ * launch sequence (configs with many uneven problems).
+ *   prec            : 64 (double) or 32 (float) for every problem.
+ *   mnkN            : HOST array of 4*count ints (m, n, k, N per problem).
+ *   A, B, C         : HOST arrays of `count` device pointers.
+ *   lda, ldb, ldc   : HOST arrays of `count` leading dimensions.
+ * Each problem obeys the rules of ozaki2_gemm / ozaki2_sgemm; any invalid
+ * problem makes the whole call fail before anything is enqueued.
+ */
+int ozaki2_gemm_batched(int prec, int count, const int *mnkN, const void *const *A,
+                        const int *lda, const void *const *B, const int *ldb, void *const *C,
+                        const int *ldc);
+
+/*
+ * ozaki2_debug_stages - run Algorithms 1-3 like ozaki2_gemm / ozaki2_sgemm
+ * and copy the intermediate quantities into caller buffers (device pointers;
+ * any may be NULL to skip it).  For parity checks against the CPU oracle.
+ *   out[0]  int32 [m]          mu'      (Algorithm 2)
+ *   out[1]  int32 [n]          nu'
+ *   out[2]  int32 [m]          row maxima of Cbar = Abar*Bbar
+ *   out[3]  int32 [n]          column maxima of Cbar
+ *   out[4]  int32 [m]          mu
+ *   out[5]  int32 [n]          nu
+ *   out[6]  int8  [N][m][k]    A'_l  (row-major per modulus: k contiguous)
+ *   out[7]  int8  [N][n][k]    B'_l^T (k contiguous per column of B)
+ *   out[8]  int8  [N][n][m]    W_l   (column-major per modulus)
+ *   out[9]  double/float [n][m] C (column-major, ldc = m)
+ *   out[10] float [m+n]        log2f values e (rows) then f (columns)
+ * Returns like ozaki2_gemm.  Synchronises the stream.
+ */
+int ozaki2_debug_stages(int prec, int m, int n, int k, const void *A, int lda, const void *B,
+                        int ldb, int N, void *const *out);
+
+/*
+ * ozaki2_debug_log2f - the library's log2f (Algorithm 2; correctly rounded
+ * to nearest FP32, which meets the accuracy assumption eq. assumption:log2)
+ * applied to `count` FP32 values d[i] >= 1 (device pointers).  For the
+ * exhaustive check over all integer-valued FP32 inputs in [1, 2^29].
+ */
+int ozaki2_debug_log2f(const float *d, float *out, int count);
+
+/*
+ * ozaki2_profile - per-kernel timing with HIP events on the library stream.
+ *   enable != 0 turns recording on (and clears previous records); 0 off.
+ * ozaki2_profile_read copies up to `cap` records (name index, milliseconds)
+ * of the calls made since the last enable; returns the number of records.
+ * ozaki2_profile_name returns the kernel-phase name of an index.
+ */
+int ozaki2_profile(int enable);
+int ozaki2_profile_read(int *phase, float *ms, int cap);
+const char *ozaki2_profile_name(int phase);
+
+/* Library version string. */
+const char *ozaki2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OZAKI2_H */

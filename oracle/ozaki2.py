@@ -304,3 +304,25 @@ def os_ii(A: np.ndarray, B: np.ndarray, N: int, rows=None, cols=None, stages: bo
     C = unscale(st["Cpp"], st["mu"], st["nu"], b)
     st["C"] = C
     return (C, st) if stages else C
+
+
+def log2f_many(d: np.ndarray) -> np.ndarray:
+    """R6 (correctly rounded FP32 log2) for many integer-valued FP32 inputs.
+
+    FP64 log2 is within a few ulp of the real value (relative error far below
+    2^-40); an FP32 result can only be decided wrongly from it when the FP64
+    value lies within 2^-40 (relative) of an FP32 rounding midpoint, and those
+    inputs are settled one by one with log2f()."""
+    d = np.asarray(d, dtype=np.float32)
+    v = np.log2(d.astype(np.float64))
+    r = v.astype(np.float32)                              # nearest FP32 of the FP64 value
+    rd = r.astype(np.float64)
+    up = np.nextafter(r, np.float32(np.inf)).astype(np.float64)
+    dn = np.nextafter(r, np.float32(-np.inf)).astype(np.float64)
+    mid_up, mid_dn = 0.5 * (rd + up), 0.5 * (rd + dn)
+    tol = np.abs(v) * 2.0 ** -40
+    near = (np.abs(v - mid_up) <= tol) | (np.abs(v - mid_dn) <= tol)
+    out = r.copy()
+    for idx in np.nonzero(near)[0]:
+        out[idx] = np.float32(float(log2f(int(d[idx]))))
+    return out

@@ -1,0 +1,99 @@
+// CRT accumulation, final reduction and inverse scaling (Algorithm 3 from the
+// weighted sums on, and the last step of Algorithm 1), fused in one pass over
+// the N INT8 slices W_l:
+//   C'(1) = fl(sum_l s_l1 W_l)      (exact for b = 64, Lemma 2)
+//   C'(2) = fl(sum_l s_l2 W_l)      (fma chain in l order; b = 64 only)
+//   Q     = round(fl(P_inv C'(1)))  (equals round(C'/P), Lemma 3)
+//   C''   = fl(fma(-Q, P2, fma(-Q, P1, C'(1)) + C'(2)))   (b = 64)
+//   C''   = single(fma(-Q, P1, C'(1)))                      (b = 32)
+//   C     = C'' * 2^(-mu_i - nu_j), one rounding.
+// Every operation is an explicit fma / single rounding (built with
+// -ffp-contract=off), so the result is deterministic.
+#include <cstdint>
+
+#include "ozaki2_internal.h"
+
+namespace oz2 {
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_crt(const int8_t* __restrict__ W, size_t sw, int ldw,
+                                             const int* __restrict__ mu, const int* __restrict__ nu,
+                                             int m, int n, int iblocks, CrtConsts cc,
+                                             const int* __restrict__ flag, T* __restrict__ C, int ldc) {
+  const int j = blockIdx.x / iblocks;
+  const int i0 = ((blockIdx.x % iblocks) * 256 + threadIdx.x) * 4;
+  if (i0 >= m) return;
+  const int8_t* wp = W + (size_t)j * ldw + i0;
+  double c1[4] = {0.0, 0.0, 0.0, 0.0}, c2[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int l = 0; l < cc.N; ++l) {
+    const uint32_t w4 = *reinterpret_cast<const uint32_t*>(wp + (size_t)l * sw);
+    const double s1 = cc.s1[l], s2 = cc.s2[l];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double w = (double)(int8_t)(w4 >> (8 * e));
+      c1[e] = fma(s1, w, c1[e]);
+      if (sizeof(T) == 8) c2[e] = fma(s2, w, c2[e]);
+    }
+  }
+  const bool bad = *flag != 0;
+  const int nuj = nu[j];
+  T* cp = C + (size_t)j * ldc;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = i0 + e;
+    if (i >= m) break;
+    const double q = rint(c1[e] * cc.Pinv);
+    const double t = fma(-q, cc.P1, c1[e]);
+    const int ex = -mu[i] - nuj;
+    if (sizeof(T) == 8) {
+      const double cpp = fma(-q, cc.P2, t + c2[e]);
+      cp[i] = bad ? (T)NAN : (T)ldexp(cpp, ex);
+    } else {
+      const float cpp = (float)t;
+      cp[i] = bad ? (T)NAN : (T)ldexp((double)cpp, ex);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_zero(T* __restrict__ C, int ldc, int m, int n,
+                                                   int iblocks) {
+  const int j = blockIdx.x / iblocks;
+  const int i = (blockIdx.x % iblocks) * 256 + threadIdx.x;
+  if (i < m) C[i + (size_t)j * ldc] = (T)0;
+}
+
+__global__ void k_or_status(const int* __restrict__ flag, int* __restrict__ status) {
+  if (threadIdx.x == 0 && *flag) atomicOr(status, 1);
+}
+
+}  // namespace
+
+void launch_or_status(hipStream_t s, const int* flag, int* status) {
+  hipLaunchKernelGGL(k_or_status, dim3(1), dim3(64), 0, s, flag, status);
+}
+
+void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,
+                const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
+                int ldc) {
+  const int iblocks = (m + 1023) / 1024;
+  dim3 grid((unsigned)iblocks * (unsigned)n);
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL(k_crt<double>, grid, dim3(256), 0, s, W, sw, ldw, mu, nu, m, n, iblocks, cc,
+                       flag, (double*)C, ldc);
+  else
+    hipLaunchKernelGGL(k_crt<float>, grid, dim3(256), 0, s, W, sw, ldw, mu, nu, m, n, iblocks, cc,
+                       flag, (float*)C, ldc);
+}
+
+void launch_fill_zero(hipStream_t s, Prec pr, void* C, int ldc, int m, int n) {
+  const int iblocks = (m + 255) / 256;
+  dim3 grid((unsigned)iblocks * (unsigned)n);
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL(k_fill_zero<double>, grid, dim3(256), 0, s, (double*)C, ldc, m, n, iblocks);
+  else
+    hipLaunchKernelGGL(k_fill_zero<float>, grid, dim3(256), 0, s, (float*)C, ldc, m, n, iblocks);
+}
+
+}  // namespace oz2

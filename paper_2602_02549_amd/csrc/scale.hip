@@ -1,0 +1,252 @@
+// Scaling-vector kernels of Algorithm 2 (Section 3.2):
+//   - per-row / per-column maximum of |a| (kept as the IEEE bit pattern of
+//     the FP64 value, whose unsigned order equals the numeric order), from
+//     which mu' = 5 - floor(log2 max|a|) follows exactly;
+//   - the final shifts mu = mu' + floor(fma_down(c, e, P')) with
+//     e = log2f(single_up(max_j Cbar_ij));
+//   - log2f, correctly rounded to FP32 (double-double series evaluation).
+#include <cstdint>
+
+#include "ozaki2_internal.h"
+
+namespace oz2 {
+namespace {
+
+constexpr uint64_t kExpMask = 0x7FF0000000000000ull;
+
+__global__ void k_init(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pad, int* rmax,
+                       int* cmax, int* flag) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int stride = gridDim.x * blockDim.x;
+  for (int i = t; i < m_pad; i += stride) {
+    rowbits[i] = 0;
+    rmax[i] = 0;
+  }
+  for (int j = t; j < n_pad; j += stride) {
+    colbits[j] = 0;
+    cmax[j] = 0;
+  }
+  if (t == 0) *flag = 0;
+}
+
+// A column-major (m x k): one thread per row, a block covers 256 rows and a
+// chunk of 64 columns; consecutive threads read consecutive rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_absmax_rows(const T* __restrict__ A, int lda, int m, int k,
+                                                     uint64_t* __restrict__ rowbits,
+                                                     int* __restrict__ flag) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  int h0 = blockIdx.y * 64, h1 = min(h0 + 64, k);
+  uint64_t mx = 0;
+  for (int h = h0; h < h1; ++h) {
+    double v = fabs((double)A[i + (size_t)h * lda]);
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    mx = b > mx ? b : mx;
+  }
+  if ((mx & kExpMask) == kExpMask) atomicOr(flag, 1);
+  if (mx) atomicMax((unsigned long long*)&rowbits[i], (unsigned long long)mx);
+}
+
+// B column-major (k x n): one block per (column, chunk of 2048 rows).
+template <typename T>
+__global__ __launch_bounds__(256) void k_absmax_cols(const T* __restrict__ B, int ldb, int k, int n,
+                                                     uint64_t* __restrict__ colbits,
+                                                     int* __restrict__ flag) {
+  int j = blockIdx.x;
+  int h0 = blockIdx.y * 2048;
+  const T* col = B + (size_t)j * ldb;
+  uint64_t mx = 0;
+  for (int q = 0; q < 8; ++q) {
+    int h = h0 + threadIdx.x + 256 * q;
+    if (h < k) {
+      uint64_t b = (uint64_t)__double_as_longlong(fabs((double)col[h]));
+      mx = b > mx ? b : mx;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    unsigned long long o = __shfl_xor((unsigned long long)mx, off);
+    mx = o > mx ? o : mx;
+  }
+  __shared__ uint64_t red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t r = red[0];
+    for (int w = 1; w < 4; ++w) r = red[w] > r ? red[w] : r;
+    if ((r & kExpMask) == kExpMask) atomicOr(flag, 1);
+    if (r) atomicMax((unsigned long long*)&colbits[j], (unsigned long long)r);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// double-double helpers (Dekker / Knuth error-free transformations)
+// ---------------------------------------------------------------------------
+struct dd {
+  double h, l;
+};
+__device__ inline dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ inline dd fast_two_sum(double a, double b) {  // |a| >= |b|
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ inline dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.h, b.h);
+  double e = s.l + (a.l + b.l);
+  return fast_two_sum(s.h, e);
+}
+__device__ inline dd dd_mul(dd a, dd b) {
+  double p = a.h * b.h;
+  double e = fma(a.h, b.h, -p);
+  e = fma(a.h, b.l, e);
+  e = fma(a.l, b.h, e);
+  return fast_two_sum(p, e);
+}
+__device__ inline dd dd_recip_int(int q) {  // 1/q as a double-double
+  double h = 1.0 / (double)q;
+  double r = fma(-h, (double)q, 1.0);      // exact remainder
+  return {h, r / (double)q};
+}
+
+// log2 of an integer-valued d in [1, 2^30), rounded to nearest FP32.
+// d = 2^E m with m in (1/sqrt2, sqrt2]; ln m = 2 atanh(z), z = (m-1)/(m+1),
+// |z| <= 0.1716, summed to 23 terms in double-double (error < 2^-100), then
+// multiplied by 1/ln2 (double-double constant).  The FP32 rounding of a
+// double-double h + l is RN(h) unless h is exactly an FP32 midpoint, in which
+// case the sign of l decides.
+__device__ float log2f_rn(float dval) {
+  double d = (double)dval;
+  int E = ilogb(d);
+  double mnt = ldexp(d, -E);
+  if (mnt > 1.4142135623730951) {
+    mnt *= 0.5;
+    E += 1;
+  }
+  double num = mnt - 1.0;   // exact: mnt has at most 31 significant bits
+  double den = mnt + 1.0;   // exact
+  double zh = num / den;
+  double zl = fma(-zh, den, num) / den;
+  dd z = {zh, zl};
+  dd z2 = dd_mul(z, z);
+  dd T = dd_recip_int(2 * 22 + 1);
+  for (int j = 21; j >= 0; --j) T = dd_add(dd_recip_int(2 * j + 1), dd_mul(z2, T));
+  dd ln = dd_mul(z, T);
+  ln.h *= 2.0;
+  ln.l *= 2.0;
+  const dd log2e = {0x1.71547652b82fep+0, 0x1.777d0ffda0d24p-56};
+  dd r = dd_add(dd_mul(ln, log2e), dd{(double)E, 0.0});
+  float y = (float)r.h;
+  float yu = nextafterf(y, INFINITY), yd = nextafterf(y, -INFINITY);
+  double mid_up = 0.5 * ((double)y + (double)yu), mid_dn = 0.5 * ((double)y + (double)yd);
+  if (r.h == mid_up && r.l > 0) return yu;
+  if (r.h == mid_dn && r.l < 0) return yd;
+  return y;
+}
+
+// single_up of a nonnegative integer M <= 2^29 (exact below 2^24).
+__device__ inline float single_up_int(int M) {
+  unsigned u = (unsigned)M;
+  int bl = 32 - __clz(u);
+  if (bl > 24) {
+    int s = bl - 24;
+    u = ((u + (1u << s) - 1u) >> s) << s;
+  }
+  return (float)u;
+}
+
+// floor(c e + P') of the exact value: the product of two FP32 numbers is
+// exact in FP64, and TwoSum gives the sum exactly as s + err; only an integer
+// s with err < 0 needs a correction.
+__device__ inline int floor_fma(float c, float e, float Pp) {
+  double ce = (double)c * (double)e;
+  dd s = two_sum(ce, (double)Pp);
+  double f = floor(s.h);
+  if (f == s.h && s.l < 0) f -= 1.0;
+  return (int)f;
+}
+
+__global__ __launch_bounds__(256) void k_shifts(const uint64_t* __restrict__ rowbits,
+                                                const int* __restrict__ rmax, int m,
+                                                const uint64_t* __restrict__ colbits,
+                                                const int* __restrict__ cmax, int n, float Pprime,
+                                                float c, int* __restrict__ mu_p,
+                                                int* __restrict__ nu_p, int* __restrict__ mu,
+                                                int* __restrict__ nu, float* __restrict__ ef) {
+  int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= m + n) return;
+  bool row = t < m;
+  int idx = row ? t : t - m;
+  uint64_t bits = row ? rowbits[idx] : colbits[idx];
+  int M = row ? rmax[idx] : cmax[idx];
+  int sp = shift_prime_bits(bits);
+  float d = single_up_int(M > 1 ? M : 1);       // R7: a zero maximum is treated as 1
+  float e = log2f_rn(d);
+  int s = sp + floor_fma(c, e, Pprime);
+  if (row) {
+    if (mu_p) mu_p[idx] = sp;
+    mu[idx] = s;
+  } else {
+    if (nu_p) nu_p[idx] = sp;
+    nu[idx] = s;
+  }
+  if (ef) ef[t] = e;
+}
+
+__global__ __launch_bounds__(256) void k_log2f(const float* __restrict__ d, float* __restrict__ out,
+                                               int count) {
+  int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < count) out[t] = log2f_rn(d[t]);
+}
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+void launch_init(hipStream_t s, uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pad,
+                 int* rmax, int* cmax, int* flag) {
+  int mx = m_pad > n_pad ? m_pad : n_pad;
+  int blocks = cdiv(mx, 256);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, rowbits, m_pad, colbits, n_pad, rmax,
+                     cmax, flag);
+}
+
+void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, int k,
+                        uint64_t* rowbits, int* flag) {
+  dim3 grid(cdiv(m, 256), cdiv(k, 64));
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL(k_absmax_rows<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, k,
+                       rowbits, flag);
+  else
+    hipLaunchKernelGGL(k_absmax_rows<float>, grid, dim3(256), 0, s, (const float*)A, lda, m, k,
+                       rowbits, flag);
+}
+
+void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,
+                        uint64_t* colbits, int* flag) {
+  dim3 grid(n, cdiv(k, 2048));
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL(k_absmax_cols<double>, grid, dim3(256), 0, s, (const double*)B, ldb, k, n,
+                       colbits, flag);
+  else
+    hipLaunchKernelGGL(k_absmax_cols<float>, grid, dim3(256), 0, s, (const float*)B, ldb, k, n,
+                       colbits, flag);
+}
+
+void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int m,
+                   const uint64_t* colbits, const int* cmax, int n, float Pprime, float c,
+                   int* mu_p, int* nu_p, int* mu, int* nu, float* ef) {
+  hipLaunchKernelGGL(k_shifts, dim3(cdiv(m + n, 256)), dim3(256), 0, s, rowbits, rmax, m, colbits,
+                     cmax, n, Pprime, c, mu_p, nu_p, mu, nu, ef);
+}
+
+void launch_log2f(hipStream_t s, const float* d, float* out, int count) {
+  hipLaunchKernelGGL(k_log2f, dim3(cdiv(count, 256)), dim3(256), 0, s, d, out, count);
+}
+
+}  // namespace oz2

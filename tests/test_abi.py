@@ -1,0 +1,91 @@
+"""The C-ABI library loads without a GPU, exports every symbol that
+include/ozaki2.h declares, and rejects bad arguments on the host before any
+HIP call (so these run on a GPU-less machine)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2602_02549_amd as oz
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ozaki2.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ozaki2_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ozaki2_gemm", "ozaki2_sgemm", "ozaki2_required_moduli", "ozaki2_set_stream",
+                     "ozaki2_workspace_bytes", "ozaki2_sync_status", "ozaki2_gemm_batched",
+                     "ozaki2_debug_stages"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = oz.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert missing == []
+    out = subprocess.run(["nm", "-D", "--defined-only", oz.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (ozaki2_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_version_and_workspace_query():
+    assert "ozaki2" in oz.ozaki2_version()
+    ws = oz.ozaki2_workspace_bytes(64, 8192, 8192, 8192, 14)
+    # three INT8 slice sets of N x 8192 x 8192 bytes dominate
+    assert ws >= 3 * 14 * 8192 * 8192
+    assert oz.ozaki2_workspace_bytes(64, 10, 10, 10, 1) == 0
+    assert oz.ozaki2_workspace_bytes(16, 10, 10, 10, 5) == 0
+
+
+FAKE = 0x1000  # never dereferenced: every case below fails validation first
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 10), oz.ERR_INVALID_ARG),
+    ((4, 4, 4, FAKE, 3, FAKE, 4, FAKE, 4, 10), oz.ERR_INVALID_ARG),     # lda < m
+    ((4, 4, 4, FAKE, 4, FAKE, 3, FAKE, 4, 10), oz.ERR_INVALID_ARG),     # ldb < k
+    ((4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 3, 10), oz.ERR_INVALID_ARG),     # ldc < m
+    ((4, 4, 4, None, 4, FAKE, 4, FAKE, 4, 10), oz.ERR_INVALID_ARG),     # NULL A
+    ((4, 4, 4, FAKE, 4, FAKE, 4, None, 4, 10), oz.ERR_INVALID_ARG),     # NULL C
+    ((4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1), oz.ERR_N_RANGE),
+    ((4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 50), oz.ERR_N_RANGE),
+    ((4, 4, 2 ** 17 + 1, FAKE, 4, FAKE, 2 ** 17 + 1, FAKE, 4, 10), oz.ERR_K_RANGE),
+    ((0, 4, 4, None, 1, FAKE, 4, None, 1, 10), oz.OK),                   # m = 0: no-op
+    ((4, 0, 4, FAKE, 4, None, 4, None, 4, 10), oz.OK),                   # n = 0: no-op
+])
+def test_gemm_argument_errors(args, code):
+    assert oz.ozaki2_gemm(*args) == code
+
+
+def test_sgemm_N_limit():
+    assert oz.ozaki2_sgemm(4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 17) == oz.ERR_N_RANGE
+    assert oz.ozaki2_sgemm(4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1) == oz.ERR_N_RANGE
+
+
+def test_batched_rejects_bad_problem_before_running():
+    rc = oz.ozaki2_gemm_batched(64, [4, 4, 4, 10, 4, 4, 4, 99], [FAKE, FAKE], [4, 4], [FAKE, FAKE],
+                                [4, 4], [FAKE, FAKE], [4, 4])
+    assert rc == oz.ERR_N_RANGE
+    assert oz.ozaki2_gemm_batched(16, [], [], [], [], [], [], []) == oz.ERR_INVALID_ARG
+
+
+def test_debug_and_log2f_argument_errors():
+    assert oz.ozaki2_debug_log2f(None, None, 0) == oz.OK
+    assert oz.ozaki2_debug_log2f(None, None, 5) == oz.ERR_INVALID_ARG
+    assert oz.ozaki2_debug_stages(64, 4, 4, 4, FAKE, 4, FAKE, 4, 10, [None] * 11) == oz.ERR_INVALID_ARG
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(oz, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(oz, "_lib", None)
+    with pytest.raises(RuntimeError):
+        oz.lib()
