@@ -211,7 +211,7 @@ int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   // Cbar = Abar Bbar; keep row maxima (over j) and column maxima (over i).
   {
     Scope sc(PH_GEMM_SCALE, s);
-    launch_gemm_i8(s, 1, Bs, 0, As, 0, L.np, L.mp, L.kp, 1, cc, nullptr, 0, 0, cmax, rmax);
+    launch_gemm_i8(s, 1, As, 0, Bs, 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax);
   }
   {
     Scope sc(PH_SHIFTS, s);
@@ -228,7 +228,7 @@ int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   }
   {
     Scope sc(PH_GEMM_RES, s);
-    launch_gemm_i8(s, 0, Bs, (size_t)L.np * L.kp, As, (size_t)L.mp * L.kp, L.np, L.mp, L.kp,
+    launch_gemm_i8(s, 0, As, (size_t)L.mp * L.kp, Bs, (size_t)L.np * L.kp, L.mp, L.np, L.kp,
                    cc.N, cc, W, (size_t)L.np * L.mp, L.mp, nullptr, nullptr);
   }
   {

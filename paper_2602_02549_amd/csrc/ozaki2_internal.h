@@ -87,8 +87,8 @@ void launch_slices(hipStream_t s, Prec pr, int mode, bool trans, const void* src
 
 // gemm_i8.hip
 //   D[x][y] = sum_h X[x][h] * Y[y][h] over k_pad, for slices z = 0..nz-1 with
-//   X_z = X + z*sx, Y_z = Y + z*sy.
-//   epi 0: W_z[x][y] = mod(D, p_z) as int8 into W + z*sw, row length ldw.
+//   X_z = X + z*sx, Y_z = Y + z*sy (X: A side, x = i; Y: B side, y = j).
+//   epi 0: W_z[y][x] = mod(D, p_z) as int8 into W + z*sw, row length ldw.
 //   epi 1: xmax[x] = max_y D, ymax[y] = max_x D (atomicMax; D >= 0).
 void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                     int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
