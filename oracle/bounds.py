@@ -123,14 +123,19 @@ def ratio_max(terms: dict, N: int, b: int) -> tuple:
     return r1, r2
 
 
-def required_moduli(A: np.ndarray, B: np.ndarray, eps: float):
-    """Smallest N in [2, 49] whose N-dependent bound is <= eps relative to
-    |A||B| (R16).  Returns (N, reachable, detail dict)."""
-    b = 64 if A.dtype == np.float64 else 32
+def required_moduli_from_terms(terms: dict, eps: float, b: int = 64):
+    """Smallest N in [2, 49] (FP32: [2, 16]) whose N-dependent bound is <= eps
+    relative to |A||B| on every entry (R16).  Returns (N, reachable, detail)."""
     nmax = N_MAX if b == 64 else 16
-    terms = planner_terms(A, B)
+    r1 = r2 = None
     for N in range(N_MIN, nmax + 1):
         r1, r2 = ratio_max(terms, N, b)
         if r1 <= eps:
             return N, True, dict(ratio=r1, est2_ratio=r2)
     return nmax, False, dict(ratio=r1, est2_ratio=r2)
+
+
+def required_moduli(A: np.ndarray, B: np.ndarray, eps: float):
+    """required_moduli_from_terms(planner_terms(A, B), eps, b)."""
+    b = 64 if A.dtype == np.float64 else 32
+    return required_moduli_from_terms(planner_terms(A, B), eps, b)

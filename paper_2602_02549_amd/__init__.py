@@ -213,3 +213,38 @@ def debug_stages(A, B, N: int):
     if rc != OK:
         raise Ozaki2Error("ozaki2_debug_stages", rc)
     return out
+
+
+def gemm_batched_cm(Acm, Bcm, Ccm, shapes, Ns):
+    """One ozaki2_gemm_batched call on column-major device buffers.
+
+    Acm[p], Bcm[p], Ccm[p]: tensors holding A_p (m x k), B_p (k x n), C_p (m x n)
+    in column-major order (as made by col_major); shapes[p] = (m, n, k);
+    Ns[p] = moduli count.  The same buffers on a later call replay the
+    captured launch sequence."""
+    torch = _torch()
+    if not Acm:
+        return
+    prec = 64 if Acm[0].dtype == torch.float64 else 32
+    mnkN, la, lb, lc = [], [], [], []
+    for (m, n, k), N in zip(shapes, Ns):
+        mnkN += [m, n, k, N]
+        la.append(max(m, 1))
+        lb.append(max(k, 1))
+        lc.append(max(m, 1))
+    _set_current_stream()
+    rc = ozaki2_gemm_batched(prec, mnkN, [a.data_ptr() for a in Acm], la,
+                             [b.data_ptr() for b in Bcm], lb, [c.data_ptr() for c in Ccm], lc)
+    if rc != OK:
+        raise Ozaki2Error("ozaki2_gemm_batched", rc)
+
+
+def gemm_batched(As, Bs, Ns):
+    """[A_p @ B_p] for logical A_p (m x k), B_p (k x n) by one batched call."""
+    torch = _torch()
+    shapes = [(A.shape[0], B.shape[1], A.shape[1]) for A, B in zip(As, Bs)]
+    Acm = [col_major(A) for A in As]
+    Bcm = [col_major(B) for B in Bs]
+    Ccm = [torch.empty((n, m), dtype=A.dtype, device=A.device) for (m, n, _), A in zip(shapes, As)]
+    gemm_batched_cm(Acm, Bcm, Ccm, shapes, Ns)
+    return [C.t() for C in Ccm]

@@ -13,8 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libozaki2.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["tables.cpp", "api.cpp", "planner.cpp", "scale.hip", "residue.hip", "gemm_i8.hip",
-           "crt.hip"]
+SOURCES = ["tables.cpp", "api.cpp", "scale.hip", "residue.hip", "gemm_i8.hip", "crt.hip",
+           "plan.hip"]
 
 # -ffp-contract=off: every fused multiply-add in the library is an explicit
 # fma(); the CRT and double-double code rely on single roundings elsewhere.

@@ -5,7 +5,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -19,27 +21,35 @@ namespace {
 
 thread_local hipStream_t g_stream = nullptr;
 
+struct BatchEntry;
+
 struct DeviceState {
   void* ws = nullptr;          // library-owned workspace
   size_t ws_bytes = 0;
   void* user_ws = nullptr;     // caller-installed workspace (takes precedence)
   size_t user_bytes = 0;
+  uint64_t ws_gen = 1;         // bumped whenever the workspace address may change
   int* status = nullptr;       // sticky data-dependent status word
+  CrtConsts* ctab[2] = {nullptr, nullptr};  // device tables of CrtConsts by N (b = 64, 32)
+  hipStream_t capture = nullptr;            // library stream used only for graph capture
+  std::vector<BatchEntry*> batches;         // captured batches, oldest first
 };
 std::mutex g_mu;
 std::map<int, DeviceState> g_dev;
 std::map<int, CrtConsts> g_consts;  // key: N * 100 + b
+PlanCoef g_plan[2];                 // planner coefficients for b = 64, 32
+bool g_plan_ok[2] = {false, false};
 
 // ---------------------------------------------------------------------------
 // profiling (HIP events around each phase on the library stream)
 // ---------------------------------------------------------------------------
 enum Phase {
   PH_INIT, PH_ABSMAX_A, PH_ABSMAX_B, PH_BAR_A, PH_BAR_B, PH_GEMM_SCALE, PH_SHIFTS, PH_RES_A,
-  PH_RES_B, PH_GEMM_RES, PH_CRT, PH_PLAN, PH_COUNT
+  PH_RES_B, PH_GEMM_RES, PH_CRT, PH_PLAN, PH_BATCH, PH_COUNT
 };
 const char* kPhaseNames[PH_COUNT] = {"init", "absmax_A", "absmax_B", "bar_A", "bar_B",
                                      "gemm_scale", "shifts", "residue_A", "residue_B",
-                                     "gemm_residue", "crt", "plan"};
+                                     "gemm_residue", "crt", "plan", "batched"};
 struct ProfRec {
   int phase;
   hipEvent_t a, b;
@@ -139,7 +149,7 @@ int get_consts(int N, int b, CrtConsts* out) {
 }
 
 // Returns a device workspace of at least `bytes` for the current device.
-int get_workspace(size_t bytes, char** base, int** status) {
+int get_workspace(size_t bytes, char** base, int** status, uint64_t* gen = nullptr) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return OZAKI2_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -152,6 +162,7 @@ int get_workspace(size_t bytes, char** base, int** status) {
   if (st.user_ws) {
     if (st.user_bytes < bytes) return OZAKI2_ERR_WORKSPACE;
     *base = (char*)st.user_ws;
+    if (gen) *gen = st.ws_gen;
     return OZAKI2_OK;
   }
   if (st.ws_bytes < bytes) {
@@ -161,10 +172,62 @@ int get_workspace(size_t bytes, char** base, int** status) {
       st.ws = nullptr;
       st.ws_bytes = 0;
     }
+    ++st.ws_gen;
     if (hipMalloc(&st.ws, bytes) != hipSuccess) return OZAKI2_ERR_HIP;
     st.ws_bytes = bytes;
   }
   *base = (char*)st.ws;
+  if (gen) *gen = st.ws_gen;
+  return OZAKI2_OK;
+}
+
+struct PlanLayout {
+  int mp, np, kp;
+  size_t rowbits, colbits, rmax, cmax, flag, res, Abar, Bbar, Abf, Bbf, pr, pc, rs, cs, sr, sc, S,
+      total;
+};
+
+PlanLayout plan_layout(int m, int n, int k) {
+  PlanLayout L;
+  L.mp = (int)rup((size_t)m, kRowPad);
+  L.np = (int)rup((size_t)n, kRowPad);
+  L.kp = (int)rup((size_t)k, kKPad);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = rup(off + bytes, 256);
+    return o;
+  };
+  const size_t tiles = L.kp / 64;
+  L.rowbits = take(8ull * L.mp);
+  L.colbits = take(8ull * L.np);
+  L.rmax = take(4ull * L.mp);
+  L.cmax = take(4ull * L.np);
+  L.flag = take(4);
+  L.res = take(8);
+  L.Abar = take((size_t)L.mp * L.kp);
+  L.Bbar = take((size_t)L.np * L.kp);
+  L.Abf = take(2ull * L.mp * L.kp);
+  L.Bbf = take(2ull * L.np * L.kp);
+  L.pr = take(8ull * tiles * L.mp);
+  L.pc = take(8ull * tiles * L.np);
+  L.rs = take(8ull * L.mp);
+  L.cs = take(8ull * L.np);
+  L.sr = take(8ull * L.mp);
+  L.sc = take(8ull * L.np);
+  L.S = take(4ull * L.mp * L.np);
+  L.total = off;
+  return L;
+}
+
+int get_plan_coef(int b, PlanCoef* out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int i = b == 64 ? 0 : 1;
+  if (!g_plan_ok[i]) {
+    if (!build_plan_coef(b, &g_plan[i])) return OZAKI2_ERR_INIT;
+    g_plan_ok[i] = true;
+  }
+  *out = g_plan[i];
   return OZAKI2_OK;
 }
 
@@ -291,6 +354,344 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
   return hipStreamSynchronize(s) == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
 }
 
+// ---------------------------------------------------------------------------
+// batched execution: every phase of Algorithm 1 is one grouped launch over all
+// problems of the batch (a device table of problem descriptors plus, per
+// phase, a prefix array of workgroup counts).  The launch sequence is captured
+// once per batch signature into a hipGraph and replayed on later calls.
+// ---------------------------------------------------------------------------
+enum BatchSlot {
+  BS_INIT, BS_ABS_A, BS_ABS_B, BS_SL_A, BS_SL_B, BS_GS_BIG, BS_GS_SMALL, BS_SHIFTS, BS_GR_BIG,
+  BS_GR_SMALL, BS_CRT, BS_COUNT
+};
+constexpr int kMaxBatchEntries = 8;
+
+struct BatchEntry {
+  std::vector<int64_t> key;
+  char* table = nullptr;                 // device: descriptors, then BS_COUNT prefix arrays
+  size_t table_bytes = 0;
+  std::vector<int> zero_fill;            // problems with k = 0 (C := 0)
+  int active = 0;                        // problems with m, n, k >= 1
+  int blocks[BS_COUNT] = {};             // grid size per slot
+  int split = 0;                         // problems with >= split 256x256 tiles use them
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int64_t pad8(int64_t v) { return (v + 7) / 8 * 8; }
+
+int env_int(const char* name, int dflt) {
+  const char* e = getenv(name);
+  return e ? atoi(e) : dflt;
+}
+
+// Device table of CrtConsts indexed by N (entries below 2 unused).
+int get_ctab(int b, CrtConsts** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return OZAKI2_ERR_HIP;
+  const int nmax = b == 64 ? kMaxModuli : 16;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    CrtConsts* t = g_dev[dev].ctab[b == 64 ? 0 : 1];
+    if (t) {
+      *out = t;
+      return OZAKI2_OK;
+    }
+  }
+  std::vector<CrtConsts> host(kMaxModuli + 1);
+  memset(host.data(), 0, host.size() * sizeof(CrtConsts));
+  for (int N = 2; N <= nmax; ++N) {
+    int rc = get_consts(N, b, &host[N]);
+    if (rc) return rc;
+  }
+  CrtConsts* t = nullptr;
+  if (hipMalloc(&t, host.size() * sizeof(CrtConsts)) != hipSuccess) return OZAKI2_ERR_HIP;
+  if (hipMemcpy(t, host.data(), host.size() * sizeof(CrtConsts), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return OZAKI2_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  CrtConsts*& slot = g_dev[dev].ctab[b == 64 ? 0 : 1];
+  if (slot) {
+    (void)hipFree(t);   // another thread got there first
+  } else {
+    slot = t;
+  }
+  *out = slot;
+  return OZAKI2_OK;
+}
+
+// Problem descriptors and per-slot prefix arrays for the active problems,
+// with the tile split `split` (problems with at least `split` 256x256 tiles
+// per product use the 256x256 kernel, the rest 128x128; 0 = all 256x256).
+void build_table(const std::vector<ProbDesc>& D, int split, std::vector<char>* out,
+                 int blocks[BS_COUNT]) {
+  const int cnt = (int)D.size();
+  const size_t desc_bytes = rup(sizeof(ProbDesc) * cnt, 256);
+  out->assign(desc_bytes + sizeof(int) * BS_COUNT * (cnt + 1), 0);
+  memcpy(out->data(), D.data(), sizeof(ProbDesc) * cnt);
+  int* pre = reinterpret_cast<int*>(out->data() + desc_bytes);
+  for (int sl = 0; sl < BS_COUNT; ++sl) {
+    int64_t acc = 0;
+    int* P = pre + sl * (cnt + 1);
+    for (int p = 0; p < cnt; ++p) {
+      const ProbDesc& d = D[p];
+      const int64_t t256 = (int64_t)(d.mp / 256) * (d.np / 256);
+      const int64_t t128 = (int64_t)(d.mp / 128) * (d.np / 128);
+      const bool big = t256 >= split;
+      int64_t c = 0;
+      switch (sl) {
+        case BS_INIT: c = cdiv_i(d.mp > d.np ? d.mp : d.np, 256); break;
+        case BS_ABS_A: c = (int64_t)cdiv_i(d.m, 256) * cdiv_i(d.k, 64); break;
+        case BS_ABS_B: c = (int64_t)d.n * cdiv_i(d.k, 2048); break;
+        case BS_SL_A: c = (int64_t)(d.kp / 64) * (d.mp / 64); break;
+        case BS_SL_B: c = (int64_t)(d.kp / 64) * (d.np / 64); break;
+        case BS_GS_BIG: c = big ? pad8(t256) : 0; break;
+        case BS_GS_SMALL: c = big ? 0 : pad8(t128); break;
+        case BS_SHIFTS: c = cdiv_i(d.m + d.n, 256); break;
+        case BS_GR_BIG: c = big ? pad8(t256 * d.N) : 0; break;
+        case BS_GR_SMALL: c = big ? 0 : pad8(t128 * d.N); break;
+        case BS_CRT: c = (int64_t)cdiv_i(d.m, 256 * 16) * d.n; break;
+      }
+      P[p] = (int)acc;
+      acc += c;
+    }
+    P[cnt] = (int)acc;
+    blocks[sl] = (int)acc;
+  }
+}
+
+// Enqueue the grouped launch sequence on `s` (table already on the device).
+void enqueue_batch(Prec pr, const BatchEntry& e, const CrtConsts* ctab, int* status, hipStream_t s,
+                   void* const* C, const int* ldc, const int* mnkN) {
+  const int cnt = e.active;
+  const ProbDesc* D = reinterpret_cast<const ProbDesc*>(e.table);
+  const int* pre = reinterpret_cast<const int*>(e.table + rup(sizeof(ProbDesc) * cnt, 256));
+  auto P = [&](int sl) { return pre + sl * (cnt + 1); };
+  for (int p : e.zero_fill) launch_fill_zero(s, pr, C[p], ldc[p], mnkN[4 * p], mnkN[4 * p + 1]);
+  if (cnt == 0) return;
+  launch_group_scale(s, pr, GP_INIT, D, P(BS_INIT), cnt, e.blocks[BS_INIT], ctab);
+  launch_group_scale(s, pr, GP_ABSMAX_A, D, P(BS_ABS_A), cnt, e.blocks[BS_ABS_A], ctab);
+  launch_group_scale(s, pr, GP_ABSMAX_B, D, P(BS_ABS_B), cnt, e.blocks[BS_ABS_B], ctab);
+  launch_group_slices(s, pr, 0, true, D, P(BS_SL_A), cnt, e.blocks[BS_SL_A], ctab);
+  launch_group_slices(s, pr, 0, false, D, P(BS_SL_B), cnt, e.blocks[BS_SL_B], ctab);
+  launch_group_gemm(s, 1, 256, D, P(BS_GS_BIG), cnt, e.blocks[BS_GS_BIG], ctab);
+  launch_group_gemm(s, 1, 128, D, P(BS_GS_SMALL), cnt, e.blocks[BS_GS_SMALL], ctab);
+  launch_group_scale(s, pr, GP_SHIFTS, D, P(BS_SHIFTS), cnt, e.blocks[BS_SHIFTS], ctab);
+  launch_group_slices(s, pr, 1, true, D, P(BS_SL_A), cnt, e.blocks[BS_SL_A], ctab);
+  launch_group_slices(s, pr, 1, false, D, P(BS_SL_B), cnt, e.blocks[BS_SL_B], ctab);
+  launch_group_gemm(s, 0, 256, D, P(BS_GR_BIG), cnt, e.blocks[BS_GR_BIG], ctab);
+  launch_group_gemm(s, 0, 128, D, P(BS_GR_SMALL), cnt, e.blocks[BS_GR_SMALL], ctab);
+  launch_group_crt(s, pr, D, P(BS_CRT), cnt, e.blocks[BS_CRT], ctab, status);
+}
+
+void free_entry(BatchEntry* e) {
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  if (e->graph) (void)hipGraphDestroy(e->graph);
+  if (e->table) (void)hipFree(e->table);
+  delete e;
+}
+
+// Autotuner: times the residue products (the dominant phase) under each
+// candidate tile split, on this batch's operands, and returns the fastest.
+int tune_split(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* ctab,
+               hipStream_t s, int* best) {
+  const int cand[4] = {1 << 30, 16, 4, 0};
+  float best_ms = 0.f;
+  *best = cand[0];
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return OZAKI2_ERR_HIP;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return OZAKI2_ERR_HIP;
+  }
+  int rc = OZAKI2_OK;
+  std::vector<char> host;
+  for (int c = 0; c < 4 && rc == OZAKI2_OK; ++c) {
+    build_table(D, cand[c], &host, e->blocks);
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(e->table, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = OZAKI2_ERR_HIP;
+      break;
+    }
+    const int cnt = e->active;
+    const ProbDesc* Dd = reinterpret_cast<const ProbDesc*>(e->table);
+    const int* pre = reinterpret_cast<const int*>(e->table + rup(sizeof(ProbDesc) * cnt, 256));
+    float ms = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if (rep == 1) (void)hipEventRecord(a, s);
+      launch_group_gemm(s, 0, 256, Dd, pre + BS_GR_BIG * (cnt + 1), cnt, e->blocks[BS_GR_BIG], ctab);
+      launch_group_gemm(s, 0, 128, Dd, pre + BS_GR_SMALL * (cnt + 1), cnt, e->blocks[BS_GR_SMALL],
+                        ctab);
+    }
+    (void)hipEventRecord(b, s);
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      rc = OZAKI2_ERR_HIP;
+      break;
+    }
+    if (c == 0 || ms < best_ms) {
+      best_ms = ms;
+      *best = cand[c];
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, const int* lda,
+                 const void* const* B, const int* ldb, void* const* C, const int* ldc) {
+  const int b = pr == Prec::F64 ? 64 : 32;
+  for (int p = 0; p < count; ++p) {
+    int rc = check_args(mnkN[4 * p], mnkN[4 * p + 1], mnkN[4 * p + 2], A[p], lda[p], B[p], ldb[p],
+                        C[p], ldc[p], true);
+    if (rc) return rc;
+    if ((rc = check_N(mnkN[4 * p + 3], b))) return rc;
+  }
+  hipStream_t s = g_stream;
+  // workspace: the single-problem layouts of the active problems, back to back
+  std::vector<int> act;
+  std::vector<size_t> off;
+  size_t total = 0;
+  for (int p = 0; p < count; ++p) {
+    const int m = mnkN[4 * p], n = mnkN[4 * p + 1], k = mnkN[4 * p + 2];
+    if (m == 0 || n == 0 || k == 0) continue;
+    act.push_back(p);
+    off.push_back(total);
+    total += rup(layout(m, n, k, mnkN[4 * p + 3]).total, 256);
+  }
+  char* ws = nullptr;
+  int* status = nullptr;
+  uint64_t gen = 0;
+  int rc = get_workspace(total > 0 ? total : 256, &ws, &status, &gen);
+  if (rc) return rc;
+  CrtConsts* ctab = nullptr;
+  if ((rc = get_ctab(b, &ctab))) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return OZAKI2_ERR_HIP;
+
+  const int forced = env_int("OZAKI2_BATCH_SPLIT", -1);
+  const bool use_graph = env_int("OZAKI2_BATCH_GRAPH", 1) != 0;
+  std::vector<int64_t> key;
+  key.reserve(4 + 10 * (size_t)count);
+  key.push_back(b);
+  key.push_back((int64_t)(intptr_t)ws);
+  key.push_back((int64_t)gen);
+  key.push_back(forced);
+  key.push_back(use_graph ? 1 : 0);
+  for (int p = 0; p < count; ++p) {
+    for (int q = 0; q < 4; ++q) key.push_back(mnkN[4 * p + q]);
+    key.push_back(lda[p]);
+    key.push_back(ldb[p]);
+    key.push_back(ldc[p]);
+    key.push_back((int64_t)(intptr_t)A[p]);
+    key.push_back((int64_t)(intptr_t)B[p]);
+    key.push_back((int64_t)(intptr_t)C[p]);
+  }
+
+  BatchEntry* e = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (BatchEntry* x : g_dev[dev].batches)
+      if (x->key == key) e = x;
+  }
+  if (!e) {
+    e = new BatchEntry;
+    e->key = key;
+    e->active = (int)act.size();
+    for (int p = 0; p < count; ++p)
+      if (mnkN[4 * p] > 0 && mnkN[4 * p + 1] > 0 && mnkN[4 * p + 2] == 0) e->zero_fill.push_back(p);
+    std::vector<ProbDesc> D(act.size());
+    for (size_t q = 0; q < act.size(); ++q) {
+      const int p = act[q];
+      const int m = mnkN[4 * p], n = mnkN[4 * p + 1], k = mnkN[4 * p + 2], N = mnkN[4 * p + 3];
+      const Layout L = layout(m, n, k, N);
+      char* w = ws + off[q];
+      ProbDesc& d = D[q];
+      d.m = m, d.n = n, d.k = k, d.N = N;
+      d.mp = L.mp, d.np = L.np, d.kp = L.kp;
+      d.lda = lda[p], d.ldb = ldb[p], d.ldc = ldc[p];
+      d.A = A[p], d.B = B[p], d.C = C[p];
+      d.rowbits = at<uint64_t>(w, L.rowbits);
+      d.colbits = at<uint64_t>(w, L.colbits);
+      d.rmax = at<int>(w, L.rmax);
+      d.cmax = at<int>(w, L.cmax);
+      d.mu = at<int>(w, L.mu);
+      d.nu = at<int>(w, L.nu);
+      d.flag = at<int>(w, L.flag);
+      d.As = at<int8_t>(w, L.A);
+      d.Bs = at<int8_t>(w, L.B);
+      d.W = at<int8_t>(w, L.W);
+    }
+    std::vector<char> host;
+    build_table(D, 0, &host, e->blocks);
+    e->table_bytes = host.size();
+    if (hipMalloc(&e->table, host.size()) != hipSuccess) {
+      free_entry(e);
+      return OZAKI2_ERR_HIP;
+    }
+    e->split = forced >= 0 ? forced : 0;
+    if (forced < 0 && e->active > 0) {
+      if ((rc = tune_split(D, e, ctab, s, &e->split))) {
+        free_entry(e);
+        return rc;
+      }
+    }
+    build_table(D, e->split, &host, e->blocks);
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(e->table, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      free_entry(e);
+      return OZAKI2_ERR_HIP;
+    }
+    if (use_graph) {
+      hipStream_t cs;
+      {
+        std::lock_guard<std::mutex> lk(g_mu);
+        cs = g_dev[dev].capture;
+      }
+      if (!cs) {
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+          free_entry(e);
+          return OZAKI2_ERR_HIP;
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_dev[dev].capture = cs;
+      }
+      bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        enqueue_batch(pr, *e, ctab, status, cs, C, ldc, mnkN);
+        ok = hipStreamEndCapture(cs, &e->graph) == hipSuccess && e->graph;
+      }
+      if (ok) ok = hipGraphInstantiateWithFlags(&e->exec, e->graph, 0) == hipSuccess;
+      if (!ok) {
+        (void)hipGetLastError();
+        free_entry(e);
+        return OZAKI2_ERR_HIP;
+      }
+    }
+    std::vector<BatchEntry*> evict;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      auto& v = g_dev[dev].batches;
+      v.push_back(e);
+      while ((int)v.size() > kMaxBatchEntries) {
+        evict.push_back(v.front());
+        v.erase(v.begin());
+      }
+    }
+    if (!evict.empty()) {
+      if (hipDeviceSynchronize() != hipSuccess) return OZAKI2_ERR_HIP;
+      for (BatchEntry* x : evict) free_entry(x);
+    }
+  }
+  Scope sc(PH_BATCH, s);
+  if (e->exec) {
+    if (hipGraphLaunch(e->exec, s) != hipSuccess) return OZAKI2_ERR_HIP;
+  } else {
+    enqueue_batch(pr, *e, ctab, status, s, C, ldc, mnkN);
+  }
+  return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -322,6 +723,7 @@ int ozaki2_set_workspace(void* dptr, size_t bytes) {
   DeviceState& st = g_dev[dev];
   st.user_ws = dptr;
   st.user_bytes = dptr ? bytes : 0;
+  ++st.ws_gen;
   return OZAKI2_OK;
 }
 
@@ -346,24 +748,108 @@ int ozaki2_gemm_batched(int prec, int count, const int* mnkN, const void* const*
   if ((prec != 64 && prec != 32) || count < 0) return OZAKI2_ERR_INVALID_ARG;
   if (count == 0) return OZAKI2_OK;
   if (!mnkN || !A || !lda || !B || !ldb || !C || !ldc) return OZAKI2_ERR_INVALID_ARG;
-  const int b = prec;
-  for (int p = 0; p < count; ++p) {
-    int rc = check_args(mnkN[4 * p], mnkN[4 * p + 1], mnkN[4 * p + 2], A[p], lda[p], B[p], ldb[p],
-                        C[p], ldc[p], true);
-    if (rc) return rc;
-    if ((rc = check_N(mnkN[4 * p + 3], b))) return rc;
-  }
-  const Prec pr = prec == 64 ? Prec::F64 : Prec::F32;
-  for (int p = 0; p < count; ++p) {
-    int rc = gemm_impl(pr, mnkN[4 * p], mnkN[4 * p + 1], mnkN[4 * p + 2], A[p], lda[p], B[p],
-                       ldb[p], C[p], ldc[p], mnkN[4 * p + 3], nullptr);
-    if (rc) return rc;
-  }
-  return OZAKI2_OK;
+  return batched_impl(prec == 64 ? Prec::F64 : Prec::F32, count, mnkN, A, lda, B, ldb, C, ldc);
 }
 
 int ozaki2_required_moduli(int prec, int m, int n, int k, const void* A, int lda, const void* B,
-                           int ldb, double eps, int* N_out);  // planner.cpp
+                           int ldb, double eps, int* N_out) {
+  if (prec != 64 && prec != 32) return OZAKI2_ERR_INVALID_ARG;
+  if (!N_out || !(eps > 0.0) || !(eps < INFINITY)) return OZAKI2_ERR_INVALID_ARG;
+  int rc = check_args(m, n, k, A, lda, B, ldb, nullptr, 1, false);
+  if (rc) return rc;
+  const int nhi = prec == 64 ? kMaxModuli : 16;
+  if (m == 0 || n == 0 || k == 0) {  // AB = 0 is represented exactly
+    *N_out = 2;
+    return OZAKI2_OK;
+  }
+  const Prec pr = prec == 64 ? Prec::F64 : Prec::F32;
+  PlanCoef pc;
+  if ((rc = get_plan_coef(prec, &pc))) return rc;
+  PlanLayout L = plan_layout(m, n, k);
+  char* ws;
+  int* status;
+  if ((rc = get_workspace(L.total, &ws, &status))) return rc;
+  hipStream_t s = g_stream;
+  uint64_t* rowbits = at<uint64_t>(ws, L.rowbits);
+  uint64_t* colbits = at<uint64_t>(ws, L.colbits);
+  int* rmax = at<int>(ws, L.rmax);
+  int* cmax = at<int>(ws, L.cmax);
+  int* flag = at<int>(ws, L.flag);
+  int* res = at<int>(ws, L.res);
+  CrtConsts cc;
+  std::memset(&cc, 0, sizeof(cc));
+  {
+    Scope sc(PH_PLAN, s);
+    launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
+    if (hipMemsetAsync(res, 0, 2 * sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
+    launch_absmax_rows(s, pr, A, lda, m, k, rowbits, flag);
+    launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag);
+    // Cbar maxima exactly as the emulation computes them (Algorithm 2)
+    launch_slices(s, pr, 0, true, A, lda, m, k, L.mp, L.kp, rowbits, nullptr, cc,
+                  at<int8_t>(ws, L.Abar));
+    launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc,
+                  at<int8_t>(ws, L.Bbar));
+    launch_gemm_i8(s, 1, at<int8_t>(ws, L.Abar), 0, at<int8_t>(ws, L.Bbar), 0, L.mp, L.np, L.kp, 1,
+                   cc, nullptr, 0, 0, rmax, cmax);
+    // scaled |A|, |B| as BF16 lower bounds, with upward row / column sums
+    launch_plan_slices(s, pr, true, A, lda, m, k, L.mp, L.kp, rowbits, at<uint16_t>(ws, L.Abf),
+                       at<double>(ws, L.pr));
+    launch_plan_slices(s, pr, false, B, ldb, n, k, L.np, L.kp, colbits, at<uint16_t>(ws, L.Bbf),
+                       at<double>(ws, L.pc));
+    launch_plan_vectors(s, at<double>(ws, L.pr), L.mp, at<double>(ws, L.pc), L.np, L.kp / 64, rmax,
+                        cmax, m, n, at<double>(ws, L.rs), at<double>(ws, L.cs),
+                        at<double>(ws, L.sr), at<double>(ws, L.sc));
+    launch_gemm_bf16_store(s, at<uint16_t>(ws, L.Abf), at<uint16_t>(ws, L.Bbf), L.mp, L.np, L.kp,
+                           at<float>(ws, L.S), L.mp);
+  }
+  PlanTable pt;
+  std::memset(&pt, 0, sizeof(pt));
+  pt.nlo = 2;
+  pt.nhi = nhi;
+  pt.k = (double)k;
+  pt.eps = eps;
+  // BF16 products of the truncated operands are exact in FP32; each of the k
+  // accumulation steps loses at most 2^-23 relative (all terms >= 0).
+  pt.acc_scale = 1.0 - (double)k * 0x1p-22;
+  for (int N = 2; N <= kMaxModuli; ++N) {
+    pt.t[N] = pc.t[N];
+    pt.tt[N] = pc.tt[N];
+    pt.extra[N] = pc.extra[N];
+  }
+  const float* S = at<float>(ws, L.S);
+  const double *rs = at<double>(ws, L.rs), *cs = at<double>(ws, L.cs);
+  const double *sr = at<double>(ws, L.sr), *scv = at<double>(ws, L.sc);
+  launch_plan_entries(s, S, L.mp, m, n, rs, cs, sr, scv, pt, res);
+  int host[2] = {0, 0};
+  int hflag = 0;
+  if (hipMemcpyAsync(host, res, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return OZAKI2_ERR_HIP;
+  if (hflag) {
+    *N_out = nhi;
+    return OZAKI2_ERR_NONFINITE;
+  }
+  // The smallest N that satisfies every entry: start at the largest
+  // per-entry minimum and check all entries (the bound is not monotone in N
+  // once the N-dependent accumulation term dominates).
+  int N = host[0] < 2 ? 2 : host[0];
+  for (; N <= nhi; ++N) {
+    if (hipMemsetAsync(res + 1, 0, sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
+    launch_plan_verify(s, S, L.mp, m, n, rs, cs, sr, scv, pt, N, res + 1);
+    int bad = 0;
+    if (hipMemcpyAsync(&bad, res + 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return OZAKI2_ERR_HIP;
+    if (!bad) break;
+  }
+  if (N > nhi) {
+    *N_out = nhi;
+    return OZAKI2_ERR_UNREACHABLE;
+  }
+  *N_out = N;
+  return OZAKI2_OK;
+}
 
 int ozaki2_debug_stages(int prec, int m, int n, int k, const void* A, int lda, const void* B,
                         int ldb, int N, void* const* out) {

@@ -16,22 +16,28 @@
 namespace oz2 {
 namespace {
 
+// One thread handles 16 consecutive rows i of one column j: one 16-byte load
+// per modulus, 16 outputs written as a contiguous run.
+constexpr int kCrtRows = 16;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_crt(const int8_t* __restrict__ W, size_t sw, int ldw,
-                                             const int* __restrict__ mu, const int* __restrict__ nu,
-                                             int m, int n, int iblocks, CrtConsts cc,
-                                             const int* __restrict__ flag, T* __restrict__ C, int ldc) {
-  const int j = blockIdx.x / iblocks;
-  const int i0 = ((blockIdx.x % iblocks) * 256 + threadIdx.x) * 4;
+__device__ inline void crt_body(const int8_t* __restrict__ W, size_t sw, int ldw,
+                                const int* __restrict__ mu, const int* __restrict__ nu, int m,
+                                const CrtConsts& cc, const int* __restrict__ flag,
+                                T* __restrict__ C, int ldc, int j, int iblock) {
+  const int i0 = (iblock * 256 + threadIdx.x) * kCrtRows;
   if (i0 >= m) return;
   const int8_t* wp = W + (size_t)j * ldw + i0;
-  double c1[4] = {0.0, 0.0, 0.0, 0.0}, c2[4] = {0.0, 0.0, 0.0, 0.0};
+  double c1[kCrtRows], c2[kCrtRows];
+#pragma unroll
+  for (int e = 0; e < kCrtRows; ++e) c1[e] = c2[e] = 0.0;
   for (int l = 0; l < cc.N; ++l) {
-    const uint32_t w4 = *reinterpret_cast<const uint32_t*>(wp + (size_t)l * sw);
+    const uint4 w16 = *reinterpret_cast<const uint4*>(wp + (size_t)l * sw);
+    const uint32_t wv[4] = {w16.x, w16.y, w16.z, w16.w};
     const double s1 = cc.s1[l], s2 = cc.s2[l];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const double w = (double)(int8_t)(w4 >> (8 * e));
+    for (int e = 0; e < kCrtRows; ++e) {
+      const double w = (double)(int8_t)(wv[e >> 2] >> (8 * (e & 3)));
       c1[e] = fma(s1, w, c1[e]);
       if (sizeof(T) == 8) c2[e] = fma(s2, w, c2[e]);
     }
@@ -40,7 +46,7 @@ __global__ __launch_bounds__(256) void k_crt(const int8_t* __restrict__ W, size_
   const int nuj = nu[j];
   T* cp = C + (size_t)j * ldc;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < kCrtRows; ++e) {
     const int i = i0 + e;
     if (i >= m) break;
     const double q = rint(c1[e] * cc.Pinv);
@@ -54,6 +60,32 @@ __global__ __launch_bounds__(256) void k_crt(const int8_t* __restrict__ W, size_
       cp[i] = bad ? (T)NAN : (T)ldexp((double)cpp, ex);
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_crt(const int8_t* __restrict__ W, size_t sw, int ldw,
+                                             const int* __restrict__ mu, const int* __restrict__ nu,
+                                             int m, int n, int iblocks, CrtConsts cc,
+                                             const int* __restrict__ flag, T* __restrict__ C, int ldc) {
+  crt_body<T>(W, sw, ldw, mu, nu, m, cc, flag, C, ldc, blockIdx.x / iblocks, blockIdx.x % iblocks);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kg_crt(const ProbDesc* __restrict__ P,
+                                              const int* __restrict__ prefix, int count,
+                                              const CrtConsts* __restrict__ ctab) {
+  int lid;
+  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
+  const int iblocks = cdiv_i(d.m, 256 * kCrtRows);
+  crt_body<T>(d.W, (size_t)d.np * d.mp, d.mp, d.mu, d.nu, d.m, ctab[d.N], d.flag, (T*)d.C, d.ldc,
+              lid / iblocks, lid % iblocks);
+}
+
+// Any problem's non-finite flag sets the sticky status word.
+__global__ __launch_bounds__(256) void kg_or_status(const ProbDesc* __restrict__ P, int count,
+                                                    int* __restrict__ status) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < count && *P[p].flag) atomicOr(status, 1);
 }
 
 template <typename T>
@@ -74,10 +106,24 @@ void launch_or_status(hipStream_t s, const int* flag, int* status) {
   hipLaunchKernelGGL(k_or_status, dim3(1), dim3(64), 0, s, flag, status);
 }
 
+void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const int* prefix, int count,
+                      int blocks, const CrtConsts* ctab, int* status) {
+  if (blocks > 0) {
+    if (pr == Prec::F64)
+      hipLaunchKernelGGL(kg_crt<double>, dim3((unsigned)blocks), dim3(256), 0, s, P, prefix, count,
+                         ctab);
+    else
+      hipLaunchKernelGGL(kg_crt<float>, dim3((unsigned)blocks), dim3(256), 0, s, P, prefix, count,
+                         ctab);
+  }
+  hipLaunchKernelGGL(kg_or_status, dim3((unsigned)cdiv_i(count, 256)), dim3(256), 0, s, P, count,
+                     status);
+}
+
 void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,
                 const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
                 int ldc) {
-  const int iblocks = (m + 1023) / 1024;
+  const int iblocks = (m + 256 * kCrtRows - 1) / (256 * kCrtRows);
   dim3 grid((unsigned)iblocks * (unsigned)n);
   if (pr == Prec::F64)
     hipLaunchKernelGGL(k_crt<double>, grid, dim3(256), 0, s, W, sw, ldw, mu, nu, m, n, iblocks, cc,

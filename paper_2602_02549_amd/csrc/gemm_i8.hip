@@ -13,9 +13,9 @@
 //
 // Tiling: a 256-thread workgroup (4 waves as 2 x 2) computes a BX x BY tile;
 // each wave owns (BX/2) x (BY/2) as (BX/64) x (BY/64) blocks of 32 x 32
-// (accumulators live in AGPRs).  K advances 64 bytes per stage through a ring
-// of S LDS stage buffers filled by direct global->LDS copies issued S-1
-// stages ahead, so HBM/L2 latency is covered by the MFMAs of S-1 stages.
+// (accumulators live in AGPRs).  K advances 64 bytes per stage through four
+// LDS stage buffers used as two pairs: direct global->LDS copies fill one pair
+// (both halves of each 128-byte line) while the MFMAs consume the other.
 //
 // Workgroup order: the hardware deals workgroups round-robin to the 8 XCDs;
 // the linear id is remapped so each XCD works on a contiguous range of
@@ -25,6 +25,7 @@
 // Accumulator layout of the 32x32x32 MFMA (lane l, register r):
 //   row (X side) = 8*(r/4) + 4*(l/32) + r%4,   column (Y side) = l%32.
 #include <cstdint>
+#include <cstdlib>
 #include <type_traits>
 
 #include "ozaki2_internal.h"
@@ -34,6 +35,8 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
 
 constexpr int kXcds = 8;
 
@@ -53,11 +56,16 @@ typedef __attribute__((address_space(3))) int8_t lds_i8_t;
 // lane l copies 16 bytes from its address g to LDS byte M0 + 16 l.  Issued as
 // inline asm so the compiler's wait-count insertion does not treat every LDS
 // read as depending on every copy in flight; the kernel waits explicitly.
+// M0 is saved in a scratch SGPR and restored, so no value the compiler keeps
+// in M0 is disturbed.
 __device__ inline void dma16(const void* g, uint32_t lds_addr) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-               :
-               : "v"(g), "s"(lds_addr)
-               : "memory", "m0");
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\t"
+      "global_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "v"(g), "s"(lds_addr)
+      : "memory");
 }
 
 __device__ inline uint32_t lds_addr(const int8_t* p) {
@@ -71,39 +79,51 @@ __device__ inline void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((V & 0xF) | (((V >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-// Main loop structure (BK = 64, S LDS stages filled by global_load_lds):
-// each stage buffer holds the X tile then the Y tile as rows of 64 bytes;
-// the four 16-byte chunks of row r sit at chunk positions c ^ swz(r),
-// swz(r) = (r >> 1) & 3, so the 16-byte fragment reads of 8 consecutive rows
-// hit distinct bank groups.  One wave instruction moves 16 rows (1 KB).
-template <int BX, int BY, int S, int EPI>
-__global__ __launch_bounds__(256, 1) void k_gemm_i8(const int8_t* __restrict__ X, size_t sx,
-                                                    const int8_t* __restrict__ Y, size_t sy,
-                                                    int tiles_x, int tiles_y, int nz, int k_pad,
-                                                    CrtConsts cc, int8_t* __restrict__ W, size_t sw,
-                                                    int ldw, int* __restrict__ xmax,
-                                                    int* __restrict__ ymax) {
-  constexpr int BK = 64;
+// Chunk swizzle of an LDS row (BK bytes of k): chunk c of row r is stored at
+// position c ^ swz(r).  For 64-byte rows (16 banks apart) the 16-byte
+// fragment reads of rows {a, a+4, a+8, a+12} (64 banks, 16 lanes per cycle)
+// and of the same-parity rows of any aligned 8 (32 banks, 8 lanes per cycle)
+// land in distinct bank groups; for 128-byte rows (32 banks apart) rows
+// r..r+15 do (64 banks).
+template <int BK>
+__device__ inline int swz(int r) {
+  return BK == 64 ? (((r >> 1) ^ (r >> 2)) & 3) : ((r >> 1) & 7);
+}
+
+// Main loop structure: k advances in groups of 128 bytes.  BK = 64 keeps a
+// group as two 64-byte stage buffers, BK = 128 as one; either way two groups
+// (128 KB for a 256x256 tile) are resident: the copies of group g+1 (direct
+// global->LDS, every 128-byte line requested as one unit for BK = 128 or as
+// two back-to-back halves for BK = 64) run while the MFMAs consume group g.
+// Each buffer holds the X tile then the Y tile as rows of BK bytes.
+// `bid` is the workgroup's index among the `launched` workgroups of this
+// product (launched >= tiles_x * tiles_y * nz; the surplus exits at once).
+template <int BX, int BY, int BK, int EPI, bool BF16>
+__device__ inline void gemm_body(const int8_t* __restrict__ X, size_t sx,
+                                 const int8_t* __restrict__ Y, size_t sy, int tiles_x,
+                                 int tiles_y, int nz, int k_pad, const CrtConsts& cc,
+                                 int8_t* __restrict__ W, size_t sw, int ldw,
+                                 int* __restrict__ xmax, int* __restrict__ ymax, int bid,
+                                 int launched) {
+  static_assert(BK == 64 || BK == 128, "BK");
   constexpr int WX = BX / 2, WY = BY / 2;
   constexpr int TX = WX / 32, TY = WY / 32;
-  constexpr int IX = BX / 16 / 4, IY = BY / 16 / 4;   // DMA instructions per wave per stage
-  constexpr int LPS = IX + IY;
-  constexpr int STAGE = (BX + BY) * BK;
+  constexpr int CPR = BK / 16;                   // 16-byte chunks per LDS row
+  constexpr int RPI = 1024 / BK;                 // rows per copy instruction
+  constexpr int IX = BX / RPI / 4, IY = BY / RPI / 4;
+  constexpr int STAGE = (BX + BY) * BK;          // one stage buffer
+  constexpr int GROUP_BYTES = (BX + BY) * 128;   // one 128-k group
   constexpr int GROUP = 8;
-  static_assert(S >= 3 && S <= 4, "stages");
-  __shared__ __attribute__((aligned(1024))) int8_t lds0[STAGE];
-  __shared__ __attribute__((aligned(1024))) int8_t lds1[STAGE];
-  __shared__ __attribute__((aligned(1024))) int8_t lds2[STAGE];
-  __shared__ __attribute__((aligned(1024))) int8_t lds3[S == 4 ? STAGE : 16];
+  __shared__ __attribute__((aligned(1024))) int8_t lds[2 * GROUP_BYTES];
 
   // ---- workgroup -> (slice z, tile) ------------------------------------
   const int total = tiles_x * tiles_y * nz;
-  int bid = blockIdx.x;
   {
     const int xcd = bid % kXcds, loc = bid / kXcds;
-    const int per = total / kXcds, extra = total % kXcds;
+    const int per = launched / kXcds, extra = launched % kXcds;
     bid = xcd * per + min(xcd, extra) + loc;
   }
+  if (bid >= total) return;   // whole workgroup, before any barrier
   const int per_slice = tiles_x * tiles_y;
   const int z = bid / per_slice;
   int t = bid % per_slice;
@@ -118,25 +138,36 @@ __global__ __launch_bounds__(256, 1) void k_gemm_i8(const int8_t* __restrict__ X
   const int wx = wave >> 1, wy = wave & 1;
   const int x0 = tx_ * BX, y0 = ty_ * BY;
 
-  // DMA source pointers: instruction q of this wave covers rows 16q..16q+15.
-  const int drow = lane >> 2;
-  const int dchunk = (lane & 3) ^ ((lane >> 3) & 3);
-  const int8_t* xsrc = X + (size_t)z * sx + (size_t)(x0 + wave * IX * 16 + drow) * k_pad + dchunk * 16;
-  const int8_t* ysrc = Y + (size_t)z * sy + (size_t)(y0 + wave * IY * 16 + drow) * k_pad + dchunk * 16;
-  const size_t rowstep = (size_t)16 * k_pad;
-
+  // Copy instruction q of this wave covers rows RPI*q .. RPI*q + RPI - 1 of
+  // its share; lane l takes row RPI*q + l/CPR and stores LDS chunk l%CPR,
+  // which holds k-chunk (l%CPR) ^ swz(row).
+  const int lr = lane / CPR, slot = lane % CPR;
+  const int ch_e = (slot ^ swz<BK>(lr)) * 16, ch_o = (slot ^ swz<BK>(RPI + lr)) * 16;
+  const int8_t* xsrc = X + (size_t)z * sx + (size_t)(x0 + wave * IX * RPI + lr) * k_pad;
+  const int8_t* ysrc = Y + (size_t)z * sy + (size_t)(y0 + wave * IY * RPI + lr) * k_pad;
+  const size_t rowstep = (size_t)RPI * k_pad;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-  auto issue = [&](int8_t* buf, int k0) {
-    const uint32_t base = lds_addr(buf);
+
+  auto issue_group = [&](int8_t* buf, int k0) {
+    const uint32_t b = lds_addr(buf);
 #pragma unroll
-    for (int q = 0; q < IX; ++q)
-      dma16(xsrc + q * rowstep + k0, base + (uint32_t)((wave_u * IX + q) * 1024));
+    for (int q = 0; q < IX; ++q) {
+      const int8_t* src = xsrc + q * rowstep + k0 + ((q & 1) ? ch_o : ch_e);
+      const uint32_t d = b + (uint32_t)((wave_u * IX + q) * 1024);
+      dma16(src, d);
+      if (BK == 64) dma16(src + 64, d + STAGE);
+    }
 #pragma unroll
-    for (int q = 0; q < IY; ++q)
-      dma16(ysrc + q * rowstep + k0, base + (uint32_t)(BX * BK + (wave_u * IY + q) * 1024));
+    for (int q = 0; q < IY; ++q) {
+      const int8_t* src = ysrc + q * rowstep + k0 + ((q & 1) ? ch_o : ch_e);
+      const uint32_t d = b + (uint32_t)(BX * BK + (wave_u * IY + q) * 1024);
+      dma16(src, d);
+      if (BK == 64) dma16(src + 64, d + STAGE);
+    }
   };
 
-  v16i acc[TX][TY];
+  using AccT = typename std::conditional<BF16, v16f, v16i>::type;
+  AccT acc[TX][TY];
 #pragma unroll
   for (int a = 0; a < TX; ++a)
 #pragma unroll
@@ -144,57 +175,82 @@ __global__ __launch_bounds__(256, 1) void k_gemm_i8(const int8_t* __restrict__ X
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
 
-  // fragment addressing: lane reads row frow of a 32-row block, k chunk 2kk + lane/32
+  // fragment offsets of the four 32-k sub-steps j of a group: lane reads row
+  // frow of a 32-row block, k chunk 2j + lane/32 of the group
   const int frow = lane & 31;
-  const int swz = (frow >> 1) & 3;
-  const int fo0 = frow * BK + ((0 + (lane >> 5)) ^ swz) * 16;
-  const int fo1 = frow * BK + ((2 + (lane >> 5)) ^ swz) * 16;
-  auto compute = [&](const int8_t* buf) {
+  int fo[4];
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const int fo = kk ? fo1 : fo0;
-      v4i a[TX], b[TY];
+  for (int j = 0; j < 4; ++j) {
+    const int c = (BK == 64 ? 2 * (j & 1) : 2 * j) + (lane >> 5);
+    fo[j] = (BK == 64 ? (j >> 1) * STAGE : 0) + frow * BK + ((c ^ swz<BK>(frow)) * 16);
+  }
+  auto load_frags = [&](const int8_t* buf, int j, v4i (&a)[TX], v4i (&b)[TY]) {
 #pragma unroll
-      for (int tx = 0; tx < TX; ++tx)
-        a[tx] = *reinterpret_cast<const v4i*>(buf + (wx * WX + tx * 32) * BK + fo);
+    for (int tx = 0; tx < TX; ++tx)
+      a[tx] = *reinterpret_cast<const v4i*>(buf + (wx * WX + tx * 32) * BK + fo[j]);
+#pragma unroll
+    for (int ty = 0; ty < TY; ++ty)
+      b[ty] = *reinterpret_cast<const v4i*>(buf + (BX + wy * WY + ty * 32) * BK + fo[j]);
+  };
+  auto mfmas = [&](const v4i (&a)[TX], const v4i (&b)[TY]) {
+#pragma unroll
+    for (int tx = 0; tx < TX; ++tx)
 #pragma unroll
       for (int ty = 0; ty < TY; ++ty)
-        b[ty] = *reinterpret_cast<const v4i*>(buf + (BX + wy * WY + ty * 32) * BK + fo);
-#pragma unroll
-      for (int tx = 0; tx < TX; ++tx)
-#pragma unroll
-        for (int ty = 0; ty < TY; ++ty)
+        if constexpr (BF16)
+          acc[tx][ty] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              __builtin_bit_cast(v8bf16, a[tx]), __builtin_bit_cast(v8bf16, b[ty]), acc[tx][ty], 0,
+              0, 0);
+        else
           acc[tx][ty] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tx], b[ty], acc[tx][ty], 0, 0, 0);
-    }
   };
-  int8_t* bufs[4] = {lds0, lds1, lds2, lds3};
-
-  const int KT = k_pad / BK;
-#pragma unroll
-  for (int s = 0; s < S - 1; ++s)
-    if (s < KT) issue(bufs[s], s * BK);
-
-  // One step per k stage; the loop is unrolled S times so every buffer is a
-  // static object (the compiler then waits only for the DMA it reads).
-  auto step = [&](auto sc, int kt) {
-    constexpr int s = decltype(sc)::value;
-    if (kt + S - 2 < KT)
-      wait_vmcnt<(S - 2) * LPS>();
-    else
-      wait_vmcnt<0>();
+  // k_pad is a multiple of 128.  Group gi lives in half gi % 2 of the LDS; it
+  // is issued while group gi-1 is consumed and waited for (all copies done +
+  // barrier) before use, which also certifies that every wave has finished
+  // reading group gi-1.  No branch encloses an MFMA, so the accumulators stay
+  // in place across iterations.
+  const int NG = k_pad / 128;
+  issue_group(lds, 0);
+  for (int gi = 0; gi < NG; ++gi) {
+    int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
+    wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
-    if (kt + S - 1 < KT) issue(bufs[(s + S - 1) % S], (kt + S - 1) * BK);
-    compute(bufs[s]);
-  };
-  for (int kt = 0; kt < KT; kt += S) {
-    step(std::integral_constant<int, 0>{}, kt);
-    if (kt + 1 < KT) step(std::integral_constant<int, 1>{}, kt + 1);
-    if (kt + 2 < KT) step(std::integral_constant<int, 2>{}, kt + 2);
-    if (S == 4 && kt + 3 < KT) step(std::integral_constant<int, (S == 4 ? 3 : 0)>{}, kt + 3);
+    v4i a0[TX], b0[TY], a1[TX], b1[TY];
+    // the first fragment reads go out before the next group's copies are
+    // issued, so their LDS latency overlaps the copy issue
+    load_frags(buf, 0, a0, b0);
+    if (gi + 1 < NG) issue_group(lds + ((gi + 1) & 1) * GROUP_BYTES, (gi + 1) * 128);
+    load_frags(buf, 1, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the MFMAs
+    mfmas(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_frags(buf, 2, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_frags(buf, 3, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas(a0, b0);
+    mfmas(a1, b1);
   }
 
   const int xb = x0 + wx * WX, yb = y0 + wy * WY;
-  if (EPI == 0) {
+  if constexpr (EPI == 2) {
+    // FP32 accumulators stored column-major: S[y][x], 4 consecutive x per lane
+    float* S = reinterpret_cast<float*>(W);
+#pragma unroll
+    for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+      for (int ty = 0; ty < TY; ++ty)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const int x = xb + tx * 32 + 8 * r4 + 4 * (lane >> 5);
+          const int y = yb + ty * 32 + (lane & 31);
+          *reinterpret_cast<float4*>(S + (size_t)y * ldw + x) =
+              make_float4((float)acc[tx][ty][4 * r4 + 0], (float)acc[tx][ty][4 * r4 + 1],
+                          (float)acc[tx][ty][4 * r4 + 2], (float)acc[tx][ty][4 * r4 + 3]);
+        }
+  } else if constexpr (EPI == 0) {
     const int p = cc.p[z];
     const double pinv = cc.pinv[z];
     int8_t* Wz = W + (size_t)z * sw;
@@ -212,7 +268,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm_i8(const int8_t* __restrict__ X
                              ((uint32_t)(mod_i32(acc[tx][ty][4 * r4 + 3], p, pinv) & 0xFF) << 24);
           *reinterpret_cast<uint32_t*>(Wz + (size_t)y * ldw + x) = w;
         }
-  } else {
+  } else if constexpr (EPI == 1) {
     // max over x for each y
 #pragma unroll
     for (int ty = 0; ty < TY; ++ty) {
@@ -240,33 +296,124 @@ __global__ __launch_bounds__(256, 1) void k_gemm_i8(const int8_t* __restrict__ X
   }
 }
 
-template <int BX, int BY, int S>
+template <int BX, int BY, int BK, int OCC, int EPI, bool BF16 = false>
+__global__ __launch_bounds__(256, OCC) void k_gemm_i8(const int8_t* __restrict__ X, size_t sx,
+                                                    const int8_t* __restrict__ Y, size_t sy,
+                                                    int tiles_x, int tiles_y, int nz, int k_pad,
+                                                    CrtConsts cc, int8_t* __restrict__ W, size_t sw,
+                                                    int ldw, int* __restrict__ xmax,
+                                                    int* __restrict__ ymax) {
+  gemm_body<BX, BY, BK, EPI, BF16>(X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax,
+                                   ymax, blockIdx.x, gridDim.x);
+}
+
+// Grouped: the scaling product (EPI 1) or the N residue products (EPI 0) of
+// every problem of a batch.
+template <int BX, int BY, int OCC, int EPI>
+__global__ __launch_bounds__(256, OCC) void kg_gemm(const ProbDesc* __restrict__ P,
+                                                    const int* __restrict__ prefix, int count,
+                                                    const CrtConsts* __restrict__ ctab) {
+  int lid;
+  const int p = find_problem(prefix, count, blockIdx.x, &lid);
+  const ProbDesc& d = P[p];
+  const int nz = EPI == 0 ? d.N : 1;
+  gemm_body<BX, BY, 128, EPI, false>(d.As, EPI == 0 ? (size_t)d.mp * d.kp : 0, d.Bs,
+                                     EPI == 0 ? (size_t)d.np * d.kp : 0, d.mp / BX, d.np / BY, nz,
+                                     d.kp, ctab[d.N], d.W, (size_t)d.np * d.mp, d.mp, d.rmax,
+                                     d.cmax, lid, prefix[p + 1] - prefix[p]);
+}
+
+template <int BX, int BY, int BK, int OCC>
 void launch_cfg(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                 int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
                 size_t sw, int ldw, int* xmax, int* ymax) {
   const int tiles_x = nx_pad / BX, tiles_y = ny_pad / BY;
   dim3 grid((unsigned)(tiles_x * tiles_y * nz));
   if (epi == 0)
-    hipLaunchKernelGGL((k_gemm_i8<BX, BY, S, 0>), grid, dim3(256), 0, s, X, sx, Y, sy, tiles_x,
-                       tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+    hipLaunchKernelGGL((k_gemm_i8<BX, BY, BK, OCC, 0>), grid, dim3(256), 0, s, X, sx, Y, sy,
+                       tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
   else
-    hipLaunchKernelGGL((k_gemm_i8<BX, BY, S, 1>), grid, dim3(256), 0, s, X, sx, Y, sy, tiles_x,
-                       tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+    hipLaunchKernelGGL((k_gemm_i8<BX, BY, BK, OCC, 1>), grid, dim3(256), 0, s, X, sx, Y, sy,
+                       tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+}
+
+// Tile configuration: 0 = automatic; 1 = 256x256 (BK 128), 2 = 128x128
+// (BK 128), 3 = 256x256 (BK 64), 4 = 128x128 (BK 64) (environment variable
+// OZAKI2_GEMM_CFG, read once; a tuning aid).
+int forced_cfg() {
+  static int v = [] {
+    const char* e = getenv("OZAKI2_GEMM_CFG");
+    return e ? atoi(e) : 0;
+  }();
+  return v;
 }
 
 }  // namespace
 
+void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const int* prefix,
+                       int count, int blocks, const CrtConsts* ctab) {
+  if (blocks <= 0) return;
+  const dim3 g((unsigned)blocks), b(256);
+  if (tile == 256) {
+    if (epi == 0)
+      hipLaunchKernelGGL((kg_gemm<256, 256, 1, 0>), g, b, 0, s, P, prefix, count, ctab);
+    else
+      hipLaunchKernelGGL((kg_gemm<256, 256, 1, 1>), g, b, 0, s, P, prefix, count, ctab);
+  } else {
+    if (epi == 0)
+      hipLaunchKernelGGL((kg_gemm<128, 128, 2, 0>), g, b, 0, s, P, prefix, count, ctab);
+    else
+      hipLaunchKernelGGL((kg_gemm<128, 128, 2, 1>), g, b, 0, s, P, prefix, count, ctab);
+  }
+}
+
+void launch_gemm_bf16_store(hipStream_t s, const uint16_t* X, const uint16_t* Y, int nx_pad,
+                            int ny_pad, int k_pad, float* S, int lds_) {
+  // BF16 rows are 2*k_pad bytes; the kernel works in bytes of k.
+  const int kb = 2 * k_pad;
+  CrtConsts cc{};
+  const long t256 = (long)(nx_pad / 256) * (ny_pad / 256);
+  if (nx_pad % 256 == 0 && ny_pad % 256 == 0 && t256 >= 512) {
+    const int tiles_x = nx_pad / 256, tiles_y = ny_pad / 256;
+    hipLaunchKernelGGL((k_gemm_i8<256, 256, 128, 1, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
+                       dim3(256), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0, tiles_x, tiles_y,
+                       1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
+  } else {
+    const int tiles_x = nx_pad / 128, tiles_y = ny_pad / 128;
+    hipLaunchKernelGGL((k_gemm_i8<128, 128, 128, 2, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
+                       dim3(256), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0, tiles_x, tiles_y,
+                       1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
+  }
+}
+
 void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                     int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
                     size_t sw, int ldw, int* xmax, int* ymax) {
-  // 256 x 256 tiles when they give at least ~2 workgroups per CU, else 128 x 128.
-  const long big_tiles = (long)(nx_pad / 256) * (ny_pad / 256) * nz;
-  if (nx_pad % 256 == 0 && ny_pad % 256 == 0 && big_tiles >= 512)
-    launch_cfg<256, 256, 4>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw, xmax,
-                             ymax);
-  else
-    launch_cfg<128, 128, 4>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw,
-                              xmax, ymax);
+  // 256x256 tiles (one workgroup per CU, 128 KB of LDS) when they give at
+  // least two waves of workgroups over the 256 CUs; otherwise 128x128 (two
+  // workgroups per CU, 64 KB of LDS each).
+  int cfg = forced_cfg();
+  const long t256 = (long)(nx_pad / 256) * (ny_pad / 256) * nz;
+  const bool fits256 = nx_pad % 256 == 0 && ny_pad % 256 == 0;
+  if (cfg < 1 || cfg > 4) cfg = (fits256 && t256 >= 512) ? 1 : 2;
+  if ((cfg == 1 || cfg == 3) && !fits256) cfg = 2;
+  switch (cfg) {
+    case 1:
+      launch_cfg<256, 256, 128, 1>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw,
+                                   ldw, xmax, ymax);
+      break;
+    case 3:
+      launch_cfg<256, 256, 64, 1>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw,
+                                  xmax, ymax);
+      break;
+    case 4:
+      launch_cfg<128, 128, 64, 2>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw,
+                                  xmax, ymax);
+      break;
+    default:
+      launch_cfg<128, 128, 128, 2>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw,
+                                   ldw, xmax, ymax);
+  }
 }
 
 }  // namespace oz2

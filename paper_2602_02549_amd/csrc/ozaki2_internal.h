@@ -42,6 +42,15 @@ struct PlanCoef {
 };
 bool build_plan_coef(int b, PlanCoef* out);
 
+// Everything the per-entry planner kernels need (passed by value).
+struct PlanTable {
+  int nlo, nhi;        // search range of N
+  double k;            // inner dimension
+  double eps;          // target
+  double acc_scale;    // lower-bound factor for the FP32-accumulated BF16 product
+  double t[kMaxModuli + 1], tt[kMaxModuli + 1], extra[kMaxModuli + 1];
+};
+
 // mu' = 5 - floor(log2 x) (Algorithm 2, eq. mu'nu') from the IEEE bit pattern
 // of x = max_h |a_ih| as an FP64 number; a zero row gets 0 (its outputs are
 // exact zeros).  Exact for subnormals.
@@ -58,6 +67,51 @@ __device__ inline int shift_prime_bits(uint64_t bits) {
   }
   return 5 - fl;
 }
+
+// ---------------------------------------------------------------------------
+// Grouped (batched) execution: one launch per phase covers every problem of a
+// batch.  Each problem has a descriptor; per phase, a prefix array over the
+// problems gives the first workgroup of each problem, and a workgroup finds
+// its problem by binary search.
+struct ProbDesc {
+  int m, n, k, N;
+  int mp, np, kp;           // padded sizes (workspace layout)
+  int lda, ldb, ldc;
+  const void* A;
+  const void* B;
+  void* C;
+  uint64_t* rowbits;
+  uint64_t* colbits;
+  int* rmax;
+  int* cmax;
+  int* mu;
+  int* nu;
+  int* flag;
+  int8_t* As;               // [N][mp][kp]
+  int8_t* Bs;               // [N][np][kp]
+  int8_t* W;                // [N][np][mp]
+};
+
+// Problem index of workgroup `bid` given the phase's prefix array
+// (prefix[0] = 0, prefix[count] = grid size); `lid` receives the local id.
+__device__ inline int find_problem(const int* __restrict__ prefix, int count, int bid, int* lid) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= bid) lo = mid; else hi = mid - 1;
+  }
+  *lid = bid - prefix[lo];
+  return lo;
+}
+
+enum GroupPhase {
+  GP_INIT, GP_ABSMAX_A, GP_ABSMAX_B, GP_SLICE_A, GP_SLICE_B, GP_GEMM_SCALE, GP_SHIFTS,
+  GP_GEMM_RES, GP_CRT, GP_COUNT
+};
+
+// Workgroup counts per phase of one problem (the same decomposition is used
+// by the single-problem launches).
+__host__ __device__ inline int cdiv_i(int a, int b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (each defined next to its kernel)
@@ -85,6 +139,12 @@ void launch_slices(hipStream_t s, Prec pr, int mode, bool trans, const void* src
                    int k, int rows_pad, int k_pad, const uint64_t* bits, const int* shift,
                    const CrtConsts& cc, int8_t* out);
 
+// Planner operands (BF16, K-major [rows_pad][k_pad]) and per-64-k-tile row
+// sums partial[k_pad/64][rows_pad] of |x| 2^-alpha.
+void launch_plan_slices(hipStream_t s, Prec pr, bool trans, const void* src, int ld, int rows,
+                        int k, int rows_pad, int k_pad, const uint64_t* bits, uint16_t* out,
+                        double* partial);
+
 // gemm_i8.hip
 //   D[x][y] = sum_h X[x][h] * Y[y][h] over k_pad, for slices z = 0..nz-1 with
 //   X_z = X + z*sx, Y_z = Y + z*sy (X: A side, x = i; Y: B side, y = j).
@@ -93,6 +153,32 @@ void launch_slices(hipStream_t s, Prec pr, int mode, bool trans, const void* src
 void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                     int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
                     size_t sw, int ldw, int* xmax, int* ymax);
+
+// S[y][x] = sum_h X[x][h] Y[y][h] over BF16 slices (FP32 accumulation on
+// the matrix cores), stored column-major with row length lds_.
+void launch_gemm_bf16_store(hipStream_t s, const uint16_t* X, const uint16_t* Y, int nx_pad,
+                            int ny_pad, int k_pad, float* S, int lds_);
+
+// plan.hip
+void launch_plan_vectors(hipStream_t s, const double* pr, int m_pad, const double* pc, int n_pad,
+                         int tiles, const int* rmax, const int* cmax, int m, int n, double* rs,
+                         double* cs, double* sr, double* sc);
+void launch_plan_entries(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
+                         const double* cs, const double* sr, const double* sc,
+                         const PlanTable& pt, int* out);
+void launch_plan_verify(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
+                        const double* cs, const double* sr, const double* sc, const PlanTable& pt,
+                        int N, int* bad);
+
+// Grouped launches (one per phase for a whole batch); `blocks` = prefix[count].
+void launch_group_scale(hipStream_t s, Prec pr, int phase, const ProbDesc* P, const int* prefix,
+                        int count, int blocks, const CrtConsts* ctab);
+void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, const ProbDesc* P,
+                         const int* prefix, int count, int blocks, const CrtConsts* ctab);
+void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const int* prefix,
+                       int count, int blocks, const CrtConsts* ctab);
+void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const int* prefix, int count,
+                      int blocks, const CrtConsts* ctab, int* status);
 
 // crt.hip: C(i, j) from W_l[j][i] (slices of row length ldw), mu, nu.
 void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,

@@ -1,0 +1,129 @@
+// Required number of moduli from the Theorem 1 bound (eq. thm:err-2).
+//
+// With alpha_i = floor(log2 max_h |a_ih|), beta_j likewise, and the row and
+// column powers of two factored out of every quantity, the N-dependent part of
+// the bound relative to S_ij = (|A||B|)_ij 2^-(alpha_i + beta_j) is
+//   T_ij(N) = t(N) (rs_i sc_j + sr_i cs_j) + (k t(N)^2 + extra(N)) sr_i sc_j,
+// where rs_i = sum_h |a_ih| 2^-alpha_i, cs_j likewise for B, sr_i =
+// sqrt(max_h Cbar_ih) (2^(e'_i/2)), sc_j likewise, t(N) = 1/sqrt(2^5 (P-1)) and
+// extra(N) t^-2 is r_b(N) minus its N-independent output-rounding part.
+// rs, cs, sr, sc are rounded up and S_ij is replaced by a lower bound, so every
+// decision errs towards a larger N.
+#include <cstdint>
+
+#include "ozaki2_internal.h"
+
+namespace oz2 {
+namespace {
+
+// Upward factors: FP64 sums of at most 2^17 nonnegative terms are within
+// 2^-36 (relative) of the exact sum; one correctly rounded sqrt within 2^-53.
+constexpr double kSumUp = 1.0 + 0x1p-30;
+constexpr double kSqrtUp = 1.0 + 0x1p-50;
+constexpr double kTUp = 1.0 + 0x1p-40;   // a few roundings in T itself
+
+__global__ __launch_bounds__(256) void k_plan_vectors(const double* __restrict__ pr, int m_pad,
+                                                      const double* __restrict__ pc, int n_pad,
+                                                      int tiles, const int* __restrict__ rmax,
+                                                      const int* __restrict__ cmax, int m, int n,
+                                                      double* __restrict__ rs, double* __restrict__ cs,
+                                                      double* __restrict__ sr,
+                                                      double* __restrict__ sc) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= m + n) return;
+  const bool row = t < m;
+  const int idx = row ? t : t - m;
+  const double* p = row ? pr + idx : pc + idx;
+  const int stride = row ? m_pad : n_pad;
+  double s = 0.0;
+  for (int q = 0; q < tiles; ++q) s += p[(size_t)q * stride];     // fixed order
+  const double M = (double)(row ? rmax[idx] : cmax[idx]);
+  if (row) {
+    rs[idx] = s * kSumUp;
+    sr[idx] = sqrt(M) * kSqrtUp;
+  } else {
+    cs[idx] = s * kSumUp;
+    sc[idx] = sqrt(M) * kSqrtUp;
+  }
+}
+
+__device__ inline bool plan_ok(const PlanTable& pt, int N, double A1, double P2, double target) {
+  const double T = (pt.t[N] * A1 + (pt.k * pt.tt[N] + pt.extra[N]) * P2) * kTUp;
+  return T <= target;
+}
+
+// Pass 1: for every entry with S > 0, the smallest N in [nlo, nhi] with
+// T(N) <= eps S (nhi + 1 if none); the maximum over all entries goes to *out.
+__global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ S, int lds_,
+                                                      int m, int n, int iblocks,
+                                                      const double* __restrict__ rs,
+                                                      const double* __restrict__ cs,
+                                                      const double* __restrict__ sr,
+                                                      const double* __restrict__ sc, PlanTable pt,
+                                                      int* __restrict__ out) {
+  const int j = blockIdx.x / iblocks;
+  const int i = (blockIdx.x % iblocks) * 256 + threadIdx.x;
+  int need = 0;
+  if (i < m && j < n) {
+    const double Sl = (double)S[(size_t)j * lds_ + i] * pt.acc_scale;
+    if (Sl > 0.0) {
+      const double A1 = rs[i] * sc[j] + sr[i] * cs[j];
+      const double P2 = sr[i] * sc[j];
+      const double target = pt.eps * Sl;
+      int N = pt.nlo;
+      while (N <= pt.nhi && !plan_ok(pt, N, A1, P2, target)) ++N;
+      need = N;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) need = max(need, __shfl_xor(need, off));
+  __shared__ int red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = need;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, max(max(red[0], red[1]), max(red[2], red[3])));
+}
+
+// Pass 2: does N satisfy every entry?  Any failure sets *bad.
+__global__ __launch_bounds__(256) void k_plan_verify(const float* __restrict__ S, int lds_, int m,
+                                                     int n, int iblocks,
+                                                     const double* __restrict__ rs,
+                                                     const double* __restrict__ cs,
+                                                     const double* __restrict__ sr,
+                                                     const double* __restrict__ sc, PlanTable pt,
+                                                     int N, int* __restrict__ bad) {
+  const int j = blockIdx.x / iblocks;
+  const int i = (blockIdx.x % iblocks) * 256 + threadIdx.x;
+  if (i >= m || j >= n) return;
+  const double Sl = (double)S[(size_t)j * lds_ + i] * pt.acc_scale;
+  if (Sl > 0.0) {
+    const double A1 = rs[i] * sc[j] + sr[i] * cs[j];
+    const double P2 = sr[i] * sc[j];
+    if (!plan_ok(pt, N, A1, P2, pt.eps * Sl)) atomicOr(bad, 1);
+  }
+}
+
+}  // namespace
+
+void launch_plan_vectors(hipStream_t s, const double* pr, int m_pad, const double* pc, int n_pad,
+                         int tiles, const int* rmax, const int* cmax, int m, int n, double* rs,
+                         double* cs, double* sr, double* sc) {
+  hipLaunchKernelGGL(k_plan_vectors, dim3((m + n + 255) / 256), dim3(256), 0, s, pr, m_pad, pc,
+                     n_pad, tiles, rmax, cmax, m, n, rs, cs, sr, sc);
+}
+
+void launch_plan_entries(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
+                         const double* cs, const double* sr, const double* sc,
+                         const PlanTable& pt, int* out) {
+  const int iblocks = (m + 255) / 256;
+  hipLaunchKernelGGL(k_plan_entries, dim3((unsigned)iblocks * (unsigned)n), dim3(256), 0, s, S,
+                     lds_, m, n, iblocks, rs, cs, sr, sc, pt, out);
+}
+
+void launch_plan_verify(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
+                        const double* cs, const double* sr, const double* sc, const PlanTable& pt,
+                        int N, int* bad) {
+  const int iblocks = (m + 255) / 256;
+  hipLaunchKernelGGL(k_plan_verify, dim3((unsigned)iblocks * (unsigned)n), dim3(256), 0, s, S,
+                     lds_, m, n, iblocks, rs, cs, sr, sc, pt, N, bad);
+}
+
+}  // namespace oz2

@@ -23,17 +23,19 @@ namespace {
 
 constexpr int kTile = 64;
 
+// The last step starts from |r| < 2^50 (the host picks nsteps so): there the
+// FP64 quotient r * (1/p) is within |r/p| 2^-52 < 1/(4p) of r/p, while r/p is
+// at least 1/(2p) away from a half-integer for odd p, so rint gives round(r/p)
+// and the result already lies in [-(p-1)/2, (p-1)/2].  For p = 256 every step
+// is exact and the result lies in [-128, 128]; the byte store wraps 128 to
+// -128.
 __device__ inline int residue_i8(double v, int p, double pinv, int nsteps) {
   double r = v;
   for (int s = 0; s < nsteps; ++s) {
-    double q = rint(r * pinv);
+    const double q = rint(r * pinv);
     r = fma(-q, (double)p, r);
   }
-  int ri = (int)r;
-  int half = p >> 1;
-  if (ri > half) ri -= p;
-  if (ri < -half) ri += p;
-  return ri;  // p = 256: 128 stays 128 and is wrapped to -128 by the byte store
+  return (int)r;
 }
 
 __device__ inline uint32_t pack4(int a, int b, int c, int d) {
@@ -41,14 +43,15 @@ __device__ inline uint32_t pack4(int a, int b, int c, int d) {
          ((uint32_t)(d & 0xFF) << 24);
 }
 
+// One 64 x 64 tile (k tile kx, row tile ry) of the slices.
 template <typename T, bool TRANS, int MODE>
-__global__ __launch_bounds__(256) void k_slices(const T* __restrict__ src, int ld, int rows, int k,
-                                                int k_pad, size_t slice, const uint64_t* __restrict__ bits,
-                                                const int* __restrict__ shift, CrtConsts cc,
-                                                int8_t* __restrict__ out) {
+__device__ inline void slices_body(const T* __restrict__ src, int ld, int rows, int k, int k_pad,
+                                   size_t slice, const uint64_t* __restrict__ bits,
+                                   const int* __restrict__ shift, const CrtConsts& cc,
+                                   int8_t* __restrict__ out, int kx, int ry) {
   __shared__ double tile[kTile][kTile + 1];
   const int t = threadIdx.x;
-  const int r0 = blockIdx.y * kTile, h0 = blockIdx.x * kTile;
+  const int r0 = ry * kTile, h0 = kx * kTile;
   if (TRANS) {  // src[r + h*ld]: consecutive threads take consecutive rows
     const int r = t & 63, rg = r0 + r;
 #pragma unroll
@@ -107,11 +110,87 @@ __global__ __launch_bounds__(256) void k_slices(const T* __restrict__ src, int l
   }
 }
 
+template <typename T, bool TRANS, int MODE>
+__global__ __launch_bounds__(256) void k_slices(const T* __restrict__ src, int ld, int rows, int k,
+                                                int k_pad, size_t slice, const uint64_t* __restrict__ bits,
+                                                const int* __restrict__ shift, CrtConsts cc,
+                                                int8_t* __restrict__ out) {
+  const int gx = k_pad / kTile;
+  slices_body<T, TRANS, MODE>(src, ld, rows, k, k_pad, slice, bits, shift, cc, out, blockIdx.x % gx,
+                              blockIdx.x / gx);
+}
+
+// Grouped: A side (TRANS, rows = m) or B side (rows = n) of every problem.
+template <typename T, bool ASIDE, int MODE>
+__global__ __launch_bounds__(256) void kg_slices(const ProbDesc* __restrict__ P,
+                                                 const int* __restrict__ prefix, int count,
+                                                 const CrtConsts* __restrict__ ctab) {
+  int lid;
+  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
+  const int gx = d.kp / kTile;
+  if (ASIDE)
+    slices_body<T, true, MODE>((const T*)d.A, d.lda, d.m, d.k, d.kp, (size_t)d.mp * d.kp,
+                               d.rowbits, d.mu, ctab[d.N], d.As, lid % gx, lid / gx);
+  else
+    slices_body<T, false, MODE>((const T*)d.B, d.ldb, d.n, d.k, d.kp, (size_t)d.np * d.kp,
+                                d.colbits, d.nu, ctab[d.N], d.Bs, lid % gx, lid / gx);
+}
+
+// Planner operands: x = |a| 2^-alpha (alpha = floor(log2 max_h |a_ih|), so
+// x < 2) truncated toward zero to BF16 -- every stored value is a lower bound
+// of the exact one -- and, per 64-k tile, the FP64 sum of the exact x of each
+// row (partial[tile][row], reduced in a fixed order).
+template <typename T, bool TRANS>
+__global__ __launch_bounds__(256) void k_plan_slices(const T* __restrict__ src, int ld, int rows,
+                                                     int k, int k_pad, int rows_pad,
+                                                     const uint64_t* __restrict__ bits,
+                                                     uint16_t* __restrict__ out,
+                                                     double* __restrict__ partial) {
+  __shared__ double tile[kTile][kTile + 1];
+  const int t = threadIdx.x;
+  const int r0 = blockIdx.y * kTile, h0 = blockIdx.x * kTile;
+  if (TRANS) {
+    const int r = t & 63, rg = r0 + r;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int h = (t >> 6) + 4 * q, hg = h0 + h;
+      tile[r][h] = (rg < rows && hg < k) ? (double)src[rg + (size_t)hg * ld] : 0.0;
+    }
+  } else {
+    const int h = t & 63, hg = h0 + h;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = (t >> 6) + 4 * q, rg = r0 + r;
+      tile[r][h] = (rg < rows && hg < k) ? (double)src[hg + (size_t)rg * ld] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int r = t >> 2, hc = (t & 3) * 16, rg = r0 + r;
+  const int sh = rg < rows ? shift_prime_bits(bits[rg]) - 5 : 0;   // -alpha
+  uint32_t packed[8];
+  double sum = 0.0;
+#pragma unroll
+  for (int e = 0; e < 16; e += 2) {
+    const double x0 = ldexp(fabs(tile[r][hc + e]), sh), x1 = ldexp(fabs(tile[r][hc + e + 1]), sh);
+    sum += x0;
+    sum += x1;
+    const uint32_t b0 = __float_as_uint(__double2float_rz(x0)) >> 16;
+    const uint32_t b1 = __float_as_uint(__double2float_rz(x1)) >> 16;
+    packed[e >> 1] = b0 | (b1 << 16);
+  }
+  uint4* dst = reinterpret_cast<uint4*>(out + (size_t)rg * k_pad + h0 + hc);
+  dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+  dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+  sum += __shfl_xor(sum, 1);
+  sum += __shfl_xor(sum, 2);
+  if ((t & 3) == 0) partial[(size_t)blockIdx.x * rows_pad + rg] = sum;
+}
+
 template <typename T>
 void launch_t(hipStream_t s, int mode, bool trans, const T* src, int ld, int rows, int k,
               int rows_pad, int k_pad, const uint64_t* bits, const int* shift, const CrtConsts& cc,
               int8_t* out) {
-  dim3 grid(k_pad / kTile, rows_pad / kTile);
+  dim3 grid((unsigned)((k_pad / kTile) * (rows_pad / kTile)));
   size_t slice = (size_t)rows_pad * k_pad;
   if (mode == 0) {
     if (trans)
@@ -130,7 +209,54 @@ void launch_t(hipStream_t s, int mode, bool trans, const T* src, int ld, int row
   }
 }
 
+template <typename T, int MODE>
+void group_slices_t(hipStream_t s, bool aside, const ProbDesc* P, const int* prefix, int count,
+                    int blocks, const CrtConsts* ctab) {
+  const dim3 g((unsigned)blocks), b(256);
+  if (aside)
+    hipLaunchKernelGGL((kg_slices<T, true, MODE>), g, b, 0, s, P, prefix, count, ctab);
+  else
+    hipLaunchKernelGGL((kg_slices<T, false, MODE>), g, b, 0, s, P, prefix, count, ctab);
+}
+
 }  // namespace
+
+void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, const ProbDesc* P,
+                         const int* prefix, int count, int blocks, const CrtConsts* ctab) {
+  if (blocks <= 0) return;
+  if (pr == Prec::F64) {
+    if (mode == 0)
+      group_slices_t<double, 0>(s, aside, P, prefix, count, blocks, ctab);
+    else
+      group_slices_t<double, 1>(s, aside, P, prefix, count, blocks, ctab);
+  } else {
+    if (mode == 0)
+      group_slices_t<float, 0>(s, aside, P, prefix, count, blocks, ctab);
+    else
+      group_slices_t<float, 1>(s, aside, P, prefix, count, blocks, ctab);
+  }
+}
+
+void launch_plan_slices(hipStream_t s, Prec pr, bool trans, const void* src, int ld, int rows,
+                        int k, int rows_pad, int k_pad, const uint64_t* bits, uint16_t* out,
+                        double* partial) {
+  dim3 grid(k_pad / kTile, rows_pad / kTile);
+  if (pr == Prec::F64) {
+    if (trans)
+      hipLaunchKernelGGL((k_plan_slices<double, true>), grid, dim3(256), 0, s, (const double*)src,
+                         ld, rows, k, k_pad, rows_pad, bits, out, partial);
+    else
+      hipLaunchKernelGGL((k_plan_slices<double, false>), grid, dim3(256), 0, s, (const double*)src,
+                         ld, rows, k, k_pad, rows_pad, bits, out, partial);
+  } else {
+    if (trans)
+      hipLaunchKernelGGL((k_plan_slices<float, true>), grid, dim3(256), 0, s, (const float*)src, ld,
+                         rows, k, k_pad, rows_pad, bits, out, partial);
+    else
+      hipLaunchKernelGGL((k_plan_slices<float, false>), grid, dim3(256), 0, s, (const float*)src, ld,
+                         rows, k, k_pad, rows_pad, bits, out, partial);
+  }
+}
 
 void launch_slices(hipStream_t s, Prec pr, int mode, bool trans, const void* src, int ld, int rows,
                    int k, int rows_pad, int k_pad, const uint64_t* bits, const int* shift,

@@ -14,10 +14,8 @@ namespace {
 
 constexpr uint64_t kExpMask = 0x7FF0000000000000ull;
 
-__global__ void k_init(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pad, int* rmax,
-                       int* cmax, int* flag) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int stride = gridDim.x * blockDim.x;
+__device__ inline void init_body(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pad,
+                                 int* rmax, int* cmax, int* flag, int t, int stride) {
   for (int i = t; i < m_pad; i += stride) {
     rowbits[i] = 0;
     rmax[i] = 0;
@@ -29,43 +27,57 @@ __global__ void k_init(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pa
   if (t == 0) *flag = 0;
 }
 
-// A column-major (m x k): one thread per row, a block covers 256 rows and a
-// chunk of 64 columns; consecutive threads read consecutive rows.
+__global__ void k_init(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pad, int* rmax,
+                       int* cmax, int* flag) {
+  init_body(rowbits, m_pad, colbits, n_pad, rmax, cmax, flag, blockIdx.x * blockDim.x + threadIdx.x,
+            gridDim.x * blockDim.x);
+}
+
+// A column-major (m x k): one thread per row, a workgroup covers 256 rows and
+// a chunk of 64 columns (workgroup bx + gx * by); consecutive threads read
+// consecutive rows.
 template <typename T>
-__global__ __launch_bounds__(256) void k_absmax_rows(const T* __restrict__ A, int lda, int m, int k,
-                                                     uint64_t* __restrict__ rowbits,
-                                                     int* __restrict__ flag) {
-  int i = blockIdx.x * 256 + threadIdx.x;
+__device__ inline void absmax_rows_body(const T* __restrict__ A, int lda, int m, int k,
+                                        uint64_t* __restrict__ rowbits, int* __restrict__ flag,
+                                        int bx, int by) {
+  const int i = bx * 256 + threadIdx.x;
   if (i >= m) return;
-  int h0 = blockIdx.y * 64, h1 = min(h0 + 64, k);
+  const int h0 = by * 64, h1 = min(h0 + 64, k);
   uint64_t mx = 0;
   for (int h = h0; h < h1; ++h) {
-    double v = fabs((double)A[i + (size_t)h * lda]);
-    uint64_t b = (uint64_t)__double_as_longlong(v);
+    const double v = fabs((double)A[i + (size_t)h * lda]);
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
     mx = b > mx ? b : mx;
   }
   if ((mx & kExpMask) == kExpMask) atomicOr(flag, 1);
   if (mx) atomicMax((unsigned long long*)&rowbits[i], (unsigned long long)mx);
 }
 
-// B column-major (k x n): one block per (column, chunk of 2048 rows).
 template <typename T>
-__global__ __launch_bounds__(256) void k_absmax_cols(const T* __restrict__ B, int ldb, int k, int n,
-                                                     uint64_t* __restrict__ colbits,
+__global__ __launch_bounds__(256) void k_absmax_rows(const T* __restrict__ A, int lda, int m, int k,
+                                                     uint64_t* __restrict__ rowbits,
                                                      int* __restrict__ flag) {
-  int j = blockIdx.x;
-  int h0 = blockIdx.y * 2048;
+  const int gx = cdiv_i(m, 256);
+  absmax_rows_body<T>(A, lda, m, k, rowbits, flag, blockIdx.x % gx, blockIdx.x / gx);
+}
+
+// B column-major (k x n): one workgroup per (column j, chunk of 2048 rows).
+template <typename T>
+__device__ inline void absmax_cols_body(const T* __restrict__ B, int ldb, int k, int n,
+                                        uint64_t* __restrict__ colbits, int* __restrict__ flag,
+                                        int j, int chunk) {
+  const int h0 = chunk * 2048;
   const T* col = B + (size_t)j * ldb;
   uint64_t mx = 0;
   for (int q = 0; q < 8; ++q) {
-    int h = h0 + threadIdx.x + 256 * q;
+    const int h = h0 + threadIdx.x + 256 * q;
     if (h < k) {
-      uint64_t b = (uint64_t)__double_as_longlong(fabs((double)col[h]));
+      const uint64_t b = (uint64_t)__double_as_longlong(fabs((double)col[h]));
       mx = b > mx ? b : mx;
     }
   }
   for (int off = 32; off >= 1; off >>= 1) {
-    unsigned long long o = __shfl_xor((unsigned long long)mx, off);
+    const unsigned long long o = __shfl_xor((unsigned long long)mx, off);
     mx = o > mx ? o : mx;
   }
   __shared__ uint64_t red[4];
@@ -77,6 +89,13 @@ __global__ __launch_bounds__(256) void k_absmax_cols(const T* __restrict__ B, in
     if ((r & kExpMask) == kExpMask) atomicOr(flag, 1);
     if (r) atomicMax((unsigned long long*)&colbits[j], (unsigned long long)r);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_absmax_cols(const T* __restrict__ B, int ldb, int k, int n,
+                                                     uint64_t* __restrict__ colbits,
+                                                     int* __restrict__ flag) {
+  absmax_cols_body<T>(B, ldb, k, n, colbits, flag, blockIdx.x % n, blockIdx.x / n);
 }
 
 // ---------------------------------------------------------------------------
@@ -169,23 +188,21 @@ __device__ inline int floor_fma(float c, float e, float Pp) {
   return (int)f;
 }
 
-__global__ __launch_bounds__(256) void k_shifts(const uint64_t* __restrict__ rowbits,
-                                                const int* __restrict__ rmax, int m,
-                                                const uint64_t* __restrict__ colbits,
-                                                const int* __restrict__ cmax, int n, float Pprime,
-                                                float c, int* __restrict__ mu_p,
-                                                int* __restrict__ nu_p, int* __restrict__ mu,
-                                                int* __restrict__ nu, float* __restrict__ ef) {
-  int t = blockIdx.x * 256 + threadIdx.x;
+__device__ inline void shifts_body(const uint64_t* __restrict__ rowbits, const int* __restrict__ rmax,
+                                   int m, const uint64_t* __restrict__ colbits,
+                                   const int* __restrict__ cmax, int n, float Pprime, float c,
+                                   int* __restrict__ mu_p, int* __restrict__ nu_p,
+                                   int* __restrict__ mu, int* __restrict__ nu,
+                                   float* __restrict__ ef, int t) {
   if (t >= m + n) return;
-  bool row = t < m;
-  int idx = row ? t : t - m;
-  uint64_t bits = row ? rowbits[idx] : colbits[idx];
-  int M = row ? rmax[idx] : cmax[idx];
-  int sp = shift_prime_bits(bits);
-  float d = single_up_int(M > 1 ? M : 1);       // R7: a zero maximum is treated as 1
-  float e = log2f_rn(d);
-  int s = sp + floor_fma(c, e, Pprime);
+  const bool row = t < m;
+  const int idx = row ? t : t - m;
+  const uint64_t bits = row ? rowbits[idx] : colbits[idx];
+  const int M = row ? rmax[idx] : cmax[idx];
+  const int sp = shift_prime_bits(bits);
+  const float d = single_up_int(M > 1 ? M : 1);       // R7: a zero maximum is treated as 1
+  const float e = log2f_rn(d);
+  const int s = sp + floor_fma(c, e, Pprime);
   if (row) {
     if (mu_p) mu_p[idx] = sp;
     mu[idx] = s;
@@ -194,6 +211,55 @@ __global__ __launch_bounds__(256) void k_shifts(const uint64_t* __restrict__ row
     nu[idx] = s;
   }
   if (ef) ef[t] = e;
+}
+
+__global__ __launch_bounds__(256) void k_shifts(const uint64_t* __restrict__ rowbits,
+                                                const int* __restrict__ rmax, int m,
+                                                const uint64_t* __restrict__ colbits,
+                                                const int* __restrict__ cmax, int n, float Pprime,
+                                                float c, int* __restrict__ mu_p,
+                                                int* __restrict__ nu_p, int* __restrict__ mu,
+                                                int* __restrict__ nu, float* __restrict__ ef) {
+  shifts_body(rowbits, rmax, m, colbits, cmax, n, Pprime, c, mu_p, nu_p, mu, nu, ef,
+              blockIdx.x * 256 + threadIdx.x);
+}
+
+// ---- grouped versions ------------------------------------------------------
+__global__ __launch_bounds__(256) void kg_init(const ProbDesc* __restrict__ P,
+                                               const int* __restrict__ prefix, int count) {
+  int lid;
+  const int p = find_problem(prefix, count, blockIdx.x, &lid);
+  const ProbDesc& d = P[p];
+  const int blocks = prefix[p + 1] - prefix[p];
+  init_body(d.rowbits, d.mp, d.colbits, d.np, d.rmax, d.cmax, d.flag, lid * 256 + threadIdx.x,
+            blocks * 256);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kg_absmax_rows(const ProbDesc* __restrict__ P,
+                                                      const int* __restrict__ prefix, int count) {
+  int lid;
+  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
+  const int gx = cdiv_i(d.m, 256);
+  absmax_rows_body<T>((const T*)d.A, d.lda, d.m, d.k, d.rowbits, d.flag, lid % gx, lid / gx);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kg_absmax_cols(const ProbDesc* __restrict__ P,
+                                                      const int* __restrict__ prefix, int count) {
+  int lid;
+  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
+  absmax_cols_body<T>((const T*)d.B, d.ldb, d.k, d.n, d.colbits, d.flag, lid % d.n, lid / d.n);
+}
+
+__global__ __launch_bounds__(256) void kg_shifts(const ProbDesc* __restrict__ P,
+                                                 const int* __restrict__ prefix, int count,
+                                                 const CrtConsts* __restrict__ ctab) {
+  int lid;
+  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
+  const CrtConsts& cc = ctab[d.N];
+  shifts_body(d.rowbits, d.rmax, d.m, d.colbits, d.cmax, d.n, cc.Pprime, cc.c, nullptr, nullptr,
+              d.mu, d.nu, nullptr, lid * 256 + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_log2f(const float* __restrict__ d, float* __restrict__ out,
@@ -218,7 +284,7 @@ void launch_init(hipStream_t s, uint64_t* rowbits, int m_pad, uint64_t* colbits,
 
 void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, int k,
                         uint64_t* rowbits, int* flag) {
-  dim3 grid(cdiv(m, 256), cdiv(k, 64));
+  dim3 grid((unsigned)(cdiv(m, 256) * cdiv(k, 64)));
   if (pr == Prec::F64)
     hipLaunchKernelGGL(k_absmax_rows<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, k,
                        rowbits, flag);
@@ -229,7 +295,7 @@ void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, i
 
 void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,
                         uint64_t* colbits, int* flag) {
-  dim3 grid(n, cdiv(k, 2048));
+  dim3 grid((unsigned)n * (unsigned)cdiv(k, 2048));
   if (pr == Prec::F64)
     hipLaunchKernelGGL(k_absmax_cols<double>, grid, dim3(256), 0, s, (const double*)B, ldb, k, n,
                        colbits, flag);
@@ -247,6 +313,34 @@ void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int 
 
 void launch_log2f(hipStream_t s, const float* d, float* out, int count) {
   hipLaunchKernelGGL(k_log2f, dim3(cdiv(count, 256)), dim3(256), 0, s, d, out, count);
+}
+
+void launch_group_scale(hipStream_t s, Prec pr, int phase, const ProbDesc* P, const int* prefix,
+                        int count, int blocks, const CrtConsts* ctab) {
+  if (blocks <= 0) return;
+  const dim3 g((unsigned)blocks), b(256);
+  switch (phase) {
+    case GP_INIT:
+      hipLaunchKernelGGL(kg_init, g, b, 0, s, P, prefix, count);
+      break;
+    case GP_ABSMAX_A:
+      if (pr == Prec::F64)
+        hipLaunchKernelGGL(kg_absmax_rows<double>, g, b, 0, s, P, prefix, count);
+      else
+        hipLaunchKernelGGL(kg_absmax_rows<float>, g, b, 0, s, P, prefix, count);
+      break;
+    case GP_ABSMAX_B:
+      if (pr == Prec::F64)
+        hipLaunchKernelGGL(kg_absmax_cols<double>, g, b, 0, s, P, prefix, count);
+      else
+        hipLaunchKernelGGL(kg_absmax_cols<float>, g, b, 0, s, P, prefix, count);
+      break;
+    case GP_SHIFTS:
+      hipLaunchKernelGGL(kg_shifts, g, b, 0, s, P, prefix, count, ctab);
+      break;
+    default:
+      break;
+  }
 }
 
 }  // namespace oz2

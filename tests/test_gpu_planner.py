@@ -1,0 +1,86 @@
+"""GPU planner (ozaki2_required_moduli) against the oracle's reading of the
+Theorem 1 bound.  The library replaces (|A||B|)_ij by a certified lower bound
+(BF16 operands truncated toward zero: at most 2^-6 low; FP32 accumulation of
+nonnegative terms: at most k 2^-22 low), so its N lies between the oracle's N
+for eps and for eps (1 - slack)."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, dev
+from oracle.bounds import planner_terms, required_moduli_from_terms
+from workload import gemm_inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_2602_02549_amd as oz  # noqa: E402
+
+
+def slack(k):
+    return 2.0 ** -6 + k * 2.0 ** -22 + 1e-9
+
+
+def effective(rc_or_ok, N, nmax):
+    """N, or nmax + 1 when the target is unreachable."""
+    ok = rc_or_ok is True or rc_or_ok == oz.OK
+    return N if ok else nmax + 1
+
+
+def check_between(rc, Ng, lo, hi, nmax):
+    g = effective(rc, Ng, nmax)
+    a = effective(lo[1], lo[0], nmax)
+    b = effective(hi[1], hi[0], nmax)
+    assert rc in (oz.OK, oz.ERR_UNREACHABLE)
+    assert a <= g <= b, (a, g, b)
+
+
+@pytest.mark.parametrize("m,n,k,phi,eps", [
+    (300, 200, 500, 0.5, 1e-15),
+    (300, 200, 500, 4.0, 1e-15),
+    (257, 129, 1000, 1.0, 1e-12),
+    (64, 700, 256, 2.0, 1e-9),
+    (40, 30, 50, 0.0, 1e-15),
+])
+def test_required_moduli_fp64(m, n, k, phi, eps):
+    announce(f"planner fp64 m={m} n={n} k={k} phi={phi} eps={eps}")
+    A, B = gemm_inputs(m, n, k, phi=phi, seed=m + k)
+    rc, Ng = oz.required_moduli(dev(A), dev(B), eps)
+    terms = planner_terms(A, B)
+    lo = required_moduli_from_terms(terms, eps * (1 + 1e-9))
+    hi = required_moduli_from_terms(terms, eps * (1 - slack(k)))
+    check_between(rc, Ng, lo, hi, 49)
+
+
+def test_required_moduli_fp32():
+    announce("planner fp32")
+    A, B = gemm_inputs(200, 150, 300, phi=1.0, seed=5, dtype=np.float32)
+    rc, Ng = oz.required_moduli(dev(A), dev(B), 1e-6)
+    terms = planner_terms(A, B)
+    lo = required_moduli_from_terms(terms, 1e-6 * (1 + 1e-9), 32)
+    hi = required_moduli_from_terms(terms, 1e-6 * (1 - slack(300)), 32)
+    check_between(rc, Ng, lo, hi, 16)
+
+
+def test_required_moduli_unreachable_and_errors():
+    announce("planner unreachable / errors")
+    A, B = gemm_inputs(50, 40, 60, seed=2)
+    rc, Ng = oz.required_moduli(dev(A), dev(B), 1e-40)
+    assert rc == oz.ERR_UNREACHABLE and Ng == 49
+    A[3, 3] = np.inf
+    rc, _ = oz.required_moduli(dev(A), dev(B), 1e-15)
+    assert rc == oz.ERR_NONFINITE
+    rc, _ = oz.required_moduli(dev(A), dev(B), -1.0)
+    assert rc == oz.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("phi", [0.0, 1.0, 2.0, 4.0])
+def test_required_moduli_4096(phi):
+    # The wide-exponent workload (4096^3, phi in {0,1,2,4}) at eps = 1e-15;
+    # the oracle's bound ingredients come from FP64 BLAS on the host.
+    announce(f"planner 4096^3 phi={phi}")
+    A, B = gemm_inputs(4096, 4096, 4096, phi=phi, seed=0)
+    rc, Ng = oz.required_moduli(dev(A), dev(B), 1e-15)
+    terms = planner_terms(A, B)
+    lo = required_moduli_from_terms(terms, 1e-15 * (1 + 1e-9))
+    hi = required_moduli_from_terms(terms, 1e-15 * (1 - slack(4096)))
+    print(f"[planner] phi={phi}: oracle {lo[:2]} .. {hi[:2]}, GPU rc={rc} N={Ng}", flush=True)
+    check_between(rc, Ng, lo, hi, 49)
