@@ -41,7 +41,92 @@ def parse():
     ap.add_argument("--samples", type=int, default=48, help="sampled rows (and columns) for errors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-size", type=int, default=320)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the uneven 512-problem batched measurement")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run one device copy of MIB MiB first (HBM counter calibration)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_i8_residue_fp64_8192_N14_traffic.txt")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2602_02549_amd", "csrc", "gemm_i8.hip")
+
+
+def measured_traffic(N: int, m: int):
+    """HBM bytes per residue-product launch from the committed counter summary,
+    or None if it does not cover this configuration or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                key, val = line.split(":", 1)
+                fields[key.strip()] = val.strip()
+    with open(GEMM_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("source_sha256") != sha or fields.get("N") != str(N) or fields.get("size") != str(m):
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def batched_measurement(torch, oz, steps: int) -> dict:
+    """The uneven batch: 512 FP64 problems, m, n, k log-uniform in [64, 2048],
+    phi = 1, N per problem from the planner at 1e-15; the batched call (one
+    captured graph) against looped native DGEMM, inputs resident in HBM."""
+    from workload import batched_inputs
+
+    dev = torch.device("cuda:0")
+    shapes, mats = batched_inputs(512, phi=1.0, seed=0)
+    Acm = [torch.from_numpy(np.ascontiguousarray(A.T)).to(dev) for A, _ in mats]
+    Bcm = [torch.from_numpy(np.ascontiguousarray(B.T)).to(dev) for _, B in mats]
+    del mats
+    Ccm = [torch.empty((n, m), dtype=torch.float64, device=dev) for m, n, _ in shapes]
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    Ns, unreachable = [], 0
+    for (m, n, k), a, b in zip(shapes, Acm, Bcm):
+        rc, N = oz.ozaki2_required_moduli(64, m, n, k, a.data_ptr(), m, b.data_ptr(), k, 1e-15)
+        if rc not in (oz.OK, oz.ERR_UNREACHABLE):
+            raise oz.Ozaki2Error("ozaki2_required_moduli", rc)
+        unreachable += rc == oz.ERR_UNREACHABLE
+        Ns.append(N)
+    flops = sum(2.0 * m * n * k for m, n, k in shapes)
+    At = [a.t() for a in Acm]
+    Bt = [b.t() for b in Bcm]
+    Cn = [torch.empty((m, n), dtype=torch.float64, device=dev) for m, n, _ in shapes]
+
+    def emulated():
+        oz.gemm_batched_cm(Acm, Bcm, Ccm, shapes, Ns)
+
+    def native():
+        for q in range(len(shapes)):
+            torch.matmul(At[q], Bt[q], out=Cn[q])
+
+    res = {}
+    for name, f in (("emulated", emulated), ("native", native)):
+        f()                      # first call: graph capture and tile tuning
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"ms": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 3)}
+    if oz.ozaki2_sync_status() != oz.OK:
+        raise RuntimeError("data-dependent status set in the batched run")
+    return {"workload": "512 FP64 problems, m,n,k log-uniform in [64,2048], phi=1, seed 0, "
+                        "N per problem from the bound at 1e-15",
+            "N_min": min(Ns), "N_max": max(Ns), "N_mean": round(float(np.mean(Ns)), 2),
+            "unreachable": unreachable, "flops": flops, **res,
+            "speedup_vs_native": round(res["native"]["ms"] / res["emulated"]["ms"], 3)}
 
 
 def cpu_baseline(size: int, N: int) -> dict:
@@ -135,6 +220,16 @@ def main():
     if oz.ozaki2_sync_status() != oz.OK:
         raise RuntimeError("data-dependent status set")
 
+    if args.calibrate_copy:
+        # A plain device copy of known size: the HBM counters of this dispatch
+        # calibrate those of the GEMM (read FETCH_SIZE / WRITE_SIZE per dispatch).
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---- timed region -----------------------------------------------------
     for _ in range(args.warmup):
         emulate(N)
@@ -176,15 +271,20 @@ def main():
                    "m": m, "n": n, "k": k, "N": N, "phi": 0.5,
                    "matched_error": "smallest N in 12..20 with sampled max|C-AB|/(|A||B|) <= native"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_INT8_TOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_INT8_TOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_INT8_TOPS, 4),
+                     "traffic": measured_traffic(N, m),
                      "kernel": "k_gemm_i8 (residue products, epilogue mod p)",
-                     "ops_per_launch": N * flops},
+                     "kernel_ms": round(gemm_ms, 4), "ops_per_launch": N * flops},
         "native_fp64": {"ms": round(native_ms, 4), "tflops": round(flops / (native_ms * 1e-3) / 1e12, 3),
                         "rel_err_sampled": native_err},
         "emulated_rel_err_sampled": {str(kk): v for kk, v in sweep.items()},
         "speedup_vs_native": round(native_ms / ms, 3),
         "phases_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
     }
+    del Acm, Bcm, Ccm, dA, dB
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_measurement(torch, oz, max(1, min(args.steps, 10)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_size, N)
     print(json.dumps(out), flush=True)

@@ -368,11 +368,12 @@ constexpr int kMaxBatchEntries = 8;
 
 struct BatchEntry {
   std::vector<int64_t> key;
-  char* table = nullptr;                 // device: descriptors, then BS_COUNT prefix arrays
-  size_t table_bytes = 0;
+  char* table = nullptr;                 // device: descriptors, then one block map per slot
+  size_t table_bytes = 0;                // allocated size
   std::vector<int> zero_fill;            // problems with k = 0 (C := 0)
   int active = 0;                        // problems with m, n, k >= 1
   int blocks[BS_COUNT] = {};             // grid size per slot
+  size_t map_off[BS_COUNT] = {};         // byte offset of each slot's block map
   int split = 0;                         // problems with >= split 256x256 tiles use them
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -420,68 +421,91 @@ int get_ctab(int b, CrtConsts** out) {
   return OZAKI2_OK;
 }
 
-// Problem descriptors and per-slot prefix arrays for the active problems,
-// with the tile split `split` (problems with at least `split` 256x256 tiles
-// per product use the 256x256 kernel, the rest 128x128; 0 = all 256x256).
+// Problem descriptors and per-slot block maps for the active problems, with
+// the tile split `split` (problems with at least `split` 256x256 tiles per
+// product use the 256x256 kernel, the rest 128x128; 0 = all 256x256).
 void build_table(const std::vector<ProbDesc>& D, int split, std::vector<char>* out,
-                 int blocks[BS_COUNT]) {
+                 int blocks[BS_COUNT], size_t map_off[BS_COUNT]) {
   const int cnt = (int)D.size();
-  const size_t desc_bytes = rup(sizeof(ProbDesc) * cnt, 256);
-  out->assign(desc_bytes + sizeof(int) * BS_COUNT * (cnt + 1), 0);
-  memcpy(out->data(), D.data(), sizeof(ProbDesc) * cnt);
-  int* pre = reinterpret_cast<int*>(out->data() + desc_bytes);
-  for (int sl = 0; sl < BS_COUNT; ++sl) {
-    int64_t acc = 0;
-    int* P = pre + sl * (cnt + 1);
-    for (int p = 0; p < cnt; ++p) {
-      const ProbDesc& d = D[p];
-      const int64_t t256 = (int64_t)(d.mp / 256) * (d.np / 256);
-      const int64_t t128 = (int64_t)(d.mp / 128) * (d.np / 128);
-      const bool big = t256 >= split;
-      int64_t c = 0;
-      switch (sl) {
-        case BS_INIT: c = cdiv_i(d.mp > d.np ? d.mp : d.np, 256); break;
-        case BS_ABS_A: c = (int64_t)cdiv_i(d.m, 256) * cdiv_i(d.k, 64); break;
-        case BS_ABS_B: c = (int64_t)d.n * cdiv_i(d.k, 2048); break;
-        case BS_SL_A: c = (int64_t)(d.kp / 64) * (d.mp / 64); break;
-        case BS_SL_B: c = (int64_t)(d.kp / 64) * (d.np / 64); break;
-        case BS_GS_BIG: c = big ? pad8(t256) : 0; break;
-        case BS_GS_SMALL: c = big ? 0 : pad8(t128); break;
-        case BS_SHIFTS: c = cdiv_i(d.m + d.n, 256); break;
-        case BS_GR_BIG: c = big ? pad8(t256 * d.N) : 0; break;
-        case BS_GR_SMALL: c = big ? 0 : pad8(t128 * d.N); break;
-        case BS_CRT: c = (int64_t)cdiv_i(d.m, 256 * 16) * d.n; break;
-      }
-      P[p] = (int)acc;
-      acc += c;
-    }
-    P[cnt] = (int)acc;
-    blocks[sl] = (int)acc;
+  std::vector<int> c((size_t)BS_COUNT * cnt);
+  for (int p = 0; p < cnt; ++p) {
+    const ProbDesc& d = D[p];
+    const bool big = (int64_t)(d.mp / 256) * (d.np / 256) >= split;
+    int* cp = &c[(size_t)p * BS_COUNT];
+    cp[BS_INIT] = group_init_blocks(d.mp, d.np);
+    cp[BS_ABS_A] = cdiv_i(d.m, 256) * cdiv_i(d.k, 64);
+    cp[BS_ABS_B] = d.n * cdiv_i(d.k, 2048);
+    cp[BS_SL_A] = (d.kp / 64) * (d.mp / 64);
+    cp[BS_SL_B] = (d.kp / 64) * (d.np / 64);
+    cp[BS_GS_BIG] = big ? group_gemm_blocks(d.mp, d.np, 256, 1) : 0;
+    cp[BS_GS_SMALL] = big ? 0 : group_gemm_blocks(d.mp, d.np, 128, 1);
+    cp[BS_SHIFTS] = cdiv_i(d.m + d.n, 256);
+    cp[BS_GR_BIG] = big ? group_gemm_blocks(d.mp, d.np, 256, d.N) : 0;
+    cp[BS_GR_SMALL] = big ? 0 : group_gemm_blocks(d.mp, d.np, 128, d.N);
+    cp[BS_CRT] = cdiv_i(d.m, 256 * kCrtRows) * d.n;
   }
+  size_t off = rup(sizeof(ProbDesc) * cnt, 256);
+  for (int sl = 0; sl < BS_COUNT; ++sl) {
+    int64_t tot = 0;
+    for (int p = 0; p < cnt; ++p) tot += c[(size_t)p * BS_COUNT + sl];
+    blocks[sl] = tot > 0x7FFFFFFF ? -1 : (int)tot;
+    map_off[sl] = off;
+    off += rup(sizeof(BlockRef) * (size_t)tot, 256);
+  }
+  out->assign(off, 0);
+  memcpy(out->data(), D.data(), sizeof(ProbDesc) * cnt);
+  for (int sl = 0; sl < BS_COUNT; ++sl) {
+    BlockRef* map = reinterpret_cast<BlockRef*>(out->data() + map_off[sl]);
+    size_t q = 0;
+    for (int p = 0; p < cnt; ++p)
+      for (int l = 0; l < c[(size_t)p * BS_COUNT + sl]; ++l) map[q++] = BlockRef{p, l};
+  }
+}
+
+// Grid sizes over 2^31 - 1 cannot be launched.
+bool table_fits(const int blocks[BS_COUNT]) {
+  for (int sl = 0; sl < BS_COUNT; ++sl)
+    if (blocks[sl] < 0) return false;
+  return true;
 }
 
 // Enqueue the grouped launch sequence on `s` (table already on the device).
 void enqueue_batch(Prec pr, const BatchEntry& e, const CrtConsts* ctab, int* status, hipStream_t s,
                    void* const* C, const int* ldc, const int* mnkN) {
-  const int cnt = e.active;
   const ProbDesc* D = reinterpret_cast<const ProbDesc*>(e.table);
-  const int* pre = reinterpret_cast<const int*>(e.table + rup(sizeof(ProbDesc) * cnt, 256));
-  auto P = [&](int sl) { return pre + sl * (cnt + 1); };
+  auto M = [&](int sl) { return reinterpret_cast<const BlockRef*>(e.table + e.map_off[sl]); };
+  auto B = [&](int sl) { return e.blocks[sl]; };
   for (int p : e.zero_fill) launch_fill_zero(s, pr, C[p], ldc[p], mnkN[4 * p], mnkN[4 * p + 1]);
-  if (cnt == 0) return;
-  launch_group_scale(s, pr, GP_INIT, D, P(BS_INIT), cnt, e.blocks[BS_INIT], ctab);
-  launch_group_scale(s, pr, GP_ABSMAX_A, D, P(BS_ABS_A), cnt, e.blocks[BS_ABS_A], ctab);
-  launch_group_scale(s, pr, GP_ABSMAX_B, D, P(BS_ABS_B), cnt, e.blocks[BS_ABS_B], ctab);
-  launch_group_slices(s, pr, 0, true, D, P(BS_SL_A), cnt, e.blocks[BS_SL_A], ctab);
-  launch_group_slices(s, pr, 0, false, D, P(BS_SL_B), cnt, e.blocks[BS_SL_B], ctab);
-  launch_group_gemm(s, 1, 256, D, P(BS_GS_BIG), cnt, e.blocks[BS_GS_BIG], ctab);
-  launch_group_gemm(s, 1, 128, D, P(BS_GS_SMALL), cnt, e.blocks[BS_GS_SMALL], ctab);
-  launch_group_scale(s, pr, GP_SHIFTS, D, P(BS_SHIFTS), cnt, e.blocks[BS_SHIFTS], ctab);
-  launch_group_slices(s, pr, 1, true, D, P(BS_SL_A), cnt, e.blocks[BS_SL_A], ctab);
-  launch_group_slices(s, pr, 1, false, D, P(BS_SL_B), cnt, e.blocks[BS_SL_B], ctab);
-  launch_group_gemm(s, 0, 256, D, P(BS_GR_BIG), cnt, e.blocks[BS_GR_BIG], ctab);
-  launch_group_gemm(s, 0, 128, D, P(BS_GR_SMALL), cnt, e.blocks[BS_GR_SMALL], ctab);
-  launch_group_crt(s, pr, D, P(BS_CRT), cnt, e.blocks[BS_CRT], ctab, status);
+  if (e.active == 0) return;
+  launch_group_scale(s, pr, GP_INIT, D, M(BS_INIT), B(BS_INIT), ctab);
+  launch_group_scale(s, pr, GP_ABSMAX_A, D, M(BS_ABS_A), B(BS_ABS_A), ctab);
+  launch_group_scale(s, pr, GP_ABSMAX_B, D, M(BS_ABS_B), B(BS_ABS_B), ctab);
+  launch_group_slices(s, pr, 0, true, D, M(BS_SL_A), B(BS_SL_A), ctab);
+  launch_group_slices(s, pr, 0, false, D, M(BS_SL_B), B(BS_SL_B), ctab);
+  launch_group_gemm(s, 1, 256, D, M(BS_GS_BIG), B(BS_GS_BIG), ctab);
+  launch_group_gemm(s, 1, 128, D, M(BS_GS_SMALL), B(BS_GS_SMALL), ctab);
+  launch_group_scale(s, pr, GP_SHIFTS, D, M(BS_SHIFTS), B(BS_SHIFTS), ctab);
+  launch_group_slices(s, pr, 1, true, D, M(BS_SL_A), B(BS_SL_A), ctab);
+  launch_group_slices(s, pr, 1, false, D, M(BS_SL_B), B(BS_SL_B), ctab);
+  launch_group_gemm(s, 0, 256, D, M(BS_GR_BIG), B(BS_GR_BIG), ctab);
+  launch_group_gemm(s, 0, 128, D, M(BS_GR_SMALL), B(BS_GR_SMALL), ctab);
+  launch_group_crt(s, pr, D, M(BS_CRT), B(BS_CRT), e.active, ctab, status);
+}
+
+// Copies a host table to the entry's device table, growing it if needed.
+int upload_table(BatchEntry* e, const std::vector<char>& host, hipStream_t s) {
+  if (hipStreamSynchronize(s) != hipSuccess) return OZAKI2_ERR_HIP;
+  if (host.empty()) return OZAKI2_OK;
+  if (host.size() > e->table_bytes) {
+    if (e->table) (void)hipFree(e->table);
+    e->table = nullptr;
+    e->table_bytes = 0;
+    if (hipMalloc(&e->table, host.size()) != hipSuccess) return OZAKI2_ERR_HIP;
+    e->table_bytes = host.size();
+  }
+  if (hipMemcpy(e->table, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return OZAKI2_ERR_HIP;
+  return OZAKI2_OK;
 }
 
 void free_entry(BatchEntry* e) {
@@ -507,21 +531,16 @@ int tune_split(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* c
   int rc = OZAKI2_OK;
   std::vector<char> host;
   for (int c = 0; c < 4 && rc == OZAKI2_OK; ++c) {
-    build_table(D, cand[c], &host, e->blocks);
-    if (hipStreamSynchronize(s) != hipSuccess ||
-        hipMemcpy(e->table, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
-      rc = OZAKI2_ERR_HIP;
-      break;
-    }
-    const int cnt = e->active;
+    build_table(D, cand[c], &host, e->blocks, e->map_off);
+    if (!table_fits(e->blocks)) continue;
+    if ((rc = upload_table(e, host, s))) break;
     const ProbDesc* Dd = reinterpret_cast<const ProbDesc*>(e->table);
-    const int* pre = reinterpret_cast<const int*>(e->table + rup(sizeof(ProbDesc) * cnt, 256));
+    auto M = [&](int sl) { return reinterpret_cast<const BlockRef*>(e->table + e->map_off[sl]); };
     float ms = 0.f;
     for (int rep = 0; rep < 3; ++rep) {
       if (rep == 1) (void)hipEventRecord(a, s);
-      launch_group_gemm(s, 0, 256, Dd, pre + BS_GR_BIG * (cnt + 1), cnt, e->blocks[BS_GR_BIG], ctab);
-      launch_group_gemm(s, 0, 128, Dd, pre + BS_GR_SMALL * (cnt + 1), cnt, e->blocks[BS_GR_SMALL],
-                        ctab);
+      launch_group_gemm(s, 0, 256, Dd, M(BS_GR_BIG), e->blocks[BS_GR_BIG], ctab);
+      launch_group_gemm(s, 0, 128, Dd, M(BS_GR_SMALL), e->blocks[BS_GR_SMALL], ctab);
     }
     (void)hipEventRecord(b, s);
     if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
@@ -623,24 +642,21 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
       d.W = at<int8_t>(w, L.W);
     }
     std::vector<char> host;
-    build_table(D, 0, &host, e->blocks);
-    e->table_bytes = host.size();
-    if (hipMalloc(&e->table, host.size()) != hipSuccess) {
-      free_entry(e);
-      return OZAKI2_ERR_HIP;
-    }
-    e->split = forced >= 0 ? forced : 0;
+    e->split = forced >= 0 ? forced : 1 << 30;
     if (forced < 0 && e->active > 0) {
       if ((rc = tune_split(D, e, ctab, s, &e->split))) {
         free_entry(e);
         return rc;
       }
     }
-    build_table(D, e->split, &host, e->blocks);
-    if (hipStreamSynchronize(s) != hipSuccess ||
-        hipMemcpy(e->table, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    build_table(D, e->split, &host, e->blocks, e->map_off);
+    if (!table_fits(e->blocks)) {
       free_entry(e);
-      return OZAKI2_ERR_HIP;
+      return OZAKI2_ERR_INVALID_ARG;
+    }
+    if ((rc = upload_table(e, host, s))) {
+      free_entry(e);
+      return rc;
     }
     if (use_graph) {
       hipStream_t cs;

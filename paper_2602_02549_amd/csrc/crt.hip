@@ -10,74 +10,101 @@
 // Every operation is an explicit fma / single rounding (built with
 // -ffp-contract=off), so the result is deterministic.
 #include <cstdint>
+#include <cstdlib>
+#include <type_traits>
 
 #include "ozaki2_internal.h"
 
 namespace oz2 {
 namespace {
 
-// One thread handles 16 consecutive rows i of one column j: one 16-byte load
-// per modulus, 16 outputs written as a contiguous run.
-constexpr int kCrtRows = 16;
-
-template <typename T>
-__device__ inline void crt_body(const int8_t* __restrict__ W, size_t sw, int ldw,
+// One thread handles R consecutive rows i of one column j: one R-byte load
+// per modulus (64 R contiguous bytes per wave) and, when C is aligned for it,
+// 2-element vector stores.  The grouped kernel uses R = kCrtRows.
+template <typename T, int R>
+__device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw, int ldw,
                                 const int* __restrict__ mu, const int* __restrict__ nu, int m,
                                 const CrtConsts& cc, const int* __restrict__ flag,
                                 T* __restrict__ C, int ldc, int j, int iblock) {
-  const int i0 = (iblock * 256 + threadIdx.x) * kCrtRows;
+  static_assert(R == 2 || R == 4 || R == 8, "rows per thread");
+  typedef typename std::conditional<R == 2, uint16_t,
+                                    typename std::conditional<R == 4, uint32_t, uint64_t>::type>::type
+      WordT;
+  const int i0 = (iblock * 256 + threadIdx.x) * R;
   if (i0 >= m) return;
   const int8_t* wp = W + (size_t)j * ldw + i0;
-  double c1[kCrtRows], c2[kCrtRows];
+  double c1[R], c2[R];
 #pragma unroll
-  for (int e = 0; e < kCrtRows; ++e) c1[e] = c2[e] = 0.0;
+  for (int e = 0; e < R; ++e) c1[e] = c2[e] = 0.0;
   for (int l = 0; l < cc.N; ++l) {
-    const uint4 w16 = *reinterpret_cast<const uint4*>(wp + (size_t)l * sw);
-    const uint32_t wv[4] = {w16.x, w16.y, w16.z, w16.w};
+    const uint64_t wv = *reinterpret_cast<const WordT*>(wp + (size_t)l * sw);
     const double s1 = cc.s1[l], s2 = cc.s2[l];
 #pragma unroll
-    for (int e = 0; e < kCrtRows; ++e) {
-      const double w = (double)(int8_t)(wv[e >> 2] >> (8 * (e & 3)));
+    for (int e = 0; e < R; ++e) {
+      const double w = (double)(int8_t)(wv >> (8 * e));
       c1[e] = fma(s1, w, c1[e]);
       if (sizeof(T) == 8) c2[e] = fma(s2, w, c2[e]);
     }
   }
   const bool bad = *flag != 0;
   const int nuj = nu[j];
-  T* cp = C + (size_t)j * ldc;
+  T out[R];
 #pragma unroll
-  for (int e = 0; e < kCrtRows; ++e) {
-    const int i = i0 + e;
-    if (i >= m) break;
+  for (int e = 0; e < R; ++e) {
+    const int i = min(i0 + e, m - 1);
     const double q = rint(c1[e] * cc.Pinv);
     const double t = fma(-q, cc.P1, c1[e]);
     const int ex = -mu[i] - nuj;
     if (sizeof(T) == 8) {
       const double cpp = fma(-q, cc.P2, t + c2[e]);
-      cp[i] = bad ? (T)NAN : (T)ldexp(cpp, ex);
+      out[e] = bad ? (T)NAN : (T)ldexp(cpp, ex);
     } else {
       const float cpp = (float)t;
-      cp[i] = bad ? (T)NAN : (T)ldexp((double)cpp, ex);
+      out[e] = bad ? (T)NAN : (T)ldexp((double)cpp, ex);
     }
+  }
+  T* cp = C + (size_t)j * ldc + i0;
+  if (i0 + R <= m && ((uintptr_t)cp & (2 * sizeof(T) - 1)) == 0) {
+#pragma unroll
+    for (int e = 0; e < R; e += 2) {
+      if (sizeof(T) == 8) {
+        double2 v;
+        v.x = (double)out[e];
+        v.y = (double)out[e + 1];
+        *reinterpret_cast<double2*>(cp + e) = v;
+      } else {
+        float2 v;
+        v.x = (float)out[e];
+        v.y = (float)out[e + 1];
+        *reinterpret_cast<float2*>(cp + e) = v;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+      if (i0 + e < m) cp[e] = out[e];
   }
 }
 
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(256) void k_crt(const int8_t* __restrict__ W, size_t sw, int ldw,
                                              const int* __restrict__ mu, const int* __restrict__ nu,
                                              int m, int n, int iblocks, CrtConsts cc,
                                              const int* __restrict__ flag, T* __restrict__ C, int ldc) {
-  crt_body<T>(W, sw, ldw, mu, nu, m, cc, flag, C, ldc, blockIdx.x / iblocks, blockIdx.x % iblocks);
+  crt_body<T, R>(W, sw, ldw, mu, nu, m, cc, flag, C, ldc, blockIdx.x / iblocks,
+                 blockIdx.x % iblocks);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void kg_crt(const ProbDesc* __restrict__ P,
-                                              const int* __restrict__ prefix, int count,
+                                              const BlockRef* __restrict__ map,
                                               const CrtConsts* __restrict__ ctab) {
-  int lid;
-  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
+  const BlockRef e = map[blockIdx.x];
+  const ProbDesc& d = P[e.x];
+  const int lid = e.y;
   const int iblocks = cdiv_i(d.m, 256 * kCrtRows);
-  crt_body<T>(d.W, (size_t)d.np * d.mp, d.mp, d.mu, d.nu, d.m, ctab[d.N], d.flag, (T*)d.C, d.ldc,
+  crt_body<T, kCrtRows>(d.W, (size_t)d.np * d.mp, d.mp, d.mu, d.nu, d.m, ctab[d.N], d.flag,
+                        (T*)d.C, d.ldc,
               lid / iblocks, lid % iblocks);
 }
 
@@ -106,31 +133,58 @@ void launch_or_status(hipStream_t s, const int* flag, int* status) {
   hipLaunchKernelGGL(k_or_status, dim3(1), dim3(64), 0, s, flag, status);
 }
 
-void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const int* prefix, int count,
-                      int blocks, const CrtConsts* ctab, int* status) {
+void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const BlockRef* map, int blocks,
+                      int count, const CrtConsts* ctab, int* status) {
   if (blocks > 0) {
     if (pr == Prec::F64)
-      hipLaunchKernelGGL(kg_crt<double>, dim3((unsigned)blocks), dim3(256), 0, s, P, prefix, count,
-                         ctab);
+      hipLaunchKernelGGL(kg_crt<double>, dim3((unsigned)blocks), dim3(256), 0, s, P, map, ctab);
     else
-      hipLaunchKernelGGL(kg_crt<float>, dim3((unsigned)blocks), dim3(256), 0, s, P, prefix, count,
-                         ctab);
+      hipLaunchKernelGGL(kg_crt<float>, dim3((unsigned)blocks), dim3(256), 0, s, P, map, ctab);
   }
   hipLaunchKernelGGL(kg_or_status, dim3((unsigned)cdiv_i(count, 256)), dim3(256), 0, s, P, count,
                      status);
 }
 
+namespace {
+
+// Rows per thread of the single-problem CRT: kCrtRows, or 2 / 4 / 8 from the
+// environment variable OZAKI2_CRT_ROWS (read once; a tuning aid).
+int crt_rows() {
+  static int v = [] {
+    const char* e = getenv("OZAKI2_CRT_ROWS");
+    const int r = e ? atoi(e) : kCrtRows;
+    return (r == 2 || r == 4 || r == 8) ? r : kCrtRows;
+  }();
+  return v;
+}
+
+template <typename T, int R>
+void launch_crt_t(hipStream_t s, const int8_t* W, size_t sw, int ldw, const int* mu, const int* nu,
+                  int m, int n, const CrtConsts& cc, const int* flag, void* C, int ldc) {
+  const int iblocks = cdiv_i(m, 256 * R);
+  hipLaunchKernelGGL((k_crt<T, R>), dim3((unsigned)iblocks * (unsigned)n), dim3(256), 0, s, W, sw,
+                     ldw, mu, nu, m, n, iblocks, cc, flag, (T*)C, ldc);
+}
+
+template <typename T>
+void launch_crt_r(hipStream_t s, const int8_t* W, size_t sw, int ldw, const int* mu, const int* nu,
+                  int m, int n, const CrtConsts& cc, const int* flag, void* C, int ldc) {
+  switch (crt_rows()) {
+    case 4: launch_crt_t<T, 4>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc); break;
+    case 8: launch_crt_t<T, 8>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc); break;
+    default: launch_crt_t<T, 2>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc); break;
+  }
+}
+
+}  // namespace
+
 void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,
                 const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
                 int ldc) {
-  const int iblocks = (m + 256 * kCrtRows - 1) / (256 * kCrtRows);
-  dim3 grid((unsigned)iblocks * (unsigned)n);
   if (pr == Prec::F64)
-    hipLaunchKernelGGL(k_crt<double>, grid, dim3(256), 0, s, W, sw, ldw, mu, nu, m, n, iblocks, cc,
-                       flag, (double*)C, ldc);
+    launch_crt_r<double>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
   else
-    hipLaunchKernelGGL(k_crt<float>, grid, dim3(256), 0, s, W, sw, ldw, mu, nu, m, n, iblocks, cc,
-                       flag, (float*)C, ldc);
+    launch_crt_r<float>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
 }
 
 void launch_fill_zero(hipStream_t s, Prec pr, void* C, int ldc, int m, int n) {

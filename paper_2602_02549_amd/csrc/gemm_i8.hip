@@ -98,14 +98,15 @@ __device__ inline int swz(int r) {
 // Each buffer holds the X tile then the Y tile as rows of BK bytes.
 // `bid` is the workgroup's index among the `launched` workgroups of this
 // product (launched >= tiles_x * tiles_y * nz; the surplus exits at once).
-template <int BX, int BY, int BK, int EPI, bool BF16>
-__device__ inline void gemm_body(const int8_t* __restrict__ X, size_t sx,
+template <int BX, int BY, int BK, int EPI, bool BF16, int SLOTS = 0>
+__device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t sx,
                                  const int8_t* __restrict__ Y, size_t sy, int tiles_x,
                                  int tiles_y, int nz, int k_pad, const CrtConsts& cc,
                                  int8_t* __restrict__ W, size_t sw, int ldw,
                                  int* __restrict__ xmax, int* __restrict__ ymax, int bid,
                                  int launched) {
   static_assert(BK == 64 || BK == 128, "BK");
+  static_assert(SLOTS == 0 || (SLOTS == 5 && BK == 128), "half-group slots: 5, with BK = 128");
   constexpr int WX = BX / 2, WY = BY / 2;
   constexpr int TX = WX / 32, TY = WY / 32;
   constexpr int CPR = BK / 16;                   // 16-byte chunks per LDS row
@@ -114,7 +115,10 @@ __device__ inline void gemm_body(const int8_t* __restrict__ X, size_t sx,
   constexpr int STAGE = (BX + BY) * BK;          // one stage buffer
   constexpr int GROUP_BYTES = (BX + BY) * 128;   // one 128-k group
   constexpr int GROUP = 8;
-  __shared__ __attribute__((aligned(1024))) int8_t lds[2 * GROUP_BYTES];
+  constexpr int XSLOT = BX * 128, YSLOT = BY * 128;  // one half-group (X or Y side)
+  constexpr int SLOT = XSLOT > YSLOT ? XSLOT : YSLOT;
+  constexpr int LDS_BYTES = SLOTS ? SLOTS * SLOT : 2 * GROUP_BYTES;
+  __shared__ __attribute__((aligned(1024))) int8_t lds[LDS_BYTES];
 
   // ---- workgroup -> (slice z, tile) ------------------------------------
   const int total = tiles_x * tiles_y * nz;
@@ -184,13 +188,17 @@ __device__ inline void gemm_body(const int8_t* __restrict__ X, size_t sx,
     const int c = (BK == 64 ? 2 * (j & 1) : 2 * j) + (lane >> 5);
     fo[j] = (BK == 64 ? (j >> 1) * STAGE : 0) + frow * BK + ((c ^ swz<BK>(frow)) * 16);
   }
-  auto load_frags = [&](const int8_t* buf, int j, v4i (&a)[TX], v4i (&b)[TY]) {
+  auto load_frags2 = [&](const int8_t* xbuf, const int8_t* ybuf, int j, v4i (&a)[TX],
+                         v4i (&b)[TY]) {
 #pragma unroll
     for (int tx = 0; tx < TX; ++tx)
-      a[tx] = *reinterpret_cast<const v4i*>(buf + (wx * WX + tx * 32) * BK + fo[j]);
+      a[tx] = *reinterpret_cast<const v4i*>(xbuf + (wx * WX + tx * 32) * BK + fo[j]);
 #pragma unroll
     for (int ty = 0; ty < TY; ++ty)
-      b[ty] = *reinterpret_cast<const v4i*>(buf + (BX + wy * WY + ty * 32) * BK + fo[j]);
+      b[ty] = *reinterpret_cast<const v4i*>(ybuf + (wy * WY + ty * 32) * BK + fo[j]);
+  };
+  auto load_frags = [&](const int8_t* buf, int j, v4i (&a)[TX], v4i (&b)[TY]) {
+    load_frags2(buf, buf + BX * BK, j, a, b);
   };
   auto mfmas = [&](const v4i (&a)[TX], const v4i (&b)[TY]) {
 #pragma unroll
@@ -204,34 +212,93 @@ __device__ inline void gemm_body(const int8_t* __restrict__ X, size_t sx,
         else
           acc[tx][ty] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tx], b[ty], acc[tx][ty], 0, 0, 0);
   };
-  // k_pad is a multiple of 128.  Group gi lives in half gi % 2 of the LDS; it
-  // is issued while group gi-1 is consumed and waited for (all copies done +
-  // barrier) before use, which also certifies that every wave has finished
-  // reading group gi-1.  No branch encloses an MFMA, so the accumulators stay
-  // in place across iterations.
-  const int NG = k_pad / 128;
-  issue_group(lds, 0);
-  for (int gi = 0; gi < NG; ++gi) {
-    int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
-    wait_vmcnt<0>();
-    __builtin_amdgcn_s_barrier();
-    v4i a0[TX], b0[TY], a1[TX], b1[TY];
-    // the first fragment reads go out before the next group's copies are
-    // issued, so their LDS latency overlaps the copy issue
-    load_frags(buf, 0, a0, b0);
-    if (gi + 1 < NG) issue_group(lds + ((gi + 1) & 1) * GROUP_BYTES, (gi + 1) * 128);
-    load_frags(buf, 1, a1, b1);
-    __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the MFMAs
-    mfmas(a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
-    load_frags(buf, 2, a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
-    mfmas(a1, b1);
-    __builtin_amdgcn_sched_barrier(0);
-    load_frags(buf, 3, a1, b1);
-    __builtin_amdgcn_sched_barrier(0);
-    mfmas(a0, b0);
-    mfmas(a1, b1);
+  if constexpr (SLOTS == 5) {
+    // Five half-group slots: half-group h (h = 2g for the X side of group g,
+    // 2g+1 for its Y side) lives in slot h % 5.  At the top of iteration g
+    // the copies issued so far end with Y_g, X_{g+1}; each wave waits until
+    // only X_{g+1} may be outstanding (its own copies of group g have
+    // landed), then a barrier (everyone's have, and every wave has finished
+    // reading group g-1).  The two slots of group g-1 then receive Y_{g+1}
+    // and X_{g+2}, so one and a half groups of copies are always queued
+    // behind the group being multiplied.
+    const int NG = k_pad / 128;
+    auto issue_x = [&](int g, int slot) {
+      const uint32_t b = lds_addr(lds + slot * SLOT);
+#pragma unroll
+      for (int q = 0; q < IX; ++q)
+        dma16(xsrc + q * rowstep + g * 128 + ((q & 1) ? ch_o : ch_e),
+              b + (uint32_t)((wave_u * IX + q) * 1024));
+    };
+    auto issue_y = [&](int g, int slot) {
+      const uint32_t b = lds_addr(lds + slot * SLOT);
+#pragma unroll
+      for (int q = 0; q < IY; ++q)
+        dma16(ysrc + q * rowstep + g * 128 + ((q & 1) ? ch_o : ch_e),
+              b + (uint32_t)((wave_u * IY + q) * 1024));
+    };
+    auto add5 = [](int a, int d) { return a + d >= 5 ? a + d - 5 : a + d; };
+    issue_x(0, 0);
+    issue_y(0, 1);
+    if (NG > 1) issue_x(1, 2);
+    int xs = 0;                              // slot of X_g; Y_g is in xs + 1
+    for (int gi = 0; gi < NG; ++gi) {
+      const int ys = add5(xs, 1);
+      const int8_t* const xb = lds + xs * SLOT;
+      const int8_t* const yb = lds + ys * SLOT;
+      if (gi + 1 < NG)
+        wait_vmcnt<IX>();
+      else
+        wait_vmcnt<0>();
+      __builtin_amdgcn_s_barrier();
+      v4i a0[TX], b0[TY], a1[TX], b1[TY];
+      load_frags2(xb, yb, 0, a0, b0);
+      if (gi + 1 < NG) issue_y(gi + 1, add5(xs, 3));
+      if (gi + 2 < NG) issue_x(gi + 2, add5(xs, 4));
+      load_frags2(xb, yb, 1, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas(a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      load_frags2(xb, yb, 2, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      load_frags2(xb, yb, 3, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas(a0, b0);
+      mfmas(a1, b1);
+      xs = add5(xs, 2);
+    }
+  } else {
+    // k_pad is a multiple of 128.  Group gi lives in half gi % 2 of the LDS; it
+    // is issued while group gi-1 is consumed and waited for (all copies done +
+    // barrier) before use, which also certifies that every wave has finished
+    // reading group gi-1.  No branch encloses an MFMA, so the accumulators stay
+    // in place across iterations.
+    const int NG = k_pad / 128;
+    issue_group(lds, 0);
+    for (int gi = 0; gi < NG; ++gi) {
+      int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
+      wait_vmcnt<0>();
+      __builtin_amdgcn_s_barrier();
+      v4i a0[TX], b0[TY], a1[TX], b1[TY];
+      // the first fragment reads go out before the next group's copies are
+      // issued, so their LDS latency overlaps the copy issue
+      load_frags(buf, 0, a0, b0);
+      if (gi + 1 < NG) issue_group(lds + ((gi + 1) & 1) * GROUP_BYTES, (gi + 1) * 128);
+      load_frags(buf, 1, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the MFMAs
+      mfmas(a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      load_frags(buf, 2, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      load_frags(buf, 3, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas(a0, b0);
+      mfmas(a1, b1);
+    }
+
   }
 
   const int xb = x0 + wx * WX, yb = y0 + wy * WY;
@@ -296,50 +363,51 @@ __device__ inline void gemm_body(const int8_t* __restrict__ X, size_t sx,
   }
 }
 
-template <int BX, int BY, int BK, int OCC, int EPI, bool BF16 = false>
+template <int BX, int BY, int BK, int OCC, int EPI, bool BF16 = false, int SLOTS = 0>
 __global__ __launch_bounds__(256, OCC) void k_gemm_i8(const int8_t* __restrict__ X, size_t sx,
                                                     const int8_t* __restrict__ Y, size_t sy,
                                                     int tiles_x, int tiles_y, int nz, int k_pad,
                                                     CrtConsts cc, int8_t* __restrict__ W, size_t sw,
                                                     int ldw, int* __restrict__ xmax,
                                                     int* __restrict__ ymax) {
-  gemm_body<BX, BY, BK, EPI, BF16>(X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax,
-                                   ymax, blockIdx.x, gridDim.x);
+  gemm_body<BX, BY, BK, EPI, BF16, SLOTS>(X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw,
+                                          ldw, xmax, ymax, blockIdx.x, gridDim.x);
 }
 
 // Grouped: the scaling product (EPI 1) or the N residue products (EPI 0) of
 // every problem of a batch.
 template <int BX, int BY, int OCC, int EPI>
 __global__ __launch_bounds__(256, OCC) void kg_gemm(const ProbDesc* __restrict__ P,
-                                                    const int* __restrict__ prefix, int count,
+                                                    const BlockRef* __restrict__ map,
                                                     const CrtConsts* __restrict__ ctab) {
-  int lid;
-  const int p = find_problem(prefix, count, blockIdx.x, &lid);
-  const ProbDesc& d = P[p];
+  static_assert(BX == BY, "square tiles");
+  const BlockRef e = map[blockIdx.x];
+  const ProbDesc& d = P[e.x];
   const int nz = EPI == 0 ? d.N : 1;
   gemm_body<BX, BY, 128, EPI, false>(d.As, EPI == 0 ? (size_t)d.mp * d.kp : 0, d.Bs,
                                      EPI == 0 ? (size_t)d.np * d.kp : 0, d.mp / BX, d.np / BY, nz,
                                      d.kp, ctab[d.N], d.W, (size_t)d.np * d.mp, d.mp, d.rmax,
-                                     d.cmax, lid, prefix[p + 1] - prefix[p]);
+                                     d.cmax, e.y, group_gemm_blocks(d.mp, d.np, BX, nz));
 }
 
-template <int BX, int BY, int BK, int OCC>
+template <int BX, int BY, int BK, int OCC, int SLOTS = 0>
 void launch_cfg(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                 int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
                 size_t sw, int ldw, int* xmax, int* ymax) {
   const int tiles_x = nx_pad / BX, tiles_y = ny_pad / BY;
   dim3 grid((unsigned)(tiles_x * tiles_y * nz));
   if (epi == 0)
-    hipLaunchKernelGGL((k_gemm_i8<BX, BY, BK, OCC, 0>), grid, dim3(256), 0, s, X, sx, Y, sy,
-                       tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+    hipLaunchKernelGGL((k_gemm_i8<BX, BY, BK, OCC, 0, false, SLOTS>), grid, dim3(256), 0, s, X,
+                       sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
   else
-    hipLaunchKernelGGL((k_gemm_i8<BX, BY, BK, OCC, 1>), grid, dim3(256), 0, s, X, sx, Y, sy,
-                       tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+    hipLaunchKernelGGL((k_gemm_i8<BX, BY, BK, OCC, 1, false, SLOTS>), grid, dim3(256), 0, s, X,
+                       sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
 }
 
 // Tile configuration: 0 = automatic; 1 = 256x256 (BK 128), 2 = 128x128
-// (BK 128), 3 = 256x256 (BK 64), 4 = 128x128 (BK 64) (environment variable
-// OZAKI2_GEMM_CFG, read once; a tuning aid).
+// (BK 128), 3 = 256x256 (BK 64), 4 = 128x128 (BK 64), 5 = 256x256 with five
+// half-group slots, 6 = 128x128 with five half-group slots (environment
+// variable OZAKI2_GEMM_CFG, read once; a tuning aid).
 int forced_cfg() {
   static int v = [] {
     const char* e = getenv("OZAKI2_GEMM_CFG");
@@ -350,20 +418,20 @@ int forced_cfg() {
 
 }  // namespace
 
-void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const int* prefix,
-                       int count, int blocks, const CrtConsts* ctab) {
+void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const BlockRef* map,
+                       int blocks, const CrtConsts* ctab) {
   if (blocks <= 0) return;
   const dim3 g((unsigned)blocks), b(256);
   if (tile == 256) {
     if (epi == 0)
-      hipLaunchKernelGGL((kg_gemm<256, 256, 1, 0>), g, b, 0, s, P, prefix, count, ctab);
+      hipLaunchKernelGGL((kg_gemm<256, 256, 1, 0>), g, b, 0, s, P, map, ctab);
     else
-      hipLaunchKernelGGL((kg_gemm<256, 256, 1, 1>), g, b, 0, s, P, prefix, count, ctab);
+      hipLaunchKernelGGL((kg_gemm<256, 256, 1, 1>), g, b, 0, s, P, map, ctab);
   } else {
     if (epi == 0)
-      hipLaunchKernelGGL((kg_gemm<128, 128, 2, 0>), g, b, 0, s, P, prefix, count, ctab);
+      hipLaunchKernelGGL((kg_gemm<128, 128, 2, 0>), g, b, 0, s, P, map, ctab);
     else
-      hipLaunchKernelGGL((kg_gemm<128, 128, 2, 1>), g, b, 0, s, P, prefix, count, ctab);
+      hipLaunchKernelGGL((kg_gemm<128, 128, 2, 1>), g, b, 0, s, P, map, ctab);
   }
 }
 
@@ -395,8 +463,8 @@ void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const in
   int cfg = forced_cfg();
   const long t256 = (long)(nx_pad / 256) * (ny_pad / 256) * nz;
   const bool fits256 = nx_pad % 256 == 0 && ny_pad % 256 == 0;
-  if (cfg < 1 || cfg > 4) cfg = (fits256 && t256 >= 512) ? 1 : 2;
-  if ((cfg == 1 || cfg == 3) && !fits256) cfg = 2;
+  if (cfg < 1 || cfg > 6) cfg = (fits256 && t256 >= 512) ? 1 : 2;
+  if ((cfg == 1 || cfg == 3 || cfg == 5) && !fits256) cfg = 2;
   switch (cfg) {
     case 1:
       launch_cfg<256, 256, 128, 1>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw,
@@ -405,6 +473,14 @@ void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const in
     case 3:
       launch_cfg<256, 256, 64, 1>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw,
                                   xmax, ymax);
+      break;
+    case 5:
+      launch_cfg<256, 256, 128, 1, 5>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw,
+                                      ldw, xmax, ymax);
+      break;
+    case 6:
+      launch_cfg<128, 128, 128, 2, 5>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw,
+                                      ldw, xmax, ymax);
       break;
     case 4:
       launch_cfg<128, 128, 64, 2>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw,

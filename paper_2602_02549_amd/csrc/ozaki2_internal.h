@@ -10,6 +10,7 @@ constexpr int kMaxModuli = 49;   // Section 3.1: p_l <= 256 pairwise coprime => 
 constexpr int kMaxK = 1 << 17;   // Section 3: k <= 2^17
 constexpr int kRowPad = 256;     // m and n are padded to this multiple in the workspace
 constexpr int kKPad = 128;       // k is padded to this multiple (bytes of INT8 per row)
+constexpr int kCrtRows = 4;      // CRT: consecutive rows per thread (256 threads per block)
 
 // Per-(N, b) constants of Section 3.1 and Algorithms 2-3, passed to kernels
 // by value (they land in the kernel-argument segment and are read with
@@ -70,9 +71,9 @@ __device__ inline int shift_prime_bits(uint64_t bits) {
 
 // ---------------------------------------------------------------------------
 // Grouped (batched) execution: one launch per phase covers every problem of a
-// batch.  Each problem has a descriptor; per phase, a prefix array over the
-// problems gives the first workgroup of each problem, and a workgroup finds
-// its problem by binary search.
+// batch.  Each problem has a descriptor; per phase, a block map gives every
+// workgroup its problem and its index among that problem's workgroups (one
+// uniform load, no search).
 struct ProbDesc {
   int m, n, k, N;
   int mp, np, kp;           // padded sizes (workspace layout)
@@ -92,26 +93,26 @@ struct ProbDesc {
   int8_t* W;                // [N][np][mp]
 };
 
-// Problem index of workgroup `bid` given the phase's prefix array
-// (prefix[0] = 0, prefix[count] = grid size); `lid` receives the local id.
-__device__ inline int find_problem(const int* __restrict__ prefix, int count, int bid, int* lid) {
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= bid) lo = mid; else hi = mid - 1;
-  }
-  *lid = bid - prefix[lo];
-  return lo;
-}
+// Block map entry: x = problem index, y = local workgroup index.
+typedef int2 BlockRef;
 
 enum GroupPhase {
   GP_INIT, GP_ABSMAX_A, GP_ABSMAX_B, GP_SLICE_A, GP_SLICE_B, GP_GEMM_SCALE, GP_SHIFTS,
   GP_GEMM_RES, GP_CRT, GP_COUNT
 };
 
-// Workgroup counts per phase of one problem (the same decomposition is used
-// by the single-problem launches).
 __host__ __device__ inline int cdiv_i(int a, int b) { return (a + b - 1) / b; }
+
+// Workgroups of one problem in the grouped init phase (a grid-stride loop over
+// max(mp, np) entries) and in a grouped product with `tile` x `tile` output
+// tiles and nz slices (padded to a multiple of 8 so that every problem starts
+// on XCD 0).
+__host__ __device__ inline int group_init_blocks(int mp, int np) {
+  return cdiv_i(mp > np ? mp : np, 256);
+}
+__host__ __device__ inline int group_gemm_blocks(int mp, int np, int tile, int nz) {
+  return ((mp / tile) * (np / tile) * nz + 7) / 8 * 8;
+}
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (each defined next to its kernel)
@@ -170,15 +171,16 @@ void launch_plan_verify(hipStream_t s, const float* S, int lds_, int m, int n, c
                         const double* cs, const double* sr, const double* sc, const PlanTable& pt,
                         int N, int* bad);
 
-// Grouped launches (one per phase for a whole batch); `blocks` = prefix[count].
-void launch_group_scale(hipStream_t s, Prec pr, int phase, const ProbDesc* P, const int* prefix,
-                        int count, int blocks, const CrtConsts* ctab);
+// Grouped launches (one per phase for a whole batch of `count` problems);
+// `map` holds `blocks` entries, one per workgroup.
+void launch_group_scale(hipStream_t s, Prec pr, int phase, const ProbDesc* P, const BlockRef* map,
+                        int blocks, const CrtConsts* ctab);
 void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, const ProbDesc* P,
-                         const int* prefix, int count, int blocks, const CrtConsts* ctab);
-void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const int* prefix,
-                       int count, int blocks, const CrtConsts* ctab);
-void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const int* prefix, int count,
-                      int blocks, const CrtConsts* ctab, int* status);
+                         const BlockRef* map, int blocks, const CrtConsts* ctab);
+void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const BlockRef* map,
+                       int blocks, const CrtConsts* ctab);
+void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const BlockRef* map, int blocks,
+                      int count, const CrtConsts* ctab, int* status);
 
 // crt.hip: C(i, j) from W_l[j][i] (slices of row length ldw), mu, nu.
 void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,

@@ -28,10 +28,12 @@ constexpr int kTile = 64;
 // at least 1/(2p) away from a half-integer for odd p, so rint gives round(r/p)
 // and the result already lies in [-(p-1)/2, (p-1)/2].  For p = 256 every step
 // is exact and the result lies in [-128, 128]; the byte store wraps 128 to
-// -128.
-__device__ inline int residue_i8(double v, int p, double pinv, int nsteps) {
+// -128.  NS (1..4 for N <= 49) is a compile-time step count.
+template <int NS>
+__device__ __forceinline__ int residue_i8(double v, int p, double pinv) {
   double r = v;
-  for (int s = 0; s < nsteps; ++s) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
     const double q = rint(r * pinv);
     r = fma(-q, (double)p, r);
   }
@@ -43,9 +45,29 @@ __device__ inline uint32_t pack4(int a, int b, int c, int d) {
          ((uint32_t)(d & 0xFF) << 24);
 }
 
+// The N residue bytes of 16 consecutive k of one row, one 16-byte store per
+// modulus.
+template <int NS>
+__device__ __forceinline__ void store_residues(const double (&v)[16], const CrtConsts& cc,
+                                               int8_t* __restrict__ dst, size_t slice) {
+  for (int l = 0; l < cc.N; ++l) {
+    const int p = cc.p[l];
+    const double pinv = cc.pinv[l];
+    int b[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) b[e] = residue_i8<NS>(v[e], p, pinv);
+    uint4 w;
+    w.x = pack4(b[0], b[1], b[2], b[3]);
+    w.y = pack4(b[4], b[5], b[6], b[7]);
+    w.z = pack4(b[8], b[9], b[10], b[11]);
+    w.w = pack4(b[12], b[13], b[14], b[15]);
+    *reinterpret_cast<uint4*>(dst + (size_t)l * slice) = w;
+  }
+}
+
 // One 64 x 64 tile (k tile kx, row tile ry) of the slices.
 template <typename T, bool TRANS, int MODE>
-__device__ inline void slices_body(const T* __restrict__ src, int ld, int rows, int k, int k_pad,
+__device__ __forceinline__ void slices_body(const T* __restrict__ src, int ld, int rows, int k, int k_pad,
                                    size_t slice, const uint64_t* __restrict__ bits,
                                    const int* __restrict__ shift, const CrtConsts& cc,
                                    int8_t* __restrict__ out, int kx, int ry) {
@@ -94,18 +116,11 @@ __device__ inline void slices_body(const T* __restrict__ src, int ld, int rows, 
     const int sh = rg < rows ? shift[rg] : 0;
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = trunc(ldexp(v[e], sh));
-    for (int l = 0; l < cc.N; ++l) {
-      const int p = cc.p[l];
-      const double pinv = cc.pinv[l];
-      int b[16];
-#pragma unroll
-      for (int e = 0; e < 16; ++e) b[e] = residue_i8(v[e], p, pinv, cc.nsteps);
-      uint4 w;
-      w.x = pack4(b[0], b[1], b[2], b[3]);
-      w.y = pack4(b[4], b[5], b[6], b[7]);
-      w.z = pack4(b[8], b[9], b[10], b[11]);
-      w.w = pack4(b[12], b[13], b[14], b[15]);
-      *reinterpret_cast<uint4*>(dst + (size_t)l * slice) = w;
+    switch (cc.nsteps) {   // uniform
+      case 1: store_residues<1>(v, cc, dst, slice); break;
+      case 2: store_residues<2>(v, cc, dst, slice); break;
+      case 3: store_residues<3>(v, cc, dst, slice); break;
+      default: store_residues<4>(v, cc, dst, slice); break;
     }
   }
 }
@@ -123,10 +138,11 @@ __global__ __launch_bounds__(256) void k_slices(const T* __restrict__ src, int l
 // Grouped: A side (TRANS, rows = m) or B side (rows = n) of every problem.
 template <typename T, bool ASIDE, int MODE>
 __global__ __launch_bounds__(256) void kg_slices(const ProbDesc* __restrict__ P,
-                                                 const int* __restrict__ prefix, int count,
+                                                 const BlockRef* __restrict__ map,
                                                  const CrtConsts* __restrict__ ctab) {
-  int lid;
-  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
+  const BlockRef e = map[blockIdx.x];
+  const ProbDesc& d = P[e.x];
+  const int lid = e.y;
   const int gx = d.kp / kTile;
   if (ASIDE)
     slices_body<T, true, MODE>((const T*)d.A, d.lda, d.m, d.k, d.kp, (size_t)d.mp * d.kp,
@@ -210,30 +226,30 @@ void launch_t(hipStream_t s, int mode, bool trans, const T* src, int ld, int row
 }
 
 template <typename T, int MODE>
-void group_slices_t(hipStream_t s, bool aside, const ProbDesc* P, const int* prefix, int count,
-                    int blocks, const CrtConsts* ctab) {
+void group_slices_t(hipStream_t s, bool aside, const ProbDesc* P, const BlockRef* map, int blocks,
+                    const CrtConsts* ctab) {
   const dim3 g((unsigned)blocks), b(256);
   if (aside)
-    hipLaunchKernelGGL((kg_slices<T, true, MODE>), g, b, 0, s, P, prefix, count, ctab);
+    hipLaunchKernelGGL((kg_slices<T, true, MODE>), g, b, 0, s, P, map, ctab);
   else
-    hipLaunchKernelGGL((kg_slices<T, false, MODE>), g, b, 0, s, P, prefix, count, ctab);
+    hipLaunchKernelGGL((kg_slices<T, false, MODE>), g, b, 0, s, P, map, ctab);
 }
 
 }  // namespace
 
 void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, const ProbDesc* P,
-                         const int* prefix, int count, int blocks, const CrtConsts* ctab) {
+                         const BlockRef* map, int blocks, const CrtConsts* ctab) {
   if (blocks <= 0) return;
   if (pr == Prec::F64) {
     if (mode == 0)
-      group_slices_t<double, 0>(s, aside, P, prefix, count, blocks, ctab);
+      group_slices_t<double, 0>(s, aside, P, map, blocks, ctab);
     else
-      group_slices_t<double, 1>(s, aside, P, prefix, count, blocks, ctab);
+      group_slices_t<double, 1>(s, aside, P, map, blocks, ctab);
   } else {
     if (mode == 0)
-      group_slices_t<float, 0>(s, aside, P, prefix, count, blocks, ctab);
+      group_slices_t<float, 0>(s, aside, P, map, blocks, ctab);
     else
-      group_slices_t<float, 1>(s, aside, P, prefix, count, blocks, ctab);
+      group_slices_t<float, 1>(s, aside, P, map, blocks, ctab);
   }
 }
 

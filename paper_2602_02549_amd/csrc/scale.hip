@@ -14,7 +14,7 @@ namespace {
 
 constexpr uint64_t kExpMask = 0x7FF0000000000000ull;
 
-__device__ inline void init_body(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pad,
+__device__ __forceinline__ void init_body(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pad,
                                  int* rmax, int* cmax, int* flag, int t, int stride) {
   for (int i = t; i < m_pad; i += stride) {
     rowbits[i] = 0;
@@ -37,7 +37,7 @@ __global__ void k_init(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pa
 // a chunk of 64 columns (workgroup bx + gx * by); consecutive threads read
 // consecutive rows.
 template <typename T>
-__device__ inline void absmax_rows_body(const T* __restrict__ A, int lda, int m, int k,
+__device__ __forceinline__ void absmax_rows_body(const T* __restrict__ A, int lda, int m, int k,
                                         uint64_t* __restrict__ rowbits, int* __restrict__ flag,
                                         int bx, int by) {
   const int i = bx * 256 + threadIdx.x;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_absmax_rows(const T* __restrict__ A, in
 
 // B column-major (k x n): one workgroup per (column j, chunk of 2048 rows).
 template <typename T>
-__device__ inline void absmax_cols_body(const T* __restrict__ B, int ldb, int k, int n,
+__device__ __forceinline__ void absmax_cols_body(const T* __restrict__ B, int ldb, int k, int n,
                                         uint64_t* __restrict__ colbits, int* __restrict__ flag,
                                         int j, int chunk) {
   const int h0 = chunk * 2048;
@@ -188,7 +188,7 @@ __device__ inline int floor_fma(float c, float e, float Pp) {
   return (int)f;
 }
 
-__device__ inline void shifts_body(const uint64_t* __restrict__ rowbits, const int* __restrict__ rmax,
+__device__ __forceinline__ void shifts_body(const uint64_t* __restrict__ rowbits, const int* __restrict__ rmax,
                                    int m, const uint64_t* __restrict__ colbits,
                                    const int* __restrict__ cmax, int n, float Pprime, float c,
                                    int* __restrict__ mu_p, int* __restrict__ nu_p,
@@ -226,40 +226,38 @@ __global__ __launch_bounds__(256) void k_shifts(const uint64_t* __restrict__ row
 
 // ---- grouped versions ------------------------------------------------------
 __global__ __launch_bounds__(256) void kg_init(const ProbDesc* __restrict__ P,
-                                               const int* __restrict__ prefix, int count) {
-  int lid;
-  const int p = find_problem(prefix, count, blockIdx.x, &lid);
-  const ProbDesc& d = P[p];
-  const int blocks = prefix[p + 1] - prefix[p];
-  init_body(d.rowbits, d.mp, d.colbits, d.np, d.rmax, d.cmax, d.flag, lid * 256 + threadIdx.x,
-            blocks * 256);
+                                               const BlockRef* __restrict__ map) {
+  const BlockRef e = map[blockIdx.x];
+  const ProbDesc& d = P[e.x];
+  init_body(d.rowbits, d.mp, d.colbits, d.np, d.rmax, d.cmax, d.flag, e.y * 256 + threadIdx.x,
+            group_init_blocks(d.mp, d.np) * 256);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void kg_absmax_rows(const ProbDesc* __restrict__ P,
-                                                      const int* __restrict__ prefix, int count) {
-  int lid;
-  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
+                                                      const BlockRef* __restrict__ map) {
+  const BlockRef e = map[blockIdx.x];
+  const ProbDesc& d = P[e.x];
   const int gx = cdiv_i(d.m, 256);
-  absmax_rows_body<T>((const T*)d.A, d.lda, d.m, d.k, d.rowbits, d.flag, lid % gx, lid / gx);
+  absmax_rows_body<T>((const T*)d.A, d.lda, d.m, d.k, d.rowbits, d.flag, e.y % gx, e.y / gx);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void kg_absmax_cols(const ProbDesc* __restrict__ P,
-                                                      const int* __restrict__ prefix, int count) {
-  int lid;
-  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
-  absmax_cols_body<T>((const T*)d.B, d.ldb, d.k, d.n, d.colbits, d.flag, lid % d.n, lid / d.n);
+                                                      const BlockRef* __restrict__ map) {
+  const BlockRef e = map[blockIdx.x];
+  const ProbDesc& d = P[e.x];
+  absmax_cols_body<T>((const T*)d.B, d.ldb, d.k, d.n, d.colbits, d.flag, e.y % d.n, e.y / d.n);
 }
 
 __global__ __launch_bounds__(256) void kg_shifts(const ProbDesc* __restrict__ P,
-                                                 const int* __restrict__ prefix, int count,
+                                                 const BlockRef* __restrict__ map,
                                                  const CrtConsts* __restrict__ ctab) {
-  int lid;
-  const ProbDesc& d = P[find_problem(prefix, count, blockIdx.x, &lid)];
+  const BlockRef e = map[blockIdx.x];
+  const ProbDesc& d = P[e.x];
   const CrtConsts& cc = ctab[d.N];
   shifts_body(d.rowbits, d.rmax, d.m, d.colbits, d.cmax, d.n, cc.Pprime, cc.c, nullptr, nullptr,
-              d.mu, d.nu, nullptr, lid * 256 + threadIdx.x);
+              d.mu, d.nu, nullptr, e.y * 256 + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_log2f(const float* __restrict__ d, float* __restrict__ out,
@@ -315,28 +313,28 @@ void launch_log2f(hipStream_t s, const float* d, float* out, int count) {
   hipLaunchKernelGGL(k_log2f, dim3(cdiv(count, 256)), dim3(256), 0, s, d, out, count);
 }
 
-void launch_group_scale(hipStream_t s, Prec pr, int phase, const ProbDesc* P, const int* prefix,
-                        int count, int blocks, const CrtConsts* ctab) {
+void launch_group_scale(hipStream_t s, Prec pr, int phase, const ProbDesc* P, const BlockRef* map,
+                        int blocks, const CrtConsts* ctab) {
   if (blocks <= 0) return;
   const dim3 g((unsigned)blocks), b(256);
   switch (phase) {
     case GP_INIT:
-      hipLaunchKernelGGL(kg_init, g, b, 0, s, P, prefix, count);
+      hipLaunchKernelGGL(kg_init, g, b, 0, s, P, map);
       break;
     case GP_ABSMAX_A:
       if (pr == Prec::F64)
-        hipLaunchKernelGGL(kg_absmax_rows<double>, g, b, 0, s, P, prefix, count);
+        hipLaunchKernelGGL(kg_absmax_rows<double>, g, b, 0, s, P, map);
       else
-        hipLaunchKernelGGL(kg_absmax_rows<float>, g, b, 0, s, P, prefix, count);
+        hipLaunchKernelGGL(kg_absmax_rows<float>, g, b, 0, s, P, map);
       break;
     case GP_ABSMAX_B:
       if (pr == Prec::F64)
-        hipLaunchKernelGGL(kg_absmax_cols<double>, g, b, 0, s, P, prefix, count);
+        hipLaunchKernelGGL(kg_absmax_cols<double>, g, b, 0, s, P, map);
       else
-        hipLaunchKernelGGL(kg_absmax_cols<float>, g, b, 0, s, P, prefix, count);
+        hipLaunchKernelGGL(kg_absmax_cols<float>, g, b, 0, s, P, map);
       break;
     case GP_SHIFTS:
-      hipLaunchKernelGGL(kg_shifts, g, b, 0, s, P, prefix, count, ctab);
+      hipLaunchKernelGGL(kg_shifts, g, b, 0, s, P, map, ctab);
       break;
     default:
       break;

@@ -265,6 +265,7 @@ bool build_consts(int N, int b, CrtConsts* out) {
     R = 128.0L + R * std::ldexp((long double)1, -51);
     ++steps;
   }
+  if (steps > 4) return false;   // the residue kernels instantiate 1..4 steps
   cc.nsteps = steps;
   *out = cc;
   return true;

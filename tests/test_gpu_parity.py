@@ -145,13 +145,14 @@ def test_log2f_exhaustive():
         assert np.array_equal(got[s:s + chunk], ref), f"log2f mismatch in chunk at {s}"
 
 
-@pytest.mark.parametrize("dtype,N", [(np.float64, 14), (np.float32, 7)])
-def test_full_size_sampled(dtype, N):
-    # The bench workload (FP64 8192^3; the FP32 case uses the same size) in
-    # the launch configuration the benchmark times; sampled rows x columns
-    # against the oracle, which needs only those rows/columns of the scaled
-    # integers plus full-matrix row/column maxima of Cbar.
-    m = n = k = 8192
+@pytest.mark.parametrize("dtype,N,size", [(np.float64, 14, 8192), (np.float32, 7, 8192),
+                                          (np.float32, 7, 16384)])
+def test_full_size_sampled(dtype, N, size):
+    # The bench workload (FP64 8192^3) in the launch configuration the
+    # benchmark times, and the FP32 16384^3 emulated SGEMM; sampled rows x
+    # columns against the oracle, which needs only those rows/columns of the
+    # scaled integers plus full-matrix row/column maxima of Cbar.
+    m = n = k = size
     announce(f"full size {m}^3 N={N} {np.dtype(dtype).name}")
     A, B = gemm_inputs(m, n, k, phi=0.5, seed=0, dtype=dtype)
     got = host(oz.gemm(dev(A), dev(B), N))

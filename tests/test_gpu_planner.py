@@ -20,8 +20,9 @@ def slack(k):
 
 
 def effective(rc_or_ok, N, nmax):
-    """N, or nmax + 1 when the target is unreachable."""
-    ok = rc_or_ok is True or rc_or_ok == oz.OK
+    """N, or nmax + 1 when the target is unreachable (rc_or_ok: the oracle's
+    reachable flag, or the library's return code)."""
+    ok = rc_or_ok if isinstance(rc_or_ok, (bool, np.bool_)) else rc_or_ok == oz.OK
     return N if ok else nmax + 1
 
 
