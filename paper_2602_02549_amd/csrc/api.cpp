@@ -88,10 +88,28 @@ struct Layout {
   size_t rowbits, colbits, rmax, cmax, mu_p, nu_p, mu, nu, ef, flag, A, B, W, total;
 };
 
-Layout layout(int m, int n, int k, int N) {
+// Row padding of one problem's layout.  The residue products use 256x256
+// tiles when there are at least 512 of them (two per CU), which needs m and n
+// padded to 256; otherwise 128x128 tiles, and padding to 128 wastes less.
+int single_row_pad(int m, int n, int N) {
+  const int64_t t = (int64_t)rup((size_t)(m > 0 ? m : 1), 256) / 256 *
+                    ((int64_t)rup((size_t)(n > 0 ? n : 1), 256) / 256) * N;
+  return t >= 512 ? 256 : 128;
+}
+
+// In a batch, a problem may use 256x256 tiles only if padding it to 256
+// costs at most 1/8 more output area than padding to 128, and it has at
+// least 4 such tiles.
+int batch_row_pad(int m, int n) {
+  const int64_t a256 = (int64_t)rup((size_t)m, 256) * (int64_t)rup((size_t)n, 256);
+  const int64_t a128 = (int64_t)rup((size_t)m, 128) * (int64_t)rup((size_t)n, 128);
+  return (8 * a256 <= 9 * a128 && a256 >= 4 * 256 * 256) ? 256 : 128;
+}
+
+Layout layout(int m, int n, int k, int N, int pad) {
   Layout L;
-  L.mp = (int)rup((size_t)(m > 0 ? m : 1), kRowPad);
-  L.np = (int)rup((size_t)(n > 0 ? n : 1), kRowPad);
+  L.mp = (int)rup((size_t)(m > 0 ? m : 1), pad);
+  L.np = (int)rup((size_t)(n > 0 ? n : 1), pad);
   L.kp = (int)rup((size_t)(k > 0 ? k : 1), kKPad);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -316,7 +334,7 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
   }
   CrtConsts cc;
   if ((rc = get_consts(N, b, &cc))) return rc;
-  Layout L = layout(m, n, k, N);
+  Layout L = layout(m, n, k, N, single_row_pad(m, n, N));
   char* ws;
   int* status;
   if ((rc = get_workspace(L.total, &ws, &status))) return rc;
@@ -430,7 +448,8 @@ void build_table(const std::vector<ProbDesc>& D, int split, std::vector<char>* o
   std::vector<int> c((size_t)BS_COUNT * cnt);
   for (int p = 0; p < cnt; ++p) {
     const ProbDesc& d = D[p];
-    const bool big = (int64_t)(d.mp / 256) * (d.np / 256) >= split;
+    const bool big = d.mp % 256 == 0 && d.np % 256 == 0 &&
+                     (int64_t)(d.mp / 256) * (d.np / 256) >= split;
     int* cp = &c[(size_t)p * BS_COUNT];
     cp[BS_INIT] = group_init_blocks(d.mp, d.np);
     cp[BS_ABS_A] = cdiv_i(d.m, 256) * cdiv_i(d.k, 64);
@@ -576,7 +595,7 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
     if (m == 0 || n == 0 || k == 0) continue;
     act.push_back(p);
     off.push_back(total);
-    total += rup(layout(m, n, k, mnkN[4 * p + 3]).total, 256);
+    total += rup(layout(m, n, k, mnkN[4 * p + 3], batch_row_pad(m, n)).total, 256);
   }
   char* ws = nullptr;
   int* status = nullptr;
@@ -623,7 +642,7 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
     for (size_t q = 0; q < act.size(); ++q) {
       const int p = act[q];
       const int m = mnkN[4 * p], n = mnkN[4 * p + 1], k = mnkN[4 * p + 2], N = mnkN[4 * p + 3];
-      const Layout L = layout(m, n, k, N);
+      const Layout L = layout(m, n, k, N, batch_row_pad(m, n));
       char* w = ws + off[q];
       ProbDesc& d = D[q];
       d.m = m, d.n = n, d.k = k, d.N = N;
@@ -729,7 +748,7 @@ int ozaki2_set_stream(void* stream) {
 
 size_t ozaki2_workspace_bytes(int prec, int m, int n, int k, int N) {
   if ((prec != 64 && prec != 32) || m < 0 || n < 0 || k < 0 || N < 2 || N > kMaxModuli) return 0;
-  return layout(m, n, k, N).total;
+  return layout(m, n, k, N, single_row_pad(m, n, N)).total;
 }
 
 int ozaki2_set_workspace(void* dptr, size_t bytes) {

@@ -13,9 +13,11 @@
 //
 // Tiling: a 256-thread workgroup (4 waves as 2 x 2) computes a BX x BY tile;
 // each wave owns (BX/2) x (BY/2) as (BX/64) x (BY/64) blocks of 32 x 32
-// (accumulators live in AGPRs).  K advances 64 bytes per stage through four
-// LDS stage buffers used as two pairs: direct global->LDS copies fill one pair
-// (both halves of each 128-byte line) while the MFMAs consume the other.
+// (accumulators live in AGPRs for 256 x 256).  K advances in groups of 128
+// bytes through two LDS group buffers: direct global->LDS copies fill one
+// (every 128-byte line of an operand row requested as one unit) while the
+// MFMAs consume the other.  BF16 operands (the planner's lower bound of
+// |A||B|) run through the same loop, counting k in bytes.
 //
 // Workgroup order: the hardware deals workgroups round-robin to the 8 XCDs;
 // the linear id is remapped so each XCD works on a contiguous range of
@@ -79,46 +81,34 @@ __device__ inline void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((V & 0xF) | (((V >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-// Chunk swizzle of an LDS row (BK bytes of k): chunk c of row r is stored at
-// position c ^ swz(r).  For 64-byte rows (16 banks apart) the 16-byte
-// fragment reads of rows {a, a+4, a+8, a+12} (64 banks, 16 lanes per cycle)
-// and of the same-parity rows of any aligned 8 (32 banks, 8 lanes per cycle)
-// land in distinct bank groups; for 128-byte rows (32 banks apart) rows
-// r..r+15 do (64 banks).
-template <int BK>
-__device__ inline int swz(int r) {
-  return BK == 64 ? (((r >> 1) ^ (r >> 2)) & 3) : ((r >> 1) & 7);
-}
+// Chunk swizzle of an LDS row (128 bytes of k, 32 banks apart): chunk c of
+// row r is stored at position c ^ swz(r), so that the 16-byte fragment reads
+// of rows r..r+15 land in distinct bank groups (64 banks).
+__device__ inline int swz(int r) { return (r >> 1) & 7; }
 
-// Main loop structure: k advances in groups of 128 bytes.  BK = 64 keeps a
-// group as two 64-byte stage buffers, BK = 128 as one; either way two groups
-// (128 KB for a 256x256 tile) are resident: the copies of group g+1 (direct
-// global->LDS, every 128-byte line requested as one unit for BK = 128 or as
-// two back-to-back halves for BK = 64) run while the MFMAs consume group g.
-// Each buffer holds the X tile then the Y tile as rows of BK bytes.
-// `bid` is the workgroup's index among the `launched` workgroups of this
-// product (launched >= tiles_x * tiles_y * nz; the surplus exits at once).
-template <int BX, int BY, int BK, int EPI, bool BF16, int SLOTS = 0>
+// Main loop structure: k advances in groups of 128 bytes; two groups (128 KB
+// for a 256x256 tile) are resident in LDS.  The copies of group g+1 (direct
+// global->LDS, every 128-byte line requested as one unit) run while the
+// MFMAs consume group g.  A group buffer holds the X tile then the Y tile as
+// rows of 128 bytes.  `bid` is the workgroup's index among the `launched`
+// workgroups of this product (launched >= tiles_x * tiles_y * nz; the
+// surplus exits at once).
+template <int BX, int BY, int EPI, bool BF16>
 __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t sx,
-                                 const int8_t* __restrict__ Y, size_t sy, int tiles_x,
-                                 int tiles_y, int nz, int k_pad, const CrtConsts& cc,
-                                 int8_t* __restrict__ W, size_t sw, int ldw,
-                                 int* __restrict__ xmax, int* __restrict__ ymax, int bid,
-                                 int launched) {
-  static_assert(BK == 64 || BK == 128, "BK");
-  static_assert(SLOTS == 0 || (SLOTS == 5 && BK == 128), "half-group slots: 5, with BK = 128");
+                                          const int8_t* __restrict__ Y, size_t sy, int tiles_x,
+                                          int tiles_y, int nz, int k_pad, const CrtConsts& cc,
+                                          int8_t* __restrict__ W, size_t sw, int ldw,
+                                          int* __restrict__ xmax, int* __restrict__ ymax, int bid,
+                                          int launched) {
+  constexpr int BK = 128;                        // bytes of k per LDS row (one group)
   constexpr int WX = BX / 2, WY = BY / 2;
   constexpr int TX = WX / 32, TY = WY / 32;
   constexpr int CPR = BK / 16;                   // 16-byte chunks per LDS row
   constexpr int RPI = 1024 / BK;                 // rows per copy instruction
   constexpr int IX = BX / RPI / 4, IY = BY / RPI / 4;
-  constexpr int STAGE = (BX + BY) * BK;          // one stage buffer
-  constexpr int GROUP_BYTES = (BX + BY) * 128;   // one 128-k group
+  constexpr int GROUP_BYTES = (BX + BY) * BK;    // one 128-k group
   constexpr int GROUP = 8;
-  constexpr int XSLOT = BX * 128, YSLOT = BY * 128;  // one half-group (X or Y side)
-  constexpr int SLOT = XSLOT > YSLOT ? XSLOT : YSLOT;
-  constexpr int LDS_BYTES = SLOTS ? SLOTS * SLOT : 2 * GROUP_BYTES;
-  __shared__ __attribute__((aligned(1024))) int8_t lds[LDS_BYTES];
+  __shared__ __attribute__((aligned(1024))) int8_t lds[2 * GROUP_BYTES];
 
   // ---- workgroup -> (slice z, tile) ------------------------------------
   const int total = tiles_x * tiles_y * nz;
@@ -146,7 +136,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   // its share; lane l takes row RPI*q + l/CPR and stores LDS chunk l%CPR,
   // which holds k-chunk (l%CPR) ^ swz(row).
   const int lr = lane / CPR, slot = lane % CPR;
-  const int ch_e = (slot ^ swz<BK>(lr)) * 16, ch_o = (slot ^ swz<BK>(RPI + lr)) * 16;
+  const int ch_e = (slot ^ swz(lr)) * 16, ch_o = (slot ^ swz(RPI + lr)) * 16;
   const int8_t* xsrc = X + (size_t)z * sx + (size_t)(x0 + wave * IX * RPI + lr) * k_pad;
   const int8_t* ysrc = Y + (size_t)z * sy + (size_t)(y0 + wave * IY * RPI + lr) * k_pad;
   const size_t rowstep = (size_t)RPI * k_pad;
@@ -155,19 +145,13 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   auto issue_group = [&](int8_t* buf, int k0) {
     const uint32_t b = lds_addr(buf);
 #pragma unroll
-    for (int q = 0; q < IX; ++q) {
-      const int8_t* src = xsrc + q * rowstep + k0 + ((q & 1) ? ch_o : ch_e);
-      const uint32_t d = b + (uint32_t)((wave_u * IX + q) * 1024);
-      dma16(src, d);
-      if (BK == 64) dma16(src + 64, d + STAGE);
-    }
+    for (int q = 0; q < IX; ++q)
+      dma16(xsrc + q * rowstep + k0 + ((q & 1) ? ch_o : ch_e),
+            b + (uint32_t)((wave_u * IX + q) * 1024));
 #pragma unroll
-    for (int q = 0; q < IY; ++q) {
-      const int8_t* src = ysrc + q * rowstep + k0 + ((q & 1) ? ch_o : ch_e);
-      const uint32_t d = b + (uint32_t)(BX * BK + (wave_u * IY + q) * 1024);
-      dma16(src, d);
-      if (BK == 64) dma16(src + 64, d + STAGE);
-    }
+    for (int q = 0; q < IY; ++q)
+      dma16(ysrc + q * rowstep + k0 + ((q & 1) ? ch_o : ch_e),
+            b + (uint32_t)(BX * BK + (wave_u * IY + q) * 1024));
   };
 
   using AccT = typename std::conditional<BF16, v16f, v16i>::type;
@@ -184,21 +168,14 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   const int frow = lane & 31;
   int fo[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int c = (BK == 64 ? 2 * (j & 1) : 2 * j) + (lane >> 5);
-    fo[j] = (BK == 64 ? (j >> 1) * STAGE : 0) + frow * BK + ((c ^ swz<BK>(frow)) * 16);
-  }
-  auto load_frags2 = [&](const int8_t* xbuf, const int8_t* ybuf, int j, v4i (&a)[TX],
-                         v4i (&b)[TY]) {
+  for (int j = 0; j < 4; ++j) fo[j] = frow * BK + (((2 * j + (lane >> 5)) ^ swz(frow)) * 16);
+  auto load_frags = [&](const int8_t* buf, int j, v4i (&a)[TX], v4i (&b)[TY]) {
 #pragma unroll
     for (int tx = 0; tx < TX; ++tx)
-      a[tx] = *reinterpret_cast<const v4i*>(xbuf + (wx * WX + tx * 32) * BK + fo[j]);
+      a[tx] = *reinterpret_cast<const v4i*>(buf + (wx * WX + tx * 32) * BK + fo[j]);
 #pragma unroll
     for (int ty = 0; ty < TY; ++ty)
-      b[ty] = *reinterpret_cast<const v4i*>(ybuf + (wy * WY + ty * 32) * BK + fo[j]);
-  };
-  auto load_frags = [&](const int8_t* buf, int j, v4i (&a)[TX], v4i (&b)[TY]) {
-    load_frags2(buf, buf + BX * BK, j, a, b);
+      b[ty] = *reinterpret_cast<const v4i*>(buf + (BX + wy * WY + ty * 32) * BK + fo[j]);
   };
   auto mfmas = [&](const v4i (&a)[TX], const v4i (&b)[TY]) {
 #pragma unroll
@@ -212,93 +189,35 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
         else
           acc[tx][ty] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tx], b[ty], acc[tx][ty], 0, 0, 0);
   };
-  if constexpr (SLOTS == 5) {
-    // Five half-group slots: half-group h (h = 2g for the X side of group g,
-    // 2g+1 for its Y side) lives in slot h % 5.  At the top of iteration g
-    // the copies issued so far end with Y_g, X_{g+1}; each wave waits until
-    // only X_{g+1} may be outstanding (its own copies of group g have
-    // landed), then a barrier (everyone's have, and every wave has finished
-    // reading group g-1).  The two slots of group g-1 then receive Y_{g+1}
-    // and X_{g+2}, so one and a half groups of copies are always queued
-    // behind the group being multiplied.
-    const int NG = k_pad / 128;
-    auto issue_x = [&](int g, int slot) {
-      const uint32_t b = lds_addr(lds + slot * SLOT);
-#pragma unroll
-      for (int q = 0; q < IX; ++q)
-        dma16(xsrc + q * rowstep + g * 128 + ((q & 1) ? ch_o : ch_e),
-              b + (uint32_t)((wave_u * IX + q) * 1024));
-    };
-    auto issue_y = [&](int g, int slot) {
-      const uint32_t b = lds_addr(lds + slot * SLOT);
-#pragma unroll
-      for (int q = 0; q < IY; ++q)
-        dma16(ysrc + q * rowstep + g * 128 + ((q & 1) ? ch_o : ch_e),
-              b + (uint32_t)((wave_u * IY + q) * 1024));
-    };
-    auto add5 = [](int a, int d) { return a + d >= 5 ? a + d - 5 : a + d; };
-    issue_x(0, 0);
-    issue_y(0, 1);
-    if (NG > 1) issue_x(1, 2);
-    int xs = 0;                              // slot of X_g; Y_g is in xs + 1
-    for (int gi = 0; gi < NG; ++gi) {
-      const int ys = add5(xs, 1);
-      const int8_t* const xb = lds + xs * SLOT;
-      const int8_t* const yb = lds + ys * SLOT;
-      if (gi + 1 < NG)
-        wait_vmcnt<IX>();
-      else
-        wait_vmcnt<0>();
-      __builtin_amdgcn_s_barrier();
-      v4i a0[TX], b0[TY], a1[TX], b1[TY];
-      load_frags2(xb, yb, 0, a0, b0);
-      if (gi + 1 < NG) issue_y(gi + 1, add5(xs, 3));
-      if (gi + 2 < NG) issue_x(gi + 2, add5(xs, 4));
-      load_frags2(xb, yb, 1, a1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-      mfmas(a0, b0);
-      __builtin_amdgcn_sched_barrier(0);
-      load_frags2(xb, yb, 2, a0, b0);
-      __builtin_amdgcn_sched_barrier(0);
-      mfmas(a1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-      load_frags2(xb, yb, 3, a1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-      mfmas(a0, b0);
-      mfmas(a1, b1);
-      xs = add5(xs, 2);
-    }
-  } else {
-    // k_pad is a multiple of 128.  Group gi lives in half gi % 2 of the LDS; it
-    // is issued while group gi-1 is consumed and waited for (all copies done +
-    // barrier) before use, which also certifies that every wave has finished
-    // reading group gi-1.  No branch encloses an MFMA, so the accumulators stay
-    // in place across iterations.
-    const int NG = k_pad / 128;
-    issue_group(lds, 0);
-    for (int gi = 0; gi < NG; ++gi) {
-      int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
-      wait_vmcnt<0>();
-      __builtin_amdgcn_s_barrier();
-      v4i a0[TX], b0[TY], a1[TX], b1[TY];
-      // the first fragment reads go out before the next group's copies are
-      // issued, so their LDS latency overlaps the copy issue
-      load_frags(buf, 0, a0, b0);
-      if (gi + 1 < NG) issue_group(lds + ((gi + 1) & 1) * GROUP_BYTES, (gi + 1) * 128);
-      load_frags(buf, 1, a1, b1);
-      __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the MFMAs
-      mfmas(a0, b0);
-      __builtin_amdgcn_sched_barrier(0);
-      load_frags(buf, 2, a0, b0);
-      __builtin_amdgcn_sched_barrier(0);
-      mfmas(a1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-      load_frags(buf, 3, a1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-      mfmas(a0, b0);
-      mfmas(a1, b1);
-    }
 
+  // k_pad is a multiple of 128.  Group gi lives in half gi % 2 of the LDS; it
+  // is issued while group gi-1 is consumed and waited for (all copies done +
+  // barrier) before use, which also certifies that every wave has finished
+  // reading group gi-1.  No branch encloses an MFMA, so the accumulators stay
+  // in place across iterations.
+  const int NG = k_pad / 128;
+  issue_group(lds, 0);
+  for (int gi = 0; gi < NG; ++gi) {
+    int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    v4i a0[TX], b0[TY], a1[TX], b1[TY];
+    // the first fragment reads go out before the next group's copies are
+    // issued, so their LDS latency overlaps the copy issue
+    load_frags(buf, 0, a0, b0);
+    if (gi + 1 < NG) issue_group(lds + ((gi + 1) & 1) * GROUP_BYTES, (gi + 1) * 128);
+    load_frags(buf, 1, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the MFMAs
+    mfmas(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_frags(buf, 2, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_frags(buf, 3, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas(a0, b0);
+    mfmas(a1, b1);
   }
 
   const int xb = x0 + wx * WX, yb = y0 + wy * WY;
@@ -363,15 +282,15 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   }
 }
 
-template <int BX, int BY, int BK, int OCC, int EPI, bool BF16 = false, int SLOTS = 0>
+template <int BX, int BY, int OCC, int EPI, bool BF16 = false>
 __global__ __launch_bounds__(256, OCC) void k_gemm_i8(const int8_t* __restrict__ X, size_t sx,
                                                     const int8_t* __restrict__ Y, size_t sy,
                                                     int tiles_x, int tiles_y, int nz, int k_pad,
                                                     CrtConsts cc, int8_t* __restrict__ W, size_t sw,
                                                     int ldw, int* __restrict__ xmax,
                                                     int* __restrict__ ymax) {
-  gemm_body<BX, BY, BK, EPI, BF16, SLOTS>(X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw,
-                                          ldw, xmax, ymax, blockIdx.x, gridDim.x);
+  gemm_body<BX, BY, EPI, BF16>(X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax,
+                               ymax, blockIdx.x, gridDim.x);
 }
 
 // Grouped: the scaling product (EPI 1) or the N residue products (EPI 0) of
@@ -384,29 +303,27 @@ __global__ __launch_bounds__(256, OCC) void kg_gemm(const ProbDesc* __restrict__
   const BlockRef e = map[blockIdx.x];
   const ProbDesc& d = P[e.x];
   const int nz = EPI == 0 ? d.N : 1;
-  gemm_body<BX, BY, 128, EPI, false>(d.As, EPI == 0 ? (size_t)d.mp * d.kp : 0, d.Bs,
-                                     EPI == 0 ? (size_t)d.np * d.kp : 0, d.mp / BX, d.np / BY, nz,
-                                     d.kp, ctab[d.N], d.W, (size_t)d.np * d.mp, d.mp, d.rmax,
-                                     d.cmax, e.y, group_gemm_blocks(d.mp, d.np, BX, nz));
+  gemm_body<BX, BY, EPI, false>(d.As, EPI == 0 ? (size_t)d.mp * d.kp : 0, d.Bs,
+                                EPI == 0 ? (size_t)d.np * d.kp : 0, d.mp / BX, d.np / BY, nz, d.kp,
+                                ctab[d.N], d.W, (size_t)d.np * d.mp, d.mp, d.rmax, d.cmax, e.y,
+                                group_gemm_blocks(d.mp, d.np, BX, nz));
 }
 
-template <int BX, int BY, int BK, int OCC, int SLOTS = 0>
+template <int BX, int BY, int OCC>
 void launch_cfg(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                 int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
                 size_t sw, int ldw, int* xmax, int* ymax) {
   const int tiles_x = nx_pad / BX, tiles_y = ny_pad / BY;
   dim3 grid((unsigned)(tiles_x * tiles_y * nz));
   if (epi == 0)
-    hipLaunchKernelGGL((k_gemm_i8<BX, BY, BK, OCC, 0, false, SLOTS>), grid, dim3(256), 0, s, X,
-                       sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+    hipLaunchKernelGGL((k_gemm_i8<BX, BY, OCC, 0>), grid, dim3(256), 0, s, X, sx, Y, sy, tiles_x,
+                       tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
   else
-    hipLaunchKernelGGL((k_gemm_i8<BX, BY, BK, OCC, 1, false, SLOTS>), grid, dim3(256), 0, s, X,
-                       sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+    hipLaunchKernelGGL((k_gemm_i8<BX, BY, OCC, 1>), grid, dim3(256), 0, s, X, sx, Y, sy, tiles_x,
+                       tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
 }
 
-// Tile configuration: 0 = automatic; 1 = 256x256 (BK 128), 2 = 128x128
-// (BK 128), 3 = 256x256 (BK 64), 4 = 128x128 (BK 64), 5 = 256x256 with five
-// half-group slots, 6 = 128x128 with five half-group slots (environment
+// Tile configuration: 0 = automatic; 1 = 256x256, 2 = 128x128 (environment
 // variable OZAKI2_GEMM_CFG, read once; a tuning aid).
 int forced_cfg() {
   static int v = [] {
@@ -443,12 +360,12 @@ void launch_gemm_bf16_store(hipStream_t s, const uint16_t* X, const uint16_t* Y,
   const long t256 = (long)(nx_pad / 256) * (ny_pad / 256);
   if (nx_pad % 256 == 0 && ny_pad % 256 == 0 && t256 >= 512) {
     const int tiles_x = nx_pad / 256, tiles_y = ny_pad / 256;
-    hipLaunchKernelGGL((k_gemm_i8<256, 256, 128, 1, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
+    hipLaunchKernelGGL((k_gemm_i8<256, 256, 1, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
                        dim3(256), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0, tiles_x, tiles_y,
                        1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
   } else {
     const int tiles_x = nx_pad / 128, tiles_y = ny_pad / 128;
-    hipLaunchKernelGGL((k_gemm_i8<128, 128, 128, 2, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
+    hipLaunchKernelGGL((k_gemm_i8<128, 128, 2, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
                        dim3(256), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0, tiles_x, tiles_y,
                        1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
   }
@@ -463,33 +380,14 @@ void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const in
   int cfg = forced_cfg();
   const long t256 = (long)(nx_pad / 256) * (ny_pad / 256) * nz;
   const bool fits256 = nx_pad % 256 == 0 && ny_pad % 256 == 0;
-  if (cfg < 1 || cfg > 6) cfg = (fits256 && t256 >= 512) ? 1 : 2;
-  if ((cfg == 1 || cfg == 3 || cfg == 5) && !fits256) cfg = 2;
-  switch (cfg) {
-    case 1:
-      launch_cfg<256, 256, 128, 1>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw,
-                                   ldw, xmax, ymax);
-      break;
-    case 3:
-      launch_cfg<256, 256, 64, 1>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw,
-                                  xmax, ymax);
-      break;
-    case 5:
-      launch_cfg<256, 256, 128, 1, 5>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw,
-                                      ldw, xmax, ymax);
-      break;
-    case 6:
-      launch_cfg<128, 128, 128, 2, 5>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw,
-                                      ldw, xmax, ymax);
-      break;
-    case 4:
-      launch_cfg<128, 128, 64, 2>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw,
-                                  xmax, ymax);
-      break;
-    default:
-      launch_cfg<128, 128, 128, 2>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw,
-                                   ldw, xmax, ymax);
-  }
+  if (cfg != 1 && cfg != 2) cfg = (fits256 && t256 >= 512) ? 1 : 2;
+  if (cfg == 1 && !fits256) cfg = 2;
+  if (cfg == 1)
+    launch_cfg<256, 256, 1>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw, xmax,
+                            ymax);
+  else
+    launch_cfg<128, 128, 2>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw, xmax,
+                            ymax);
 }
 
 }  // namespace oz2
