@@ -454,8 +454,8 @@ void build_table(const std::vector<ProbDesc>& D, int split, std::vector<char>* o
     cp[BS_INIT] = group_init_blocks(d.mp, d.np);
     cp[BS_ABS_A] = cdiv_i(d.m, 256) * cdiv_i(d.k, 64);
     cp[BS_ABS_B] = d.n * cdiv_i(d.k, 2048);
-    cp[BS_SL_A] = (d.kp / 64) * (d.mp / 64);
-    cp[BS_SL_B] = (d.kp / 64) * (d.np / 64);
+    cp[BS_SL_A] = (d.kp / 128) * (d.mp / 32);
+    cp[BS_SL_B] = (d.kp / 128) * (d.np / 32);
     cp[BS_GS_BIG] = big ? group_gemm_blocks(d.mp, d.np, 256, 1) : 0;
     cp[BS_GS_SMALL] = big ? 0 : group_gemm_blocks(d.mp, d.np, 128, 1);
     cp[BS_SHIFTS] = cdiv_i(d.m + d.n, 256);

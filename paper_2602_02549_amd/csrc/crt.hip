@@ -36,14 +36,25 @@ __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw
   double c1[R], c2[R];
 #pragma unroll
   for (int e = 0; e < R; ++e) c1[e] = c2[e] = 0.0;
-  for (int l = 0; l < cc.N; ++l) {
-    const uint64_t wv = *reinterpret_cast<const WordT*>(wp + (size_t)l * sw);
-    const double s1 = cc.s1[l], s2 = cc.s2[l];
+  // Moduli in groups of 4, loads first (clamped to the last slice); a modulus
+  // past N gets weight 0, and fma(0, w, c) = c, so the l-ordered fma chains
+  // are unchanged.
+  for (int l0 = 0; l0 < cc.N; l0 += 4) {
+    uint64_t wv[4];
 #pragma unroll
-    for (int e = 0; e < R; ++e) {
-      const double w = (double)(int8_t)(wv >> (8 * e));
-      c1[e] = fma(s1, w, c1[e]);
-      if (sizeof(T) == 8) c2[e] = fma(s2, w, c2[e]);
+    for (int u = 0; u < 4; ++u)
+      wv[u] = *reinterpret_cast<const WordT*>(wp + (size_t)min(l0 + u, cc.N - 1) * sw);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int l = min(l0 + u, cc.N - 1);
+      const bool in = l0 + u < cc.N;
+      const double s1 = in ? cc.s1[l] : 0.0, s2 = in ? cc.s2[l] : 0.0;
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        const double w = (double)(int8_t)(wv[u] >> (8 * e));
+        c1[e] = fma(s1, w, c1[e]);
+        if (sizeof(T) == 8) c2[e] = fma(s2, w, c2[e]);
+      }
     }
   }
   const bool bad = *flag != 0;

@@ -35,20 +35,28 @@ __global__ void k_init(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pa
 
 // A column-major (m x k): one thread per row, a workgroup covers 256 rows and
 // a chunk of 64 columns (workgroup bx + gx * by); consecutive threads read
-// consecutive rows.
+// consecutive rows.  Loads go out 16 at a time from clamped (always valid)
+// addresses; a repeated element does not change a maximum.
 template <typename T>
 __device__ __forceinline__ void absmax_rows_body(const T* __restrict__ A, int lda, int m, int k,
                                         uint64_t* __restrict__ rowbits, int* __restrict__ flag,
                                         int bx, int by) {
   const int i = bx * 256 + threadIdx.x;
-  if (i >= m) return;
-  const int h0 = by * 64, h1 = min(h0 + 64, k);
+  const T* a = A + min(i, m - 1);
+  const int h0 = by * 64;
   uint64_t mx = 0;
-  for (int h = h0; h < h1; ++h) {
-    const double v = fabs((double)A[i + (size_t)h * lda]);
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    mx = b > mx ? b : mx;
+#pragma unroll
+  for (int q0 = 0; q0 < 64; q0 += 16) {
+    T x[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[u] = a[(size_t)min(h0 + q0 + u, k - 1) * lda];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const uint64_t b = (uint64_t)__double_as_longlong(fabs((double)x[u]));
+      mx = b > mx ? b : mx;
+    }
   }
+  if (i >= m) return;
   if ((mx & kExpMask) == kExpMask) atomicOr(flag, 1);
   if (mx) atomicMax((unsigned long long*)&rowbits[i], (unsigned long long)mx);
 }
@@ -69,12 +77,13 @@ __device__ __forceinline__ void absmax_cols_body(const T* __restrict__ B, int ld
   const int h0 = chunk * 2048;
   const T* col = B + (size_t)j * ldb;
   uint64_t mx = 0;
+  T x[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) x[q] = col[min(h0 + (int)threadIdx.x + 256 * q, k - 1)];
+#pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int h = h0 + threadIdx.x + 256 * q;
-    if (h < k) {
-      const uint64_t b = (uint64_t)__double_as_longlong(fabs((double)col[h]));
-      mx = b > mx ? b : mx;
-    }
+    const uint64_t b = (uint64_t)__double_as_longlong(fabs((double)x[q]));
+    mx = b > mx ? b : mx;
   }
   for (int off = 32; off >= 1; off >>= 1) {
     const unsigned long long o = __shfl_xor((unsigned long long)mx, off);

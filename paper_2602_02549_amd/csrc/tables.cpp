@@ -267,6 +267,10 @@ bool build_consts(int N, int b, CrtConsts* out) {
   }
   if (steps > 4) return false;   // the residue kernels instantiate 1..4 steps
   cc.nsteps = steps;
+  // 32-bit limbs of |A'| < 2^B: two limbs keep the upper one within 2^31 for
+  // B <= 63, three for B <= 95; for B <= 50 one reduction step is cheaper.
+  const int B = 6 + (int)std::floor((double)cc.Pprime);
+  cc.nlimbs = B <= 50 ? 0 : (B <= 63 ? 2 : (B <= 95 ? 3 : 0));
   *out = cc;
   return true;
 }
