@@ -453,7 +453,7 @@ void build_table(const std::vector<ProbDesc>& D, int split, std::vector<char>* o
     int* cp = &c[(size_t)p * BS_COUNT];
     cp[BS_INIT] = group_init_blocks(d.mp, d.np);
     cp[BS_ABS_A] = cdiv_i(d.m, 256) * cdiv_i(d.k, 64);
-    cp[BS_ABS_B] = d.n * cdiv_i(d.k, 2048);
+    cp[BS_ABS_B] = absmax_cols_blocks(d.n);
     cp[BS_SL_A] = (d.kp / 128) * (d.mp / 32);
     cp[BS_SL_B] = (d.kp / 128) * (d.np / 32);
     cp[BS_GS_BIG] = big ? group_gemm_blocks(d.mp, d.np, 256, 1) : 0;
@@ -461,7 +461,7 @@ void build_table(const std::vector<ProbDesc>& D, int split, std::vector<char>* o
     cp[BS_SHIFTS] = cdiv_i(d.m + d.n, 256);
     cp[BS_GR_BIG] = big ? group_gemm_blocks(d.mp, d.np, 256, d.N) : 0;
     cp[BS_GR_SMALL] = big ? 0 : group_gemm_blocks(d.mp, d.np, 128, d.N);
-    cp[BS_CRT] = cdiv_i(d.m, 256 * kCrtRows) * d.n;
+    cp[BS_CRT] = (int)crt_blocks(d.m, d.n);
   }
   size_t off = rup(sizeof(ProbDesc) * cnt, 256);
   for (int sl = 0; sl < BS_COUNT; ++sl) {

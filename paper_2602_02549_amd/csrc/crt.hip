@@ -21,17 +21,22 @@ namespace {
 // One thread handles R consecutive rows i of one column j: one R-byte load
 // per modulus (64 R contiguous bytes per wave) and, when C is aligned for it,
 // 2-element vector stores.  The grouped kernel uses R = kCrtRows.
+// Thread g (g = 0 .. ceil(m/R) n - 1) takes row chunk g % ceil(m/R) of column
+// g / ceil(m/R): consecutive threads walk down a column and continue in the
+// next, so small-m problems keep every lane busy.
 template <typename T, int R>
 __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw, int ldw,
                                 const int* __restrict__ mu, const int* __restrict__ nu, int m,
-                                const CrtConsts& cc, const int* __restrict__ flag,
-                                T* __restrict__ C, int ldc, int j, int iblock) {
+                                int n, const CrtConsts& cc, const int* __restrict__ flag,
+                                T* __restrict__ C, int ldc, int64_t g) {
   static_assert(R == 2 || R == 4 || R == 8, "rows per thread");
   typedef typename std::conditional<R == 2, uint16_t,
                                     typename std::conditional<R == 4, uint32_t, uint64_t>::type>::type
       WordT;
-  const int i0 = (iblock * 256 + threadIdx.x) * R;
-  if (i0 >= m) return;
+  const int chunks = cdiv_i(m, R);
+  const int j = (int)(g / chunks);
+  if (j >= n) return;
+  const int i0 = (int)(g - (int64_t)j * chunks) * R;
   const int8_t* wp = W + (size_t)j * ldw + i0;
   double c1[R], c2[R];
 #pragma unroll
@@ -100,10 +105,10 @@ __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw
 template <typename T, int R>
 __global__ __launch_bounds__(256) void k_crt(const int8_t* __restrict__ W, size_t sw, int ldw,
                                              const int* __restrict__ mu, const int* __restrict__ nu,
-                                             int m, int n, int iblocks, CrtConsts cc,
+                                             int m, int n, CrtConsts cc,
                                              const int* __restrict__ flag, T* __restrict__ C, int ldc) {
-  crt_body<T, R>(W, sw, ldw, mu, nu, m, cc, flag, C, ldc, blockIdx.x / iblocks,
-                 blockIdx.x % iblocks);
+  crt_body<T, R>(W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc,
+                 (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 template <typename T>
@@ -112,11 +117,8 @@ __global__ __launch_bounds__(256) void kg_crt(const ProbDesc* __restrict__ P,
                                               const CrtConsts* __restrict__ ctab) {
   const BlockRef e = map[blockIdx.x];
   const ProbDesc& d = P[e.x];
-  const int lid = e.y;
-  const int iblocks = cdiv_i(d.m, 256 * kCrtRows);
-  crt_body<T, kCrtRows>(d.W, (size_t)d.np * d.mp, d.mp, d.mu, d.nu, d.m, ctab[d.N], d.flag,
-                        (T*)d.C, d.ldc,
-              lid / iblocks, lid % iblocks);
+  crt_body<T, kCrtRows>(d.W, (size_t)d.np * d.mp, d.mp, d.mu, d.nu, d.m, d.n, ctab[d.N], d.flag,
+                        (T*)d.C, d.ldc, (int64_t)e.y * 256 + threadIdx.x);
 }
 
 // Any problem's non-finite flag sets the sticky status word.
@@ -172,9 +174,9 @@ int crt_rows() {
 template <typename T, int R>
 void launch_crt_t(hipStream_t s, const int8_t* W, size_t sw, int ldw, const int* mu, const int* nu,
                   int m, int n, const CrtConsts& cc, const int* flag, void* C, int ldc) {
-  const int iblocks = cdiv_i(m, 256 * R);
-  hipLaunchKernelGGL((k_crt<T, R>), dim3((unsigned)iblocks * (unsigned)n), dim3(256), 0, s, W, sw,
-                     ldw, mu, nu, m, n, iblocks, cc, flag, (T*)C, ldc);
+  const int64_t blocks = ((int64_t)cdiv_i(m, R) * n + 255) / 256;
+  hipLaunchKernelGGL((k_crt<T, R>), dim3((unsigned)blocks), dim3(256), 0, s, W, sw, ldw, mu, nu, m,
+                     n, cc, flag, (T*)C, ldc);
 }
 
 template <typename T>

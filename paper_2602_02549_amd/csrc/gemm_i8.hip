@@ -42,14 +42,19 @@ typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
 
 constexpr int kXcds = 8;
 
-// mod(x, p) of an INT32 product as an INT8 value (Section 1.2).  For odd p
-// the FP64 quotient x * (1/p) is within 2^-25 of x/p, which is never within
-// 1/(2p) of a half-integer, so rint gives round(x/p) exactly.  For p = 256
-// the low byte is the two's-complement wrap of Section 3.1.
-__device__ inline int mod_i32(int x, int p, double pinv) {
-  if (p == 256) return (int)(int8_t)(x & 0xFF);
-  const double q = rint((double)x * pinv);
-  return x - (int)q * p;
+// mod(x, p) of an INT32 product as an INT8 value (Section 1.2), odd p: the
+// FP64 quotient x * (1/p) is within 2^-25 of x/p, which is never within
+// 1/(2p) of a half-integer, so rint gives round(x/p) exactly and one fma
+// gives x - round(x/p) p exactly.  (p = 256 takes the low byte, the
+// two's-complement wrap of Section 3.1, in the caller.)
+__device__ inline int mod_odd(int x, double p, double pinv) {
+  const double xd = (double)x;
+  return (int)fma(-rint(xd * pinv), p, xd);
+}
+
+__device__ inline uint32_t pack_bytes(int a, int b, int c, int d) {
+  return (uint32_t)(a & 0xFF) | ((uint32_t)(b & 0xFF) << 8) | ((uint32_t)(c & 0xFF) << 16) |
+         ((uint32_t)(d & 0xFF) << 24);
 }
 
 typedef __attribute__((address_space(3))) int8_t lds_i8_t;
@@ -137,20 +142,21 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   // which holds k-chunk (l%CPR) ^ swz(row).
   const int lr = lane / CPR, slot = lane % CPR;
   const int ch_e = (slot ^ swz(lr)) * 16, ch_o = (slot ^ swz(RPI + lr)) * 16;
-  const int8_t* xsrc = X + (size_t)z * sx + (size_t)(x0 + wave * IX * RPI + lr) * k_pad;
-  const int8_t* ysrc = Y + (size_t)z * sy + (size_t)(y0 + wave * IY * RPI + lr) * k_pad;
+  const int8_t* xsrc = X + (size_t)(x0 + wave * IX * RPI + lr) * k_pad;
+  const int8_t* ysrc = Y + (size_t)(y0 + wave * IY * RPI + lr) * k_pad;
   const size_t rowstep = (size_t)RPI * k_pad;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
 
-  auto issue_group = [&](int8_t* buf, int k0) {
+  auto issue_group = [&](int8_t* buf, int z, int k0) {
     const uint32_t b = lds_addr(buf);
+    const int8_t* xs = xsrc + (size_t)z * sx + k0;
+    const int8_t* ys = ysrc + (size_t)z * sy + k0;
 #pragma unroll
     for (int q = 0; q < IX; ++q)
-      dma16(xsrc + q * rowstep + k0 + ((q & 1) ? ch_o : ch_e),
-            b + (uint32_t)((wave_u * IX + q) * 1024));
+      dma16(xs + q * rowstep + ((q & 1) ? ch_o : ch_e), b + (uint32_t)((wave_u * IX + q) * 1024));
 #pragma unroll
     for (int q = 0; q < IY; ++q)
-      dma16(ysrc + q * rowstep + k0 + ((q & 1) ? ch_o : ch_e),
+      dma16(ys + q * rowstep + ((q & 1) ? ch_o : ch_e),
             b + (uint32_t)(BX * BK + (wave_u * IY + q) * 1024));
   };
 
@@ -190,13 +196,106 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
           acc[tx][ty] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tx], b[ty], acc[tx][ty], 0, 0, 0);
   };
 
+  const int xb = x0 + wx * WX, yb = y0 + wy * WY;
+  // Epilogue (EPI 0: mod p_z into W_z; EPI 1: maxima; EPI 2: store).
+  auto finish = [&]() {
+    if constexpr (EPI == 2) {
+      // FP32 accumulators stored column-major: S[y][x], 4 consecutive x per lane
+      float* S = reinterpret_cast<float*>(W);
+#pragma unroll
+      for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+        for (int ty = 0; ty < TY; ++ty)
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const int x = xb + tx * 32 + 8 * r4 + 4 * (lane >> 5);
+            const int y = yb + ty * 32 + (lane & 31);
+            *reinterpret_cast<float4*>(S + (size_t)y * ldw + x) =
+                make_float4((float)acc[tx][ty][4 * r4 + 0], (float)acc[tx][ty][4 * r4 + 1],
+                            (float)acc[tx][ty][4 * r4 + 2], (float)acc[tx][ty][4 * r4 + 3]);
+          }
+    } else if constexpr (EPI == 0) {
+      const int p = cc.p[z];
+      int8_t* Wz = W + (size_t)z * sw;
+      // Per 32 x 32 block, lane l holds rows {0-3, 8-11, 16-19, 24-27} + 4 (l/32)
+      // of column l%32, packed as 4 dwords R0..R3.  Swapping R0<->R2 and R1<->R3
+      // between lanes l and l+32 (v_permlane32_swap) leaves rows 0-15 in lane l
+      // and rows 16-31 in lane l+32, each stored as one 16-byte write.
+      auto store_block = [&](int tx, int ty, uint32_t R0, uint32_t R1, uint32_t R2, uint32_t R3) {
+        const auto s02 = __builtin_amdgcn_permlane32_swap(R0, R2, false, false);
+        const auto s13 = __builtin_amdgcn_permlane32_swap(R1, R3, false, false);
+        const int x = xb + tx * 32 + 16 * (lane >> 5);
+        const int y = yb + ty * 32 + (lane & 31);
+        uint4 v;
+        v.x = s02[0];
+        v.y = s02[1];
+        v.z = s13[0];
+        v.w = s13[1];
+        *reinterpret_cast<uint4*>(Wz + (size_t)y * ldw + x) = v;
+      };
+      // The modulus is uniform: one branch for the whole tile.
+      if (p == 256) {
+#pragma unroll
+        for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+          for (int ty = 0; ty < TY; ++ty) {
+            uint32_t R[4];
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4)
+              R[r4] = pack_bytes(acc[tx][ty][4 * r4 + 0], acc[tx][ty][4 * r4 + 1],
+                                 acc[tx][ty][4 * r4 + 2], acc[tx][ty][4 * r4 + 3]);
+            store_block(tx, ty, R[0], R[1], R[2], R[3]);
+          }
+      } else {
+        const double pd = (double)p, pinv = cc.pinv[z];
+#pragma unroll
+        for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+          for (int ty = 0; ty < TY; ++ty) {
+            uint32_t R[4];
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4)
+              R[r4] = pack_bytes(mod_odd(acc[tx][ty][4 * r4 + 0], pd, pinv),
+                                 mod_odd(acc[tx][ty][4 * r4 + 1], pd, pinv),
+                                 mod_odd(acc[tx][ty][4 * r4 + 2], pd, pinv),
+                                 mod_odd(acc[tx][ty][4 * r4 + 3], pd, pinv));
+            store_block(tx, ty, R[0], R[1], R[2], R[3]);
+          }
+      }
+    } else if constexpr (EPI == 1) {
+      // max over x for each y
+#pragma unroll
+      for (int ty = 0; ty < TY; ++ty) {
+        int mv = 0;
+#pragma unroll
+        for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) mv = max(mv, acc[tx][ty][r]);
+        mv = max(mv, __shfl_xor(mv, 32));
+        if (lane < 32) atomicMax(&ymax[yb + ty * 32 + lane], mv);
+      }
+      // max over y for each x
+#pragma unroll
+      for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          int mv = 0;
+#pragma unroll
+          for (int ty = 0; ty < TY; ++ty) mv = max(mv, acc[tx][ty][r]);
+#pragma unroll
+          for (int off = 16; off >= 1; off >>= 1) mv = max(mv, __shfl_xor(mv, off));
+          if ((lane & 31) == 0)
+            atomicMax(&xmax[xb + tx * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)], mv);
+        }
+    }  };
+
   // k_pad is a multiple of 128.  Group gi lives in half gi % 2 of the LDS; it
   // is issued while group gi-1 is consumed and waited for (all copies done +
   // barrier) before use, which also certifies that every wave has finished
   // reading group gi-1.  No branch encloses an MFMA, so the accumulators stay
   // in place across iterations.
   const int NG = k_pad / 128;
-  issue_group(lds, 0);
+  issue_group(lds, z, 0);
   for (int gi = 0; gi < NG; ++gi) {
     int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
     wait_vmcnt<0>();
@@ -205,7 +304,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
     // the first fragment reads go out before the next group's copies are
     // issued, so their LDS latency overlaps the copy issue
     load_frags(buf, 0, a0, b0);
-    if (gi + 1 < NG) issue_group(lds + ((gi + 1) & 1) * GROUP_BYTES, (gi + 1) * 128);
+    if (gi + 1 < NG) issue_group(lds + ((gi + 1) & 1) * GROUP_BYTES, z, (gi + 1) * 128);
     load_frags(buf, 1, a1, b1);
     __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the MFMAs
     mfmas(a0, b0);
@@ -219,67 +318,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
     mfmas(a0, b0);
     mfmas(a1, b1);
   }
-
-  const int xb = x0 + wx * WX, yb = y0 + wy * WY;
-  if constexpr (EPI == 2) {
-    // FP32 accumulators stored column-major: S[y][x], 4 consecutive x per lane
-    float* S = reinterpret_cast<float*>(W);
-#pragma unroll
-    for (int tx = 0; tx < TX; ++tx)
-#pragma unroll
-      for (int ty = 0; ty < TY; ++ty)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          const int x = xb + tx * 32 + 8 * r4 + 4 * (lane >> 5);
-          const int y = yb + ty * 32 + (lane & 31);
-          *reinterpret_cast<float4*>(S + (size_t)y * ldw + x) =
-              make_float4((float)acc[tx][ty][4 * r4 + 0], (float)acc[tx][ty][4 * r4 + 1],
-                          (float)acc[tx][ty][4 * r4 + 2], (float)acc[tx][ty][4 * r4 + 3]);
-        }
-  } else if constexpr (EPI == 0) {
-    const int p = cc.p[z];
-    const double pinv = cc.pinv[z];
-    int8_t* Wz = W + (size_t)z * sw;
-#pragma unroll
-    for (int tx = 0; tx < TX; ++tx)
-#pragma unroll
-      for (int ty = 0; ty < TY; ++ty)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          const int x = xb + tx * 32 + 8 * r4 + 4 * (lane >> 5);
-          const int y = yb + ty * 32 + (lane & 31);
-          const uint32_t w = (uint32_t)(mod_i32(acc[tx][ty][4 * r4 + 0], p, pinv) & 0xFF) |
-                             ((uint32_t)(mod_i32(acc[tx][ty][4 * r4 + 1], p, pinv) & 0xFF) << 8) |
-                             ((uint32_t)(mod_i32(acc[tx][ty][4 * r4 + 2], p, pinv) & 0xFF) << 16) |
-                             ((uint32_t)(mod_i32(acc[tx][ty][4 * r4 + 3], p, pinv) & 0xFF) << 24);
-          *reinterpret_cast<uint32_t*>(Wz + (size_t)y * ldw + x) = w;
-        }
-  } else if constexpr (EPI == 1) {
-    // max over x for each y
-#pragma unroll
-    for (int ty = 0; ty < TY; ++ty) {
-      int mv = 0;
-#pragma unroll
-      for (int tx = 0; tx < TX; ++tx)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) mv = max(mv, acc[tx][ty][r]);
-      mv = max(mv, __shfl_xor(mv, 32));
-      if (lane < 32) atomicMax(&ymax[yb + ty * 32 + lane], mv);
-    }
-    // max over y for each x
-#pragma unroll
-    for (int tx = 0; tx < TX; ++tx)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        int mv = 0;
-#pragma unroll
-        for (int ty = 0; ty < TY; ++ty) mv = max(mv, acc[tx][ty][r]);
-#pragma unroll
-        for (int off = 16; off >= 1; off >>= 1) mv = max(mv, __shfl_xor(mv, off));
-        if ((lane & 31) == 0)
-          atomicMax(&xmax[xb + tx * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)], mv);
-      }
-  }
+  finish();
 }
 
 template <int BX, int BY, int OCC, int EPI, bool BF16 = false>

@@ -114,6 +114,12 @@ __host__ __device__ inline int group_init_blocks(int mp, int np) {
 __host__ __device__ inline int group_gemm_blocks(int mp, int np, int tile, int nz) {
   return ((mp / tile) * (np / tile) * nz + 7) / 8 * 8;
 }
+// Workgroups of the CRT (one thread per kCrtRows rows of one column) and of
+// the column abs-max (one wave per column, four per workgroup).
+__host__ __device__ inline int64_t crt_blocks(int m, int n) {
+  return ((int64_t)cdiv_i(m, kCrtRows) * n + 255) / 256;
+}
+__host__ __device__ inline int absmax_cols_blocks(int n) { return cdiv_i(n, 4); }
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (each defined next to its kernel)

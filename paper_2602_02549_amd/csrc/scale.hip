@@ -69,34 +69,35 @@ __global__ __launch_bounds__(256) void k_absmax_rows(const T* __restrict__ A, in
   absmax_rows_body<T>(A, lda, m, k, rowbits, flag, blockIdx.x % gx, blockIdx.x / gx);
 }
 
-// B column-major (k x n): one workgroup per (column j, chunk of 2048 rows).
+// B column-major (k x n): one wave per column j (four columns per
+// workgroup), 16 loads in flight per lane; the wave's maximum is stored
+// directly (the wave owns the column).
 template <typename T>
 __device__ __forceinline__ void absmax_cols_body(const T* __restrict__ B, int ldb, int k, int n,
                                         uint64_t* __restrict__ colbits, int* __restrict__ flag,
-                                        int j, int chunk) {
-  const int h0 = chunk * 2048;
+                                        int wg) {
+  const int lane = threadIdx.x & 63;
+  const int j = wg * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;   // whole wave
   const T* col = B + (size_t)j * ldb;
   uint64_t mx = 0;
-  T x[8];
+  for (int h0 = 0; h0 < k; h0 += 1024) {
+    T x[16];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) x[q] = col[min(h0 + (int)threadIdx.x + 256 * q, k - 1)];
+    for (int q = 0; q < 16; ++q) x[q] = col[min(h0 + lane + 64 * q, k - 1)];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const uint64_t b = (uint64_t)__double_as_longlong(fabs((double)x[q]));
-    mx = b > mx ? b : mx;
+    for (int q = 0; q < 16; ++q) {
+      const uint64_t b = (uint64_t)__double_as_longlong(fabs((double)x[q]));
+      mx = b > mx ? b : mx;
+    }
   }
   for (int off = 32; off >= 1; off >>= 1) {
     const unsigned long long o = __shfl_xor((unsigned long long)mx, off);
     mx = o > mx ? o : mx;
   }
-  __shared__ uint64_t red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t r = red[0];
-    for (int w = 1; w < 4; ++w) r = red[w] > r ? red[w] : r;
-    if ((r & kExpMask) == kExpMask) atomicOr(flag, 1);
-    if (r) atomicMax((unsigned long long*)&colbits[j], (unsigned long long)r);
+  if (lane == 0) {
+    if ((mx & kExpMask) == kExpMask) atomicOr(flag, 1);
+    colbits[j] = mx;
   }
 }
 
@@ -104,7 +105,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_absmax_cols(const T* __restrict__ B, int ldb, int k, int n,
                                                      uint64_t* __restrict__ colbits,
                                                      int* __restrict__ flag) {
-  absmax_cols_body<T>(B, ldb, k, n, colbits, flag, blockIdx.x % n, blockIdx.x / n);
+  absmax_cols_body<T>(B, ldb, k, n, colbits, flag, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(256) void kg_absmax_cols(const ProbDesc* __restrict
                                                       const BlockRef* __restrict__ map) {
   const BlockRef e = map[blockIdx.x];
   const ProbDesc& d = P[e.x];
-  absmax_cols_body<T>((const T*)d.B, d.ldb, d.k, d.n, d.colbits, d.flag, e.y % d.n, e.y / d.n);
+  absmax_cols_body<T>((const T*)d.B, d.ldb, d.k, d.n, d.colbits, d.flag, e.y);
 }
 
 __global__ __launch_bounds__(256) void kg_shifts(const ProbDesc* __restrict__ P,
@@ -302,7 +303,7 @@ void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, i
 
 void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,
                         uint64_t* colbits, int* flag) {
-  dim3 grid((unsigned)n * (unsigned)cdiv(k, 2048));
+  dim3 grid((unsigned)absmax_cols_blocks(n));
   if (pr == Prec::F64)
     hipLaunchKernelGGL(k_absmax_cols<double>, grid, dim3(256), 0, s, (const double*)B, ldb, k, n,
                        colbits, flag);
