@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--N", type=int, default=0, help="fix N instead of matching the native error")
     ap.add_argument("--samples", type=int, default=48, help="sampled rows (and columns) for errors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-size", type=int, default=320)
+    ap.add_argument("--cpu-size", type=int, default=400)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven 512-problem batched measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

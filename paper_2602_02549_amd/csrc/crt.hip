@@ -10,7 +10,6 @@
 // Every operation is an explicit fma / single rounding (built with
 // -ffp-contract=off), so the result is deterministic.
 #include <cstdint>
-#include <cstdlib>
 #include <type_traits>
 
 #include "ozaki2_internal.h"
@@ -18,9 +17,9 @@
 namespace oz2 {
 namespace {
 
-// One thread handles R consecutive rows i of one column j: one R-byte load
-// per modulus (64 R contiguous bytes per wave) and, when C is aligned for it,
-// 2-element vector stores.  The grouped kernel uses R = kCrtRows.
+// One thread handles R = kCrtRows consecutive rows i of one column j: one
+// R-byte load per modulus (64 R contiguous bytes per wave) and, when C is
+// aligned for it, 2-element vector stores.
 // Thread g (g = 0 .. ceil(m/R) n - 1) takes row chunk g % ceil(m/R) of column
 // g / ceil(m/R): consecutive threads walk down a column and continue in the
 // next, so small-m problems keep every lane busy.
@@ -160,33 +159,11 @@ void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const BlockRef*
 
 namespace {
 
-// Rows per thread of the single-problem CRT: kCrtRows, or 2 / 4 / 8 from the
-// environment variable OZAKI2_CRT_ROWS (read once; a tuning aid).
-int crt_rows() {
-  static int v = [] {
-    const char* e = getenv("OZAKI2_CRT_ROWS");
-    const int r = e ? atoi(e) : kCrtRows;
-    return (r == 2 || r == 4 || r == 8) ? r : kCrtRows;
-  }();
-  return v;
-}
-
-template <typename T, int R>
+template <typename T>
 void launch_crt_t(hipStream_t s, const int8_t* W, size_t sw, int ldw, const int* mu, const int* nu,
                   int m, int n, const CrtConsts& cc, const int* flag, void* C, int ldc) {
-  const int64_t blocks = ((int64_t)cdiv_i(m, R) * n + 255) / 256;
-  hipLaunchKernelGGL((k_crt<T, R>), dim3((unsigned)blocks), dim3(256), 0, s, W, sw, ldw, mu, nu, m,
-                     n, cc, flag, (T*)C, ldc);
-}
-
-template <typename T>
-void launch_crt_r(hipStream_t s, const int8_t* W, size_t sw, int ldw, const int* mu, const int* nu,
-                  int m, int n, const CrtConsts& cc, const int* flag, void* C, int ldc) {
-  switch (crt_rows()) {
-    case 4: launch_crt_t<T, 4>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc); break;
-    case 8: launch_crt_t<T, 8>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc); break;
-    default: launch_crt_t<T, 2>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc); break;
-  }
+  hipLaunchKernelGGL((k_crt<T, kCrtRows>), dim3((unsigned)crt_blocks(m, n)), dim3(256), 0, s, W, sw,
+                     ldw, mu, nu, m, n, cc, flag, (T*)C, ldc);
 }
 
 }  // namespace
@@ -195,9 +172,9 @@ void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, con
                 const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
                 int ldc) {
   if (pr == Prec::F64)
-    launch_crt_r<double>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
+    launch_crt_t<double>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
   else
-    launch_crt_r<float>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
+    launch_crt_t<float>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
 }
 
 void launch_fill_zero(hipStream_t s, Prec pr, void* C, int ldc, int m, int n) {
