@@ -45,7 +45,98 @@ def parse():
                     help="skip the uneven 512-problem batched measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device copy of MIB MiB first (HBM counter calibration)")
+    ap.add_argument("--extras", action="store_true",
+                    help="also measure the 4096^3 phi sweep (N from the bound at 1e-15) and the "
+                         "FP32 16384^3 emulated SGEMM against native SGEMM at matched error")
     return ap.parse_args()
+
+
+def _time_ms(torch, f, reps):
+    f()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extras_measurement(torch, oz) -> dict:
+    """The wide-exponent sweep (FP64 4096^3, phi in {0, 1, 2, 4}, N from the
+    bound at 1e-15: planning time, emulation time, observed error) and the
+    FP32 16384^3 emulated SGEMM against native SGEMM at matched error."""
+    from workload import gemm_inputs
+    from workload.reference import ExactSamples
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(4321)
+    out = {"phi_sweep_4096": [], "fp32_16384": {}}
+    torch.backends.cuda.matmul.allow_tf32 = False
+    n = 4096
+    for phi in (0.0, 1.0, 2.0, 4.0):
+        A, B = gemm_inputs(n, n, n, phi=phi, seed=0)
+        rows = np.sort(rng.choice(n, 24, replace=False))
+        cols = np.sort(rng.choice(n, 24, replace=False))
+        ex = ExactSamples(A, B, rows, cols)
+        dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        Acm, Bcm = oz.col_major(dA), oz.col_major(dB)
+        Ccm = torch.empty((n, n), dtype=torch.float64, device=dev)
+        oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        t0 = time.perf_counter()
+        rc, N = oz.ozaki2_required_moduli(64, n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, 1e-15)
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        oz.ozaki2_required_moduli(64, n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, 1e-15)
+        plan_ms = min(plan_ms, (time.perf_counter() - t0) * 1e3)
+
+        def emu():
+            r = oz.ozaki2_gemm(n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, Ccm.data_ptr(), n, N)
+            if r != oz.OK:
+                raise oz.Ozaki2Error("ozaki2_gemm", r)
+
+        ms = _time_ms(torch, emu, 5)
+        sub = Ccm.t()[torch.as_tensor(rows, device=dev)][:, torch.as_tensor(cols, device=dev)]
+        err = ex.rel_error(sub.cpu().numpy())
+        nat_ms = _time_ms(torch, lambda: torch.matmul(dA, dB), 5)
+        Cn = torch.matmul(dA, dB)
+        nat_err = ex.rel_error(Cn[torch.as_tensor(rows, device=dev)][:, torch.as_tensor(cols, device=dev)].cpu().numpy())
+        out["phi_sweep_4096"].append({
+            "phi": phi, "N": N, "reachable": rc == oz.OK, "plan_ms": round(plan_ms, 3),
+            "ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2),
+            "rel_err_sampled": err, "native_ms": round(nat_ms, 4), "native_rel_err_sampled": nat_err})
+        del dA, dB, Acm, Bcm, Ccm, Cn
+        torch.cuda.empty_cache()
+    # FP32 16384^3
+    n = 16384
+    A, B = gemm_inputs(n, n, n, phi=0.5, seed=0, dtype=np.float32)
+    rows = np.sort(rng.choice(n, 16, replace=False))
+    cols = np.sort(rng.choice(n, 16, replace=False))
+    ex = ExactSamples(A, B, rows, cols)
+    dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    del A, B
+    Acm, Bcm = oz.col_major(dA), oz.col_major(dB)
+    Ccm = torch.empty((n, n), dtype=torch.float32, device=dev)
+    ri, ci = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
+    nat_ms = _time_ms(torch, lambda: torch.matmul(dA, dB), 3)
+    nat_err = ex.rel_error(torch.matmul(dA, dB)[ri][:, ci].cpu().numpy())
+    res = {}
+    for N in (6, 7, 8):
+        def emu():
+            r = oz.ozaki2_sgemm(n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, Ccm.data_ptr(), n, N)
+            if r != oz.OK:
+                raise oz.Ozaki2Error("ozaki2_sgemm", r)
+
+        ms = _time_ms(torch, emu, 3)
+        err = ex.rel_error(Ccm.t()[ri][:, ci].cpu().numpy())
+        res[str(N)] = {"ms": round(ms, 3), "tflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2),
+                       "rel_err_sampled": err}
+    matched = next((int(k) for k, v in res.items() if v["rel_err_sampled"] <= nat_err), None)
+    out["fp32_16384"] = {"native_ms": round(nat_ms, 3),
+                         "native_tflops": round(2.0 * n ** 3 / (nat_ms * 1e-3) / 1e12, 2),
+                         "native_rel_err_sampled": nat_err, "emulated": res, "matched_N": matched}
+    return out
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_i8_residue_fp64_8192_N14_traffic.txt")
@@ -285,6 +376,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_measurement(torch, oz, max(1, min(args.steps, 10)))
+    if args.extras:
+        out["extras"] = extras_measurement(torch, oz)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_size, N)
     print(json.dumps(out), flush=True)
