@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -32,10 +33,12 @@ struct DeviceState {
   int* status = nullptr;       // sticky data-dependent status word
   CrtConsts* ctab[2] = {nullptr, nullptr};  // device tables of CrtConsts by N (b = 64, 32)
   hipStream_t capture = nullptr;            // library stream used only for graph capture
-  std::vector<BatchEntry*> batches;         // captured batches, oldest first
+  std::vector<std::shared_ptr<BatchEntry>> batches;  // captured batches, oldest first
 };
 std::mutex g_mu;
-std::map<int, DeviceState> g_dev;
+// Never destroyed: its entries own device resources, and HIP must not be
+// called from static destructors at process exit.
+std::map<int, DeviceState>& g_dev = *new std::map<int, DeviceState>;
 std::map<int, CrtConsts> g_consts;  // key: N * 100 + b
 PlanCoef g_plan[2];                 // planner coefficients for b = 64, 32
 bool g_plan_ok[2] = {false, false};
@@ -385,6 +388,7 @@ enum BatchSlot {
 constexpr int kMaxBatchEntries = 8;
 
 struct BatchEntry {
+  int dev = 0;                           // device holding the resources below
   std::vector<int64_t> key;
   char* table = nullptr;                 // device: descriptors, then one block map per slot
   size_t table_bytes = 0;                // allocated size
@@ -395,6 +399,19 @@ struct BatchEntry {
   int split = 0;                         // problems with >= split 256x256 tiles use them
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // The last reference may drop while a replay is still running: wait for
+  // the entry's device before releasing the graph and the table.
+  ~BatchEntry() {
+    if (!exec && !graph && !table) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (table) (void)hipFree(table);
+    if (cur != dev) (void)hipSetDevice(cur);
+  }
 };
 
 int64_t pad8(int64_t v) { return (v + 7) / 8 * 8; }
@@ -527,13 +544,6 @@ int upload_table(BatchEntry* e, const std::vector<char>& host, hipStream_t s) {
   return OZAKI2_OK;
 }
 
-void free_entry(BatchEntry* e) {
-  if (e->exec) (void)hipGraphExecDestroy(e->exec);
-  if (e->graph) (void)hipGraphDestroy(e->graph);
-  if (e->table) (void)hipFree(e->table);
-  delete e;
-}
-
 // Autotuner: times the residue products (the dominant phase) under each
 // candidate tile split, on this batch's operands, and returns the fastest.
 int tune_split(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* ctab,
@@ -626,14 +636,15 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
     key.push_back((int64_t)(intptr_t)C[p]);
   }
 
-  BatchEntry* e = nullptr;
+  std::shared_ptr<BatchEntry> e;   // keeps the entry alive while it is used
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    for (BatchEntry* x : g_dev[dev].batches)
+    for (const auto& x : g_dev[dev].batches)
       if (x->key == key) e = x;
   }
   if (!e) {
-    e = new BatchEntry;
+    e = std::make_shared<BatchEntry>();
+    e->dev = dev;
     e->key = key;
     e->active = (int)act.size();
     for (int p = 0; p < count; ++p)
@@ -663,20 +674,11 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
     std::vector<char> host;
     e->split = forced >= 0 ? forced : 1 << 30;
     if (forced < 0 && e->active > 0) {
-      if ((rc = tune_split(D, e, ctab, s, &e->split))) {
-        free_entry(e);
-        return rc;
-      }
+      if ((rc = tune_split(D, e.get(), ctab, s, &e->split))) return rc;
     }
     build_table(D, e->split, &host, e->blocks, e->map_off);
-    if (!table_fits(e->blocks)) {
-      free_entry(e);
-      return OZAKI2_ERR_INVALID_ARG;
-    }
-    if ((rc = upload_table(e, host, s))) {
-      free_entry(e);
-      return rc;
-    }
+    if (!table_fits(e->blocks)) return OZAKI2_ERR_INVALID_ARG;
+    if ((rc = upload_table(e.get(), host, s))) return rc;
     if (use_graph) {
       hipStream_t cs;
       {
@@ -684,10 +686,8 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
         cs = g_dev[dev].capture;
       }
       if (!cs) {
-        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
-          free_entry(e);
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
           return OZAKI2_ERR_HIP;
-        }
         std::lock_guard<std::mutex> lk(g_mu);
         g_dev[dev].capture = cs;
       }
@@ -699,11 +699,10 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
       if (ok) ok = hipGraphInstantiateWithFlags(&e->exec, e->graph, 0) == hipSuccess;
       if (!ok) {
         (void)hipGetLastError();
-        free_entry(e);
         return OZAKI2_ERR_HIP;
       }
     }
-    std::vector<BatchEntry*> evict;
+    std::vector<std::shared_ptr<BatchEntry>> evict;   // released outside the lock
     {
       std::lock_guard<std::mutex> lk(g_mu);
       auto& v = g_dev[dev].batches;
@@ -712,10 +711,6 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
         evict.push_back(v.front());
         v.erase(v.begin());
       }
-    }
-    if (!evict.empty()) {
-      if (hipDeviceSynchronize() != hipSuccess) return OZAKI2_ERR_HIP;
-      for (BatchEntry* x : evict) free_entry(x);
     }
   }
   Scope sc(PH_BATCH, s);

@@ -191,14 +191,31 @@ __device__ __forceinline__ void slices_body(const T* __restrict__ src, int ld, i
   }
 }
 
+// Tile order of workgroup b: for the column-major A side (TRANS) row tiles
+// vary fastest, so workgroups running together read neighbouring 256-byte
+// pieces of the same columns (DRAM pages); for B, whose rows are contiguous
+// in k, k tiles vary fastest.
+template <bool TRANS>
+__device__ inline void slice_tile(int b, int k_pad, int rows_pad, int* kx, int* ry) {
+  if (TRANS) {
+    const int gy = rows_pad / kTR;
+    *kx = b / gy;
+    *ry = b % gy;
+  } else {
+    const int gx = k_pad / kTK;
+    *kx = b % gx;
+    *ry = b / gx;
+  }
+}
+
 template <typename T, bool TRANS, int MODE>
 __global__ __launch_bounds__(256) void k_slices(const T* __restrict__ src, int ld, int rows, int k,
                                                 int k_pad, size_t slice, const uint64_t* __restrict__ bits,
                                                 const int* __restrict__ shift, CrtConsts cc,
                                                 int8_t* __restrict__ out) {
-  const int gx = k_pad / kTK;
-  slices_body<T, TRANS, MODE>(src, ld, rows, k, k_pad, slice, bits, shift, cc, out, blockIdx.x % gx,
-                              blockIdx.x / gx);
+  int kx, ry;
+  slice_tile<TRANS>(blockIdx.x, k_pad, (int)(slice / k_pad), &kx, &ry);
+  slices_body<T, TRANS, MODE>(src, ld, rows, k, k_pad, slice, bits, shift, cc, out, kx, ry);
 }
 
 // Grouped: A side (TRANS, rows = m) or B side (rows = n) of every problem.
@@ -208,14 +225,16 @@ __global__ __launch_bounds__(256) void kg_slices(const ProbDesc* __restrict__ P,
                                                  const CrtConsts* __restrict__ ctab) {
   const BlockRef e = map[blockIdx.x];
   const ProbDesc& d = P[e.x];
-  const int lid = e.y;
-  const int gx = d.kp / kTK;
-  if (ASIDE)
+  int kx, ry;
+  if (ASIDE) {
+    slice_tile<true>(e.y, d.kp, d.mp, &kx, &ry);
     slices_body<T, true, MODE>((const T*)d.A, d.lda, d.m, d.k, d.kp, (size_t)d.mp * d.kp,
-                               d.rowbits, d.mu, ctab[d.N], d.As, lid % gx, lid / gx);
-  else
+                               d.rowbits, d.mu, ctab[d.N], d.As, kx, ry);
+  } else {
+    slice_tile<false>(e.y, d.kp, d.np, &kx, &ry);
     slices_body<T, false, MODE>((const T*)d.B, d.ldb, d.n, d.k, d.kp, (size_t)d.np * d.kp,
-                                d.colbits, d.nu, ctab[d.N], d.Bs, lid % gx, lid / gx);
+                                d.colbits, d.nu, ctab[d.N], d.Bs, kx, ry);
+  }
 }
 
 // Planner operands: x = |a| 2^-alpha (alpha = floor(log2 max_h |a_ih|), so
