@@ -34,6 +34,28 @@ def run_stage_case(m, n, k, N, phi, seed, dtype):
     assert oz.ozaki2_sync_status() == oz.OK
 
 
+def test_stages_config_256():
+    # The small FP64 configuration exactly (256^3, N = 14, phi = 0.5, seed 0):
+    # every stage bit-exact, plus the exact big-integer product A'B' against
+    # the CRT reconstruction of the GPU's W_l.
+    announce("stages 256^3 N=14 phi=0.5 seed=0")
+    A, B = gemm_inputs(256, 256, 256, phi=0.5, seed=0)
+    got = {kk: host(v) for kk, v in oz.debug_stages(dev(A), dev(B), 14).items()}
+    C_ref, st = os_ii(A, B, 14, stages=True)
+    assert compare_stages(got, st, C_ref, 14) == []
+    from oracle.constants import constants
+    from oracle.exact import exact_int_product
+    const = constants(14, 64)
+    ApBp = exact_int_product(st["Ap"], st["Bp"])
+    P = int(const.P)
+    recon = np.zeros((256, 256), dtype=object)
+    for l in range(14):
+        recon = recon + np.asarray(got["WT"][l].T, dtype=object) * int(const.x[l])
+    recon = np.vectorize(lambda v: ((int(v) + P // 2) % P) - P // 2, otypes=[object])(recon)
+    assert np.array_equal(recon, ApBp)
+    assert oz.ozaki2_sync_status() == oz.OK
+
+
 @pytest.mark.parametrize("m,n,k,N,phi", [
     (300, 200, 500, 14, 0.5),     # several 128-tiles in each direction, ragged tails
     (64, 64, 64, 2, 0.5),
@@ -163,4 +185,23 @@ def test_full_size_sampled(dtype, N, size):
     ref = os_ii(A, B, N, rows=rows, cols=cols)
     sub = got[np.ix_(rows, cols)]
     assert np.array_equal(sub, ref)
+    assert oz.ozaki2_sync_status() == oz.OK
+
+
+@pytest.mark.parametrize("phi", [0.0, 2.0, 4.0])
+def test_wide_exponent_4096_sampled(phi):
+    # The wide-exponent workload at 4096^3 with N from the bound at 1e-15
+    # (49 where it is unreachable): sampled rows x columns against the oracle.
+    n = 4096
+    A, B = gemm_inputs(n, n, n, phi=phi, seed=0)
+    dA, dB = dev(A), dev(B)
+    rc, N = oz.required_moduli(dA, dB, 1e-15)
+    assert rc in (oz.OK, oz.ERR_UNREACHABLE)
+    announce(f"wide exponent 4096^3 phi={phi} N={N}")
+    got = host(oz.gemm(dA, dB, N))
+    rng = np.random.default_rng(7)
+    rows = np.sort(rng.choice(n, 10, replace=False))
+    cols = np.sort(rng.choice(n, 10, replace=False))
+    rows[0], cols[-1] = 0, n - 1
+    assert np.array_equal(got[np.ix_(rows, cols)], os_ii(A, B, N, rows=rows, cols=cols))
     assert oz.ozaki2_sync_status() == oz.OK
