@@ -110,18 +110,29 @@ int ozaki2_set_workspace(void *dptr, size_t bytes);
 int ozaki2_sync_status(void);
 
 /*
- * ozaki2_gemm_batched - `count` independent emulated GEMMs in one persistent
- * launch sequence (configs with many uneven problems).
+ * ozaki2_gemm_batched - `count` independent emulated GEMMs of uneven sizes
+ * and per-problem N, run as one launch per phase of Algorithm 1 over all
+ * problems; results are bit-identical to `count` separate calls.
  *   prec            : 64 (double) or 32 (float) for every problem.
  *   mnkN            : HOST array of 4*count ints (m, n, k, N per problem).
  *   A, B, C         : HOST arrays of `count` device pointers.
  *   lda, ldb, ldc   : HOST arrays of `count` leading dimensions.
  * Each problem obeys the rules of ozaki2_gemm / ozaki2_sgemm; any invalid
  * problem makes the whole call fail before anything is enqueued.
+ * The first call with a given batch (sizes, N, pointers, leading dimensions
+ * and workspace) builds a device problem table, times tile choices on the
+ * batch's own operands, captures the launch sequence into a hipGraph and
+ * synchronises the stream; later calls with the same batch replay the graph
+ * asynchronously and allocate nothing.  Up to eight batches stay cached per
+ * device.  The workspace needed is ozaki2_batched_workspace_bytes.
  */
 int ozaki2_gemm_batched(int prec, int count, const int *mnkN, const void *const *A,
                         const int *lda, const void *const *B, const int *ldb, void *const *C,
                         const int *ldc);
+
+/* Bytes of device workspace ozaki2_gemm_batched needs for these problems
+ * (mnkN as for ozaki2_gemm_batched); 0 for invalid arguments. */
+size_t ozaki2_batched_workspace_bytes(int prec, int count, const int *mnkN);
 
 /*
  * ozaki2_debug_stages - run Algorithms 1-3 like ozaki2_gemm / ozaki2_sgemm

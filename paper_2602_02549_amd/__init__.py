@@ -44,6 +44,7 @@ _SIGS = {
     "ozaki2_gemm_batched": ([_c_int, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_ptr),
                              ctypes.POINTER(_c_int), ctypes.POINTER(_c_ptr), ctypes.POINTER(_c_int),
                              ctypes.POINTER(_c_ptr), ctypes.POINTER(_c_int)], _c_int),
+    "ozaki2_batched_workspace_bytes": ([_c_int, _c_int, ctypes.POINTER(_c_int)], ctypes.c_size_t),
     "ozaki2_debug_stages": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int,
                              ctypes.POINTER(_c_ptr)], _c_int),
     "ozaki2_debug_log2f": ([_c_ptr, _c_ptr, _c_int], _c_int),
@@ -116,6 +117,11 @@ def ozaki2_gemm_batched(prec, mnkN, A, lda, B, ldb, C, ldc):
     arr_p = lambda v: (_c_ptr * len(v))(*v)
     return _call("ozaki2_gemm_batched", prec, count, arr_i(mnkN), arr_p(A), arr_i(lda), arr_p(B),
                  arr_i(ldb), arr_p(C), arr_i(ldc))
+
+
+def ozaki2_batched_workspace_bytes(prec, mnkN):
+    count = len(mnkN) // 4
+    return lib().ozaki2_batched_workspace_bytes(prec, count, (_c_int * max(len(mnkN), 1))(*mnkN))
 
 
 def ozaki2_debug_stages(prec, m, n, k, A, lda, B, ldb, N, outs):

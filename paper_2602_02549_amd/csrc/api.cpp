@@ -586,6 +586,20 @@ int tune_split(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* c
   return rc;
 }
 
+// Workspace of a batch: the layouts of the active problems (m, n, k >= 1),
+// back to back; their indices and offsets go to act / off.
+size_t batch_layout(int count, const int* mnkN, std::vector<int>* act, std::vector<size_t>* off) {
+  size_t total = 0;
+  for (int p = 0; p < count; ++p) {
+    const int m = mnkN[4 * p], n = mnkN[4 * p + 1], k = mnkN[4 * p + 2];
+    if (m == 0 || n == 0 || k == 0) continue;
+    if (act) act->push_back(p);
+    if (off) off->push_back(total);
+    total += rup(layout(m, n, k, mnkN[4 * p + 3], batch_row_pad(m, n)).total, 256);
+  }
+  return total;
+}
+
 int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, const int* lda,
                  const void* const* B, const int* ldb, void* const* C, const int* ldc) {
   const int b = pr == Prec::F64 ? 64 : 32;
@@ -596,21 +610,13 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
     if ((rc = check_N(mnkN[4 * p + 3], b))) return rc;
   }
   hipStream_t s = g_stream;
-  // workspace: the single-problem layouts of the active problems, back to back
   std::vector<int> act;
   std::vector<size_t> off;
-  size_t total = 0;
-  for (int p = 0; p < count; ++p) {
-    const int m = mnkN[4 * p], n = mnkN[4 * p + 1], k = mnkN[4 * p + 2];
-    if (m == 0 || n == 0 || k == 0) continue;
-    act.push_back(p);
-    off.push_back(total);
-    total += rup(layout(m, n, k, mnkN[4 * p + 3], batch_row_pad(m, n)).total, 256);
-  }
+  const size_t total = batch_layout(count, mnkN, &act, &off);
   char* ws = nullptr;
   int* status = nullptr;
   uint64_t gen = 0;
-  int rc = get_workspace(total > 0 ? total : 256, &ws, &status, &gen);
+  int rc = get_workspace(total, &ws, &status, &gen);
   if (rc) return rc;
   CrtConsts* ctab = nullptr;
   if ((rc = get_ctab(b, &ctab))) return rc;
@@ -779,6 +785,16 @@ int ozaki2_gemm_batched(int prec, int count, const int* mnkN, const void* const*
   if (count == 0) return OZAKI2_OK;
   if (!mnkN || !A || !lda || !B || !ldb || !C || !ldc) return OZAKI2_ERR_INVALID_ARG;
   return batched_impl(prec == 64 ? Prec::F64 : Prec::F32, count, mnkN, A, lda, B, ldb, C, ldc);
+}
+
+size_t ozaki2_batched_workspace_bytes(int prec, int count, const int* mnkN) {
+  if ((prec != 64 && prec != 32) || count < 0 || (count > 0 && !mnkN)) return 0;
+  const int nmax = prec == 64 ? kMaxModuli : 16;
+  for (int p = 0; p < count; ++p) {
+    const int m = mnkN[4 * p], n = mnkN[4 * p + 1], k = mnkN[4 * p + 2], N = mnkN[4 * p + 3];
+    if (m < 0 || n < 0 || k < 0 || k > kMaxK || N < 2 || N > nmax) return 0;
+  }
+  return batch_layout(count, mnkN, nullptr, nullptr);
 }
 
 int ozaki2_required_moduli(int prec, int m, int n, int k, const void* A, int lda, const void* B,

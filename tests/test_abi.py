@@ -89,3 +89,21 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(oz, "_lib", None)
     with pytest.raises(RuntimeError):
         oz.lib()
+
+
+def test_batched_workspace_query():
+    # Degenerate problems need no workspace; each active problem adds its own
+    # layout; invalid arguments give 0.  (No device work is involved.)
+    q = oz.ozaki2_batched_workspace_bytes
+    assert q(64, []) == 0
+    assert q(64, [5, 4, 0, 10, 0, 7, 9, 12]) == 0
+    one = q(64, [300, 200, 500, 14])
+    two = q(64, [300, 200, 500, 14, 100, 90, 300, 20])
+    assert 0 < one < two
+    assert q(64, [300, 200, 500, 14, 5, 4, 0, 10]) == one
+    assert q(64, [300, 200, 500, 50]) == 0          # N out of range
+    assert q(32, [300, 200, 500, 17]) == 0          # FP32 allows N <= 16
+    assert q(64, [300, 200, (1 << 17) + 1, 14]) == 0
+    assert q(16, [300, 200, 500, 14]) == 0
+    # at least the moduli slices and W of every active problem
+    assert two >= 20 * (128 * 384 + 128 * 384 + 128 * 128) + 14 * (384 * 512 + 256 * 512 + 256 * 384)
