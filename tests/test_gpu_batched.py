@@ -159,3 +159,38 @@ def test_batched_512_workload_sampled():
         want = os_ii(mats[q][0], mats[q][1], Ns[q], rows=rows, cols=cols)
         got = host(Ccm[q]).T[np.ix_(rows, cols)]
         assert np.array_equal(got, want), f"problem {q} vs oracle"
+
+
+def test_caller_owned_workspace():
+    # Single and batched calls on a caller-installed workspace of exactly the
+    # queried size give the same bits as on the library's; one byte less is
+    # refused before anything runs.
+    announce("caller-owned workspace")
+    A, B = gemm_inputs(300, 200, 500, seed=11)
+    ref = single(A, B, 14)
+    cases = [(300, 200, 500, 14), (64, 64, 64, 2), (5, 4, 0, 10)]
+    As, Bs = make_batch(cases, np.float64, seed=12)
+    Ns = [c[3] for c in cases]
+    refs = [single(a, b, N) for a, b, N in zip(As, Bs, Ns)]   # on the library's workspace
+    try:
+        nbytes = oz.ozaki2_workspace_bytes(64, 300, 200, 500, 14)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+        assert oz.ozaki2_set_workspace(ws.data_ptr(), nbytes) == oz.OK
+        assert np.array_equal(single(A, B, 14), ref)
+        assert oz.ozaki2_set_workspace(ws.data_ptr(), nbytes - 1) == oz.OK
+        with pytest.raises(oz.Ozaki2Error) as ei:
+            oz.gemm(dev(A), dev(B), 14)
+        assert ei.value.code == oz.ERR_WORKSPACE
+        need = oz.ozaki2_batched_workspace_bytes(64, [v for c in cases for v in c])
+        wsb = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+        assert oz.ozaki2_set_workspace(wsb.data_ptr(), need) == oz.OK
+        _, _, Ccm, _ = run_batched(As, Bs, Ns)
+        for q in range(len(cases)):
+            assert np.array_equal(host(Ccm[q]).T, refs[q]), f"problem {q}"
+        assert oz.ozaki2_set_workspace(wsb.data_ptr(), need - 1) == oz.OK
+        with pytest.raises(oz.Ozaki2Error) as ei:
+            run_batched(As, Bs, Ns)
+        assert ei.value.code == oz.ERR_WORKSPACE
+        torch.cuda.synchronize()
+    finally:
+        oz.ozaki2_set_workspace(None, 0)
