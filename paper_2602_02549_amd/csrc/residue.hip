@@ -120,6 +120,11 @@ __device__ __forceinline__ void slices_body(const T* __restrict__ src, int ld, i
   __shared__ double tile[kTR * kRS];
   const int t = threadIdx.x;
   const int r0 = ry * kTR, h0 = kx * kTK;
+  // Residue slices of padding rows feed only products of padding rows, which
+  // the CRT never reads: they are left unwritten (the k padding of real rows
+  // is still zeroed).  Abar/Bbar padding must stay zero, since the scaling
+  // product's maxima cover whole rows and columns.
+  if (MODE == 1 && r0 >= rows) return;   // whole workgroup, before any barrier
   // All 16 loads of a thread go out before any is used: their addresses are
   // clamped into the matrix and out-of-range elements are replaced by zero
   // afterwards, so no branch separates them.
@@ -173,7 +178,8 @@ __device__ __forceinline__ void slices_body(const T* __restrict__ src, int ld, i
     w.w = pack4(b[12], b[13], b[14], b[15]);
     *reinterpret_cast<uint4*>(dst) = w;
   } else {
-    const int sh = rg < rows ? shift[rg] : 0;
+    if (rg >= rows) return;   // after the only barrier
+    const int sh = shift[rg];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = trunc(ldexp(v[e], sh));
     if (cc.nlimbs == 2) {          // uniform branches
