@@ -97,7 +97,8 @@ int ozaki2_required_moduli(int prec, int m, int n, int k, const void *A, int lda
  * (a hipStream_t; NULL = the null stream). */
 int ozaki2_set_stream(void *stream);
 
-/* Bytes of device workspace a call with these sizes needs (prec 64 or 32). */
+/* Bytes of device workspace a call with these sizes needs (prec 64 or 32);
+ * 0 for arguments the call itself would reject. */
 size_t ozaki2_workspace_bytes(int prec, int m, int n, int k, int N);
 
 /* Install a caller-owned device workspace for the current device (NULL, 0

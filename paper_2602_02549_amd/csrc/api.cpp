@@ -748,7 +748,8 @@ int ozaki2_set_stream(void* stream) {
 }
 
 size_t ozaki2_workspace_bytes(int prec, int m, int n, int k, int N) {
-  if ((prec != 64 && prec != 32) || m < 0 || n < 0 || k < 0 || N < 2 || N > kMaxModuli) return 0;
+  if ((prec != 64 && prec != 32) || m < 0 || n < 0 || k < 0 || k > kMaxK) return 0;
+  if (check_N(N, prec) != OZAKI2_OK) return 0;
   return layout(m, n, k, N, single_row_pad(m, n, N)).total;
 }
 

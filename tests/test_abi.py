@@ -43,6 +43,9 @@ def test_version_and_workspace_query():
     # three INT8 slice sets of N x 8192 x 8192 bytes dominate
     assert ws >= 3 * 14 * 8192 * 8192
     assert oz.ozaki2_workspace_bytes(64, 10, 10, 10, 1) == 0
+    assert oz.ozaki2_workspace_bytes(32, 10, 10, 10, 17) == 0     # FP32 allows N <= 16
+    assert oz.ozaki2_workspace_bytes(32, 10, 10, 10, 16) > 0
+    assert oz.ozaki2_workspace_bytes(64, 10, 10, (1 << 17) + 1, 14) == 0
     assert oz.ozaki2_workspace_bytes(16, 10, 10, 10, 5) == 0
 
 
