@@ -63,6 +63,12 @@ def test_stages_config_256():
     (257, 129, 130, 20, 1.0),
     (100, 90, 300, 49, 2.0),
     (33, 300, 129, 11, 4.0),
+    # residue paths: two limbs from N = 12, three from N = 15, then 2 and 3
+    # exact reduction steps (N = 24, 30)
+    (70, 65, 200, 12, 1.0),
+    (70, 65, 200, 15, 1.0),
+    (70, 65, 200, 24, 3.0),
+    (70, 65, 200, 30, 4.0),
 ])
 def test_stages_fp64(m, n, k, N, phi):
     run_stage_case(m, n, k, N, phi, seed=m + n + k + N, dtype=np.float64)
@@ -204,4 +210,28 @@ def test_wide_exponent_4096_sampled(phi):
     cols = np.sort(rng.choice(n, 10, replace=False))
     rows[0], cols[-1] = 0, n - 1
     assert np.array_equal(got[np.ix_(rows, cols)], os_ii(A, B, N, rows=rows, cols=cols))
+    assert oz.ozaki2_sync_status() == oz.OK
+
+
+@pytest.mark.parametrize("phi,N", [(0.5, 14), (4.0, 30)])
+def test_error_within_theorem1_bound_4096(phi, N):
+    # Theorem 1 on the GPU's own output at 4096^3, on sampled entries:
+    # |AB - C| <= est1 <= est2 with the exact AB and the exact A'B'.
+    from oracle.bounds import theorem1
+    from oracle.exact import abs_error, exact_int_product, exact_product
+    n = 4096
+    announce(f"Theorem 1 on GPU output 4096^3 phi={phi} N={N}")
+    A, B = gemm_inputs(n, n, n, phi=phi, seed=3)
+    got = host(oz.gemm(dev(A), dev(B), N))
+    rng = np.random.default_rng(11)
+    rows = np.sort(rng.choice(n, 8, replace=False))
+    cols = np.sort(rng.choice(n, 8, replace=False))
+    C_ref, st = os_ii(A, B, N, rows=rows, cols=cols, stages=True)
+    sub = got[np.ix_(rows, cols)]
+    assert np.array_equal(sub, C_ref)
+    ApBp = exact_int_product(st["Ap"], st["Bp"])
+    est1, est2 = theorem1(A, B, st, ApBp)
+    err = abs_error(sub, exact_product(A, B, rows, cols))
+    for idx in np.ndindex(err.shape):
+        assert err[idx] <= float(est1[idx]) <= float(est2[idx]), idx
     assert oz.ozaki2_sync_status() == oz.OK
