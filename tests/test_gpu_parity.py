@@ -11,7 +11,7 @@ import pytest
 
 from gpu_util import announce, compare_stages, dev, host, rel_close
 from oracle.ozaki2 import log2f_many, os_ii
-from workload import gemm_inputs
+from workload import gemm_inputs, wrap_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +54,46 @@ def test_stages_config_256():
     recon = np.vectorize(lambda v: ((int(v) + P // 2) % P) - P // 2, otypes=[object])(recon)
     assert np.array_equal(recon, ApBp)
     assert oz.ozaki2_sync_status() == oz.OK
+
+
+def test_int32_wrap_at_k_max(monkeypatch):
+    # k = 2^17 with every residue modulo 256 equal to -128 (N = 14): the
+    # p = 256 residue product sums k terms of 2^14 to 2^31, which the INT8
+    # matrix cores must wrap to -2^31 (W = 0), not saturate (W = -1).  Every
+    # stage bit-exact against the oracle (128x128 kernel).  Then a 512 x 512
+    # problem of the same kind through the single call (128x128 tiles) and
+    # the batched path with all 256x256 and all 128x128 tiles: bit-identical,
+    # and equal to the oracle on sampled entries.
+    m, n, k, N = 40, 33, 2 ** 17, 14
+    announce(f"int32 wrap m={m} n={n} k={k} N={N}")
+    A, B = wrap_inputs(m, n, k, seed=2)
+    got = {kk: host(v) for kk, v in oz.debug_stages(dev(A), dev(B), N).items()}
+    C_ref, st = os_ii(A, B, N, stages=True)
+    l = list(st["const"].p).index(256)
+    assert np.all(st["Cl"][l] == -2 ** 31)
+    assert np.all(got["WT"][l] == 0)
+    bad = compare_stages(got, st, C_ref, N)
+    assert bad == [], bad
+    assert oz.ozaki2_sync_status() == oz.OK
+    assert np.array_equal(host(oz.gemm(dev(A), dev(B), N)), C_ref)
+
+    m = n = 512
+    announce(f"int32 wrap m={m} n={n} k={k} N={N} single and batched")
+    A, B = wrap_inputs(m, n, k, seed=3)
+    ref = host(oz.gemm(dev(A), dev(B), N))
+    rows, cols = np.array([0, 77, 300, 511]), np.array([3, 128, 255, 500])
+    want, st = os_ii(A, B, N, rows=rows, cols=cols, stages=True)
+    assert np.all(st["Cl"][l] == -2 ** 31)
+    assert np.array_equal(ref[np.ix_(rows, cols)], want)
+    dA, dB = dev(np.ascontiguousarray(A.T)), dev(np.ascontiguousarray(B.T))
+    del A, B
+    for split in ("0", "1000000"):
+        announce(f"int32 wrap batched split={split}")
+        monkeypatch.setenv("OZAKI2_BATCH_SPLIT", split)
+        Cc = torch.full((n, m), float("nan"), dtype=torch.float64, device="cuda:0")
+        oz.gemm_batched_cm([dA], [dB], [Cc], [(m, n, k)], [N])
+        assert oz.ozaki2_sync_status() == oz.OK
+        assert np.array_equal(host(Cc).T, ref), f"split {split}"
 
 
 @pytest.mark.parametrize("m,n,k,N,phi", [

@@ -7,8 +7,8 @@ import numpy as np
 import pytest
 
 import oracle.ozaki2 as oz
-from pins import all_pins
-from workload import gemm_inputs
+from pins import all_pins, pin_residues
+from workload import gemm_inputs, wrap_inputs
 
 
 def _const_mut(monkeypatch, fn):
@@ -79,6 +79,10 @@ def m_drop_C2(mp):
     mp.setattr(oz, "crt_reconstruct", f)
 
 
+def m_saturate_int32(mp):
+    mp.setattr(oz, "wrap_int32", lambda X: np.clip(X, -2 ** 31, 2 ** 31 - 1))
+
+
 MUTATIONS = [m_s2_sign, m_drop_P2, m_wrong_q, m_shift_plus_one, m_floor_mod,
              m_transposed_operand, m_floor_instead_of_ceil, m_unscale_sign]
 
@@ -101,3 +105,13 @@ def test_dropping_C2_is_caught(monkeypatch):
     A, B = gemm_inputs(6, 6, 6, phi=1.0, seed=22)
     _, st = oz.os_ii(A, B, 14, stages=True)
     assert all_pins(A, B, st) != []
+
+
+def test_saturating_accumulator_is_caught(monkeypatch):
+    # An INT32 accumulator that saturates instead of wrapping gives 2^31 - 1
+    # for the p = 256 product at k = 2^17, which is not congruent to A'B'
+    # modulo 256; the residue pin must see it.
+    m_saturate_int32(monkeypatch)
+    A, B = wrap_inputs(4, 3, 2 ** 17, seed=1)
+    _, st = oz.os_ii(A, B, 14, stages=True)
+    assert pin_residues(st) != []

@@ -8,7 +8,7 @@ import pytest
 from oracle.ozaki2 import os_ii
 from pins import (all_pins, pin_accumulation, pin_lemma0_lemma1, pin_residues,
                   pin_scaling, pin_theorem1)
-from workload import gemm_inputs
+from workload import gemm_inputs, wrap_inputs
 
 
 @pytest.mark.parametrize("N", list(range(2, 50)))
@@ -22,6 +22,21 @@ def test_all_pins_fp64_every_N(N):
 def test_all_pins_fp32_every_N(N):
     A, B = gemm_inputs(5, 4, 7, phi=1.0, seed=100 + N, dtype=np.float32)
     _, st = os_ii(A, B, N, stages=True)
+    assert all_pins(A, B, st) == []
+
+
+def test_int32_wrap_at_k_max():
+    # k = 2^17 (the largest k of the analysis) with every residue of A' and B'
+    # modulo 256 equal to -128 (N = 14 for these inputs): each of the k terms
+    # of the p = 256 residue product is 2^14, so the INT32 sum is 2^31 and
+    # wraps to -2^31.  Wrap-around keeps it congruent mod 256 (W = 0), which
+    # Theorem CRT needs; every lemma and Theorem 1 must still hold.
+    A, B = wrap_inputs(4, 3, 2 ** 17, seed=1)
+    _, st = os_ii(A, B, 14, stages=True)
+    l = list(st["const"].p).index(256)
+    assert np.all(st["Al"][l] == -128) and np.all(st["Bl"][l] == -128)
+    assert np.all(st["Cl"][l] == -2 ** 31)
+    assert np.all(st["W"][l] == 0)
     assert all_pins(A, B, st) == []
 
 

@@ -52,3 +52,19 @@ def batched_inputs(count: int = 512, phi: float = 1.0, seed: int = 0, dtype=np.f
         B = draw_matrix(rng, (k, n), phi).astype(dtype)
         out.append((A, B))
     return shapes, out
+
+
+def wrap_inputs(m: int, n: int, k: int, seed: int = 0, spread: int = 20):
+    """Structured A (m x k) and B (k x n) whose entries are
+    +-(1 + 2^-39) * 2^e, with a random sign per entry and one random integer
+    exponent e in [-spread, spread] per row of A and per column of B.
+
+    Every row of A and column of B then has the same significand pattern, so
+    the scaled integers A', B' share one residue pattern modulo a power of
+    two; at suitable N and k this drives INT32 accumulation of a residue
+    product to its limit (used for the k = 2^17 wrap-around case)."""
+    rng = np.random.default_rng(seed)
+    u = 1.0 + 2.0 ** -39
+    A = u * rng.choice([-1.0, 1.0], (m, k)) * np.ldexp(1.0, rng.integers(-spread, spread + 1, (m, 1)))
+    B = u * rng.choice([-1.0, 1.0], (k, n)) * np.ldexp(1.0, rng.integers(-spread, spread + 1, (1, n)))
+    return A, B
