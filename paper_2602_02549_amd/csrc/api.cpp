@@ -176,6 +176,7 @@ int get_workspace(size_t bytes, char** base, int** status, uint64_t* gen = nullp
   std::lock_guard<std::mutex> lk(g_mu);
   DeviceState& st = g_dev[dev];
   if (!st.status) {
+    init_slice_launch(dev);
     if (hipMalloc(&st.status, sizeof(int)) != hipSuccess) return OZAKI2_ERR_HIP;
     if (hipMemset(st.status, 0, sizeof(int)) != hipSuccess) return OZAKI2_ERR_HIP;
   }

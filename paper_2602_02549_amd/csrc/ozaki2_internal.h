@@ -138,6 +138,10 @@ void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int 
                    int* mu_p, int* nu_p, int* mu, int* nu, float* ef);
 void launch_log2f(hipStream_t s, const float* d, float* out, int count);
 
+// residue.hip: per-device launch figures of the slice kernels (resident workgroups);
+// called once per device before its first launch, outside stream capture.
+void init_slice_launch(int dev);
+
 // residue.hip: INT8 slices in K-major layout [S][rows_pad][k_pad].
 //   src element (r, h) is at  trans ? src[r + h*ld] : src[h + r*ld].
 //   mode 0 (bar):     S = 1, byte = ceil(2^shift |x|) (>= 1 if x != 0),

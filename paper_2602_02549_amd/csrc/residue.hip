@@ -8,10 +8,11 @@
 // the column-major A (rows contiguous) and the column-major B (k contiguous)
 // are both read coalesced, then each thread owns 16 consecutive k of one row
 // and writes 16 bytes per slice, 8 threads covering one full 128-byte line.
-// The LDS rows are 132 doubles apart and their columns XOR-swizzled by
-// (row / 8), and each thread walks its 16 elements starting at its chunk
-// index: both the staging stores and the reads then touch every bank exactly
-// twice per wave (the minimum for 64 x 8 bytes).
+// The LDS rows are 132 doubles apart and the low bits of each column index
+// XOR-swizzled (tile_pos): the staging stores and the in-order reads then
+// touch every bank exactly twice per wave (the minimum for 64 x 8 bytes).
+// Each workgroup walks tiles in a grid-stride loop and issues the loads of
+// its next tile before computing the current one.
 //
 // Residues of the scaled integer v = trunc(2^mu a) (|v| < 2^(6 + floor P'))
 // are exact in FP64.  Up to three 32-bit limbs (N <= 20): v = sum_t v_t 2^(32t)
@@ -21,7 +22,10 @@
 // p.  Larger N take nsteps such steps from v itself (each exact, shrinking |r|
 // by ~2^-52 relative; the last starts from |r| < 2^50).  For p = 256 the
 // result lies in [-128, 128] and the byte store wraps 128 to -128.
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
+#include <type_traits>
 
 #include "ozaki2_internal.h"
 
@@ -111,59 +115,142 @@ __device__ __forceinline__ void store_residues_limbs(const double (&v)[16], cons
   }
 }
 
-// One 32-row x 128-k tile (k tile kx, row tile ry) of the slices.
-template <typename T, bool TRANS, int MODE>
-__device__ __forceinline__ void slices_body(const T* __restrict__ src, int ld, int rows, int k, int k_pad,
-                                   size_t slice, const uint64_t* __restrict__ bits,
-                                   const int* __restrict__ shift, const CrtConsts& cc,
-                                   int8_t* __restrict__ out, int kx, int ry) {
-  __shared__ double tile[kTR * kRS];
+// Workgroup barrier for the LDS tile only: it waits for this wave's LDS
+// (and scalar) traffic, not for its global loads, so the next tile's loads
+// stay in flight across it.  The memory clobber keeps the compiler from
+// moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// The 16 source elements of one thread for the tile at rows r0.., k h0..;
+// all 16 loads go out before any is used.  Addresses are clamped into the
+// matrix (rows, k >= 1); out-of-range elements are zeroed when staged.
+template <typename T, bool TRANS>
+__device__ __forceinline__ void tile_loads(const T* __restrict__ src, int ld, int rows, int k,
+                                           int r0, int h0, T (&x)[16]) {
   const int t = threadIdx.x;
-  const int r0 = ry * kTR, h0 = kx * kTK;
-  // Residue slices of padding rows feed only products of padding rows, which
-  // the CRT never reads: they are left unwritten (the k padding of real rows
-  // is still zeroed).  Abar/Bbar padding must stay zero, since the scaling
-  // product's maxima cover whole rows and columns.
-  if (MODE == 1 && r0 >= rows) return;   // whole workgroup, before any barrier
-  // All 16 loads of a thread go out before any is used: their addresses are
-  // clamped into the matrix and out-of-range elements are replaced by zero
-  // afterwards, so no branch separates them.
-  T x[16];
   if (TRANS) {  // src[r + h*ld]: 32 consecutive rows per half-wave, two columns per wave
-    const int r = t & 31, rg = r0 + r, sw = r >> 3;
-    const int hb = t >> 5;
-    const T* a = src + min(rg, rows - 1);
+    const T* a = src + min(r0 + (t & 31), rows - 1);
+    const int hb = h0 + (t >> 5);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) x[q] = a[(size_t)min(h0 + hb + 8 * q, k - 1) * ld];
+    for (int q = 0; q < 16; ++q) x[q] = a[(size_t)min(hb + 8 * q, k - 1) * ld];
+  } else {      // src[h + r*ld]: 128 consecutive k per half-block
+    const T* a = src + min(h0 + (t & 127), k - 1);
+    const int rb = r0 + (t >> 7);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int h = hb + 8 * q;
-      tile[r * kRS + (h ^ sw)] = (rg < rows && h0 + h < k) ? (double)x[q] : 0.0;
+    for (int q = 0; q < 16; ++q) x[q] = a[(size_t)min(rb + 2 * q, rows - 1) * ld];
+  }
+}
+
+// Per-row input of the thread's output row r0 + t/8 (clamped): the abs-max
+// bit pattern (mode 0) or the shift mu / nu (mode 1).
+template <int MODE>
+__device__ __forceinline__ int64_t row_aux(const void* __restrict__ aux, int rows, int r0) {
+  const int rg = min(r0 + (int)(threadIdx.x >> 3), rows - 1);
+  if (MODE == 0) return (int64_t)static_cast<const uint64_t*>(aux)[rg];
+  return static_cast<const int*>(aux)[rg];
+}
+
+// LDS position of element (r, h) of a tile: rows kRS doubles apart, and the
+// low two bits of h XORed with bits of h / 32 and r / 8.  Both staging
+// patterns and the in-order reads of tile_finish then touch every bank
+// exactly twice per wave (the minimum for 64 lanes x 8 bytes).
+__device__ __forceinline__ int tile_pos(int r, int h) {
+  return r * kRS + (h ^ (((h >> 5) ^ (r >> 3)) & 3));
+}
+
+// Writes the thread's 16 elements into the LDS tile (zero outside the matrix).
+// Within each group of four steps q the XOR term of tile_pos is constant
+// (h / 32 and r / 8 depend on q / 4 only), so the positions are four bases
+// plus constant offsets.
+template <typename T, bool TRANS>
+__device__ __forceinline__ void tile_stage(const T (&x)[16], int rows, int k, int r0, int h0,
+                                           double* tile) {
+  const int t = threadIdx.x;
+  if (TRANS) {  // element (r, h = hb + 8q): tile_pos = r*kRS + 8q + (hb ^ ((q/4 ^ r/8) & 3))
+    const int r = t & 31, rg = r0 + r, hb = t >> 5;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double* base = tile + r * kRS + (hb ^ ((j ^ (r >> 3)) & 3));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = 4 * j + i, h = hb + 8 * q;
+        base[8 * q] = (rg < rows && h0 + h < k) ? (double)x[q] : 0.0;
+      }
     }
-  } else {      // src[h + r*ld]: 64 consecutive k per wave
-    const int h = t & 127, hg = h0 + h;
-    const T* a = src + min(hg, k - 1);
+  } else {      // element (r = 2q + t/128, h): tile_pos = r*kRS + (h ^ ((h/32 ^ q/4) & 3))
+    const int h = t & 127, hg = h0 + h, rb = t >> 7;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) x[q] = a[(size_t)min(r0 + 2 * q + (t >> 7), rows - 1) * ld];
+    for (int j = 0; j < 4; ++j) {
+      double* base = tile + rb * kRS + (h ^ (((h >> 5) ^ j) & 3));
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int r = 2 * q + (t >> 7), rg = r0 + r;
-      tile[r * kRS + (h ^ (r >> 3))] = (rg < rows && hg < k) ? (double)x[q] : 0.0;
+      for (int i = 0; i < 4; ++i) {
+        const int q = 4 * j + i, rg = r0 + 2 * q + rb;
+        base[2 * q * kRS] = (rg < rows && hg < k) ? (double)x[q] : 0.0;
+      }
     }
   }
-  __syncthreads();
+}
 
-  const int r = t >> 3, c = t & 7, rg = r0 + r, sw = r >> 3;
+// Each thread reads 16 consecutive k of one row from the staged tile and
+// writes 16 bytes per slice (mode 0: Abar; mode 1: the N residues).
+// Residue paths of mode 1: limbs (2 or 3) or exact reduction steps (1-4);
+// kAnyPath chooses at run time from the constants (grouped launches, whose
+// problems differ in N).
+enum ResiduePath { kLimbs2, kLimbs3, kSteps1, kSteps2, kSteps3, kSteps4, kAnyPath };
+
+int residue_path(const CrtConsts& cc) {
+  if (cc.nlimbs == 2) return kLimbs2;
+  if (cc.nlimbs == 3) return kLimbs3;
+  return cc.nsteps <= 1 ? kSteps1 : cc.nsteps == 2 ? kSteps2 : cc.nsteps == 3 ? kSteps3 : kSteps4;
+}
+
+template <int PATH>
+__device__ __forceinline__ void store_residues_path(const double (&v)[16], const CrtConsts& cc,
+                                                    int8_t* __restrict__ dst, size_t slice) {
+  switch (PATH) {
+    case kLimbs2: store_residues_limbs<2>(v, cc, dst, slice); break;
+    case kLimbs3: store_residues_limbs<3>(v, cc, dst, slice); break;
+    case kSteps1: store_residues<1>(v, cc, dst, slice); break;
+    case kSteps2: store_residues<2>(v, cc, dst, slice); break;
+    case kSteps3: store_residues<3>(v, cc, dst, slice); break;
+    case kSteps4: store_residues<4>(v, cc, dst, slice); break;
+    default:
+      if (cc.nlimbs == 2) {          // uniform branches
+        store_residues_limbs<2>(v, cc, dst, slice);
+      } else if (cc.nlimbs == 3) {
+        store_residues_limbs<3>(v, cc, dst, slice);
+      } else {
+        switch (cc.nsteps) {
+          case 1: store_residues<1>(v, cc, dst, slice); break;
+          case 2: store_residues<2>(v, cc, dst, slice); break;
+          case 3: store_residues<3>(v, cc, dst, slice); break;
+          default: store_residues<4>(v, cc, dst, slice); break;
+        }
+      }
+  }
+}
+
+template <int MODE, int PATH>
+__device__ __forceinline__ void tile_finish(const double* tile, int64_t aux, int rows, int k_pad,
+                                            size_t slice, const CrtConsts& cc,
+                                            int8_t* __restrict__ out, int r0, int h0) {
+  const int t = threadIdx.x;
+  const int r = t >> 3, c = t & 7, rg = r0 + r;
+  // element (r, 16c + e): tile_pos = r*kRS + 16c + 4(e/4) + ((e%4) ^ g)
+  const int g = ((c >> 1) ^ (r >> 3)) & 3;
   double v[16];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int el = (e + c) & 15;
-    v[el] = tile[r * kRS + ((16 * c + el) ^ sw)];
+  for (int el = 0; el < 4; ++el) {
+    const double* base = tile + r * kRS + 16 * c + (el ^ g);
+#pragma unroll
+    for (int eh = 0; eh < 4; ++eh) v[4 * eh + el] = base[4 * eh];
   }
   int8_t* dst = out + (size_t)rg * k_pad + h0 + 16 * c;
 
   if (MODE == 0) {
-    const int sh = rg < rows ? shift_prime_bits(bits[rg]) : 0;
+    const int sh = rg < rows ? shift_prime_bits((uint64_t)aux) : 0;
     int b[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -177,34 +264,21 @@ __device__ __forceinline__ void slices_body(const T* __restrict__ src, int ld, i
     w.z = pack4(b[8], b[9], b[10], b[11]);
     w.w = pack4(b[12], b[13], b[14], b[15]);
     *reinterpret_cast<uint4*>(dst) = w;
-  } else {
-    if (rg >= rows) return;   // after the only barrier
-    const int sh = shift[rg];
+  } else if (rg < rows) {
+    const int sh = (int)aux;
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = trunc(ldexp(v[e], sh));
-    if (cc.nlimbs == 2) {          // uniform branches
-      store_residues_limbs<2>(v, cc, dst, slice);
-    } else if (cc.nlimbs == 3) {
-      store_residues_limbs<3>(v, cc, dst, slice);
-    } else {
-      switch (cc.nsteps) {
-        case 1: store_residues<1>(v, cc, dst, slice); break;
-        case 2: store_residues<2>(v, cc, dst, slice); break;
-        case 3: store_residues<3>(v, cc, dst, slice); break;
-        default: store_residues<4>(v, cc, dst, slice); break;
-      }
-    }
+    store_residues_path<PATH>(v, cc, dst, slice);
   }
 }
 
-// Tile order of workgroup b: for the column-major A side (TRANS) row tiles
-// vary fastest, so workgroups running together read neighbouring 256-byte
-// pieces of the same columns (DRAM pages); for B, whose rows are contiguous
-// in k, k tiles vary fastest.
+// Tile b of an operand with gy row tiles of 32: for the column-major A side
+// (TRANS) row tiles vary fastest, so workgroups running together read
+// neighbouring 256-byte pieces of the same columns (DRAM pages); for B, whose
+// rows are contiguous in k, k tiles vary fastest.
 template <bool TRANS>
-__device__ inline void slice_tile(int b, int k_pad, int rows_pad, int* kx, int* ry) {
+__device__ inline void slice_tile(int b, int k_pad, int gy, int* kx, int* ry) {
   if (TRANS) {
-    const int gy = rows_pad / kTR;
     *kx = b / gy;
     *ry = b % gy;
   } else {
@@ -214,32 +288,112 @@ __device__ inline void slice_tile(int b, int k_pad, int rows_pad, int* kx, int* 
   }
 }
 
-template <typename T, bool TRANS, int MODE>
+// Grid-stride loop over `tiles` tiles (row tiles: gy; mode 1 leaves out the
+// tiles of padding rows, whose residues no product of real rows reads; Abar
+// and Bbar padding must stay zero, since the scaling product's maxima cover
+// whole rows and columns).  Each workgroup stages tile i in LDS, issues the
+// loads of its next tile, and only then computes and stores tile i, so that
+// HBM reads overlap the residue arithmetic.
+template <typename T, bool TRANS, int MODE, int PATH>
 __global__ __launch_bounds__(256) void k_slices(const T* __restrict__ src, int ld, int rows, int k,
-                                                int k_pad, size_t slice, const uint64_t* __restrict__ bits,
-                                                const int* __restrict__ shift, CrtConsts cc,
+                                                int k_pad, int gy, int tiles, size_t slice,
+                                                const void* __restrict__ aux, CrtConsts cc,
                                                 int8_t* __restrict__ out) {
+  __shared__ double tile[kTR * kRS];
+  int i = blockIdx.x;
+  if (i >= tiles) return;
   int kx, ry;
-  slice_tile<TRANS>(blockIdx.x, k_pad, (int)(slice / k_pad), &kx, &ry);
-  slices_body<T, TRANS, MODE>(src, ld, rows, k, k_pad, slice, bits, shift, cc, out, kx, ry);
+  slice_tile<TRANS>(i, k_pad, gy, &kx, &ry);
+  T x[16];
+  tile_loads<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x);
+  int64_t xa = row_aux<MODE>(aux, rows, ry * kTR);
+  for (;;) {
+    const int r0 = ry * kTR, h0 = kx * kTK;
+    lds_barrier();                 // every wave is done with the previous tile
+    tile_stage<T, TRANS>(x, rows, k, r0, h0, tile);
+    __asm__ volatile("" ::: "memory");  // x is free: the next loads reuse its registers
+    const int64_t a = xa;
+    const int ni = i + (int)gridDim.x;
+    if (ni < tiles) {
+      slice_tile<TRANS>(ni, k_pad, gy, &kx, &ry);
+      tile_loads<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x);
+      xa = row_aux<MODE>(aux, rows, ry * kTR);
+    }
+    lds_barrier();                 // the tile is staged
+    tile_finish<MODE, PATH>(tile, a, rows, k_pad, slice, cc, out, r0, h0);
+    if (ni >= tiles) break;
+    i = ni;
+  }
 }
 
-// Grouped: A side (TRANS, rows = m) or B side (rows = n) of every problem.
+// One tile of the grouped launch: which problem side and where.
+struct TileJob {
+  const void* src;
+  const void* aux;
+  int8_t* out;
+  size_t slice;
+  int ld, rows, k, k_pad, r0, h0, N;
+};
+
+// Map entry i of the grouped launch; false for a mode-1 tile of padding rows.
+template <bool ASIDE, int MODE>
+__device__ __forceinline__ bool tile_job(const ProbDesc* __restrict__ P,
+                                         const BlockRef* __restrict__ map, int i, TileJob* j) {
+  const BlockRef e = map[i];
+  const ProbDesc& d = P[e.x];
+  const int rows = ASIDE ? d.m : d.n, rows_pad = ASIDE ? d.mp : d.np;
+  int kx, ry;
+  slice_tile<ASIDE>(e.y, d.kp, rows_pad / kTR, &kx, &ry);
+  j->r0 = ry * kTR;
+  j->h0 = kx * kTK;
+  if (MODE == 1 && j->r0 >= rows) return false;
+  j->src = ASIDE ? d.A : d.B;
+  j->aux = MODE == 0 ? (const void*)(ASIDE ? d.rowbits : d.colbits)
+                     : (const void*)(ASIDE ? d.mu : d.nu);
+  j->out = ASIDE ? d.As : d.Bs;
+  j->slice = (size_t)rows_pad * d.kp;
+  j->ld = ASIDE ? d.lda : d.ldb;
+  j->rows = rows;
+  j->k = d.k;
+  j->k_pad = d.kp;
+  j->N = d.N;
+  return true;
+}
+
+// Grouped: A side (TRANS, rows = m) or B side (rows = n) of every problem;
+// the same grid-stride loop over the `tiles` entries of the block map.
 template <typename T, bool ASIDE, int MODE>
 __global__ __launch_bounds__(256) void kg_slices(const ProbDesc* __restrict__ P,
-                                                 const BlockRef* __restrict__ map,
+                                                 const BlockRef* __restrict__ map, int tiles,
                                                  const CrtConsts* __restrict__ ctab) {
-  const BlockRef e = map[blockIdx.x];
-  const ProbDesc& d = P[e.x];
-  int kx, ry;
-  if (ASIDE) {
-    slice_tile<true>(e.y, d.kp, d.mp, &kx, &ry);
-    slices_body<T, true, MODE>((const T*)d.A, d.lda, d.m, d.k, d.kp, (size_t)d.mp * d.kp,
-                               d.rowbits, d.mu, ctab[d.N], d.As, kx, ry);
-  } else {
-    slice_tile<false>(e.y, d.kp, d.np, &kx, &ry);
-    slices_body<T, false, MODE>((const T*)d.B, d.ldb, d.n, d.k, d.kp, (size_t)d.np * d.kp,
-                                d.colbits, d.nu, ctab[d.N], d.Bs, kx, ry);
+  __shared__ double tile[kTR * kRS];
+  const int G = (int)gridDim.x;
+  int i = blockIdx.x;
+  TileJob cur;
+  while (i < tiles && !tile_job<ASIDE, MODE>(P, map, i, &cur)) i += G;
+  if (i >= tiles) return;
+  T x[16];
+  tile_loads<T, ASIDE>(static_cast<const T*>(cur.src), cur.ld, cur.rows, cur.k, cur.r0, cur.h0, x);
+  int64_t xa = row_aux<MODE>(cur.aux, cur.rows, cur.r0);
+  for (;;) {
+    lds_barrier();
+    tile_stage<T, ASIDE>(x, cur.rows, cur.k, cur.r0, cur.h0, tile);
+    __asm__ volatile("" ::: "memory");
+    const int64_t a = xa;
+    TileJob nxt;
+    int ni = i + G;
+    while (ni < tiles && !tile_job<ASIDE, MODE>(P, map, ni, &nxt)) ni += G;
+    if (ni < tiles) {
+      tile_loads<T, ASIDE>(static_cast<const T*>(nxt.src), nxt.ld, nxt.rows, nxt.k, nxt.r0,
+                           nxt.h0, x);
+      xa = row_aux<MODE>(nxt.aux, nxt.rows, nxt.r0);
+    }
+    lds_barrier();
+    tile_finish<MODE, kAnyPath>(tile, a, cur.rows, cur.k_pad, cur.slice, ctab[cur.N], cur.out, cur.r0,
+                      cur.h0);
+    if (ni >= tiles) break;
+    i = ni;
+    cur = nxt;
   }
 }
 
@@ -293,40 +447,128 @@ __global__ __launch_bounds__(256) void k_plan_slices(const T* __restrict__ src, 
   if ((t & 3) == 0) partial[(size_t)blockIdx.x * rows_pad + rg] = sum;
 }
 
+// Resident workgroups per compute unit of each slice kernel and compute
+// units per device, filled once per device by init_slice_launch (outside
+// any stream capture); a grid-stride launch uses at most that many
+// workgroups.  Index: [float][trans / A side][variant], variant 0 = mode 0,
+// 1 + path = mode 1 on that residue path, 7 / 8 = grouped mode 0 / 1.
+constexpr int kMaxDevices = 64;
+constexpr int kVariants = 9;
+std::atomic<int> g_cus[kMaxDevices];
+std::atomic<int> g_occ[2][2][kVariants];
+
+template <typename K>
+int resident_per_cu(K* kern) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kern), 256, 0) !=
+          hipSuccess ||
+      n < 1)
+    n = 1;
+  return n;
+}
+
+template <typename T, bool TR>
+void fill_occ() {
+  std::atomic<int>* o = g_occ[std::is_same<T, float>::value ? 1 : 0][TR ? 1 : 0];
+  o[0] = resident_per_cu(k_slices<T, TR, 0, kAnyPath>);
+  o[1 + kLimbs2] = resident_per_cu(k_slices<T, TR, 1, kLimbs2>);
+  o[1 + kLimbs3] = resident_per_cu(k_slices<T, TR, 1, kLimbs3>);
+  o[1 + kSteps1] = resident_per_cu(k_slices<T, TR, 1, kSteps1>);
+  o[1 + kSteps2] = resident_per_cu(k_slices<T, TR, 1, kSteps2>);
+  o[1 + kSteps3] = resident_per_cu(k_slices<T, TR, 1, kSteps3>);
+  o[1 + kSteps4] = resident_per_cu(k_slices<T, TR, 1, kSteps4>);
+  o[7] = resident_per_cu(kg_slices<T, TR, 0>);
+  o[8] = resident_per_cu(kg_slices<T, TR, 1>);
+}
+
+// Workgroups for `tiles` tiles: all resident slots of the device, or one per
+// tile if the device's figures are unknown.
+int slice_grid(bool f32, bool trans, int variant, int tiles) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return tiles;
+  const int cus = g_cus[dev].load(std::memory_order_relaxed);
+  const int occ = g_occ[f32 ? 1 : 0][trans ? 1 : 0][variant].load(std::memory_order_relaxed);
+  if (cus <= 0 || occ <= 0) return tiles;
+  return (int)std::min<int64_t>(tiles, (int64_t)cus * occ);
+}
+
+template <typename T>
+struct SliceLaunch {
+  const T* src;
+  int ld, rows, k, k_pad, gy, tiles;
+  size_t slice;
+  const void* aux;
+  int8_t* out;
+};
+
+template <typename T, bool TR, int MODE, int PATH>
+void launch_one(hipStream_t s, const SliceLaunch<T>& L, const CrtConsts& cc) {
+  const int variant = MODE == 0 ? 0 : 1 + PATH;
+  const dim3 grid((unsigned)slice_grid(std::is_same<T, float>::value, TR, variant, L.tiles));
+  hipLaunchKernelGGL((k_slices<T, TR, MODE, PATH>), grid, dim3(256), 0, s, L.src, L.ld, L.rows,
+                     L.k, L.k_pad, L.gy, L.tiles, L.slice, L.aux, cc, L.out);
+}
+
+template <typename T, bool TR>
+void launch_side(hipStream_t s, int mode, const SliceLaunch<T>& L, const CrtConsts& cc) {
+  if (mode == 0) {
+    launch_one<T, TR, 0, kAnyPath>(s, L, cc);
+    return;
+  }
+  switch (residue_path(cc)) {
+    case kLimbs2: launch_one<T, TR, 1, kLimbs2>(s, L, cc); break;
+    case kLimbs3: launch_one<T, TR, 1, kLimbs3>(s, L, cc); break;
+    case kSteps1: launch_one<T, TR, 1, kSteps1>(s, L, cc); break;
+    case kSteps2: launch_one<T, TR, 1, kSteps2>(s, L, cc); break;
+    case kSteps3: launch_one<T, TR, 1, kSteps3>(s, L, cc); break;
+    default: launch_one<T, TR, 1, kSteps4>(s, L, cc); break;
+  }
+}
+
 template <typename T>
 void launch_t(hipStream_t s, int mode, bool trans, const T* src, int ld, int rows, int k,
               int rows_pad, int k_pad, const uint64_t* bits, const int* shift, const CrtConsts& cc,
               int8_t* out) {
-  dim3 grid((unsigned)((k_pad / kTK) * (rows_pad / kTR)));
-  size_t slice = (size_t)rows_pad * k_pad;
-  if (mode == 0) {
-    if (trans)
-      hipLaunchKernelGGL((k_slices<T, true, 0>), grid, dim3(256), 0, s, src, ld, rows, k, k_pad,
-                         slice, bits, shift, cc, out);
-    else
-      hipLaunchKernelGGL((k_slices<T, false, 0>), grid, dim3(256), 0, s, src, ld, rows, k, k_pad,
-                         slice, bits, shift, cc, out);
-  } else {
-    if (trans)
-      hipLaunchKernelGGL((k_slices<T, true, 1>), grid, dim3(256), 0, s, src, ld, rows, k, k_pad,
-                         slice, bits, shift, cc, out);
-    else
-      hipLaunchKernelGGL((k_slices<T, false, 1>), grid, dim3(256), 0, s, src, ld, rows, k, k_pad,
-                         slice, bits, shift, cc, out);
-  }
+  SliceLaunch<T> L;
+  L.src = src;
+  L.ld = ld;
+  L.rows = rows;
+  L.k = k;
+  L.k_pad = k_pad;
+  L.gy = mode == 0 ? rows_pad / kTR : cdiv_i(rows, kTR);
+  L.tiles = (k_pad / kTK) * L.gy;
+  L.slice = (size_t)rows_pad * k_pad;
+  L.aux = mode == 0 ? (const void*)bits : (const void*)shift;
+  L.out = out;
+  if (L.tiles <= 0) return;
+  if (trans)
+    launch_side<T, true>(s, mode, L, cc);
+  else
+    launch_side<T, false>(s, mode, L, cc);
 }
 
 template <typename T, int MODE>
 void group_slices_t(hipStream_t s, bool aside, const ProbDesc* P, const BlockRef* map, int blocks,
                     const CrtConsts* ctab) {
-  const dim3 g((unsigned)blocks), b(256);
+  const dim3 g((unsigned)slice_grid(std::is_same<T, float>::value, aside, 7 + MODE, blocks)), b(256);
   if (aside)
-    hipLaunchKernelGGL((kg_slices<T, true, MODE>), g, b, 0, s, P, map, ctab);
+    hipLaunchKernelGGL((kg_slices<T, true, MODE>), g, b, 0, s, P, map, blocks, ctab);
   else
-    hipLaunchKernelGGL((kg_slices<T, false, MODE>), g, b, 0, s, P, map, ctab);
+    hipLaunchKernelGGL((kg_slices<T, false, MODE>), g, b, 0, s, P, map, blocks, ctab);
 }
 
 }  // namespace
+
+void init_slice_launch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+  fill_occ<double, true>();
+  fill_occ<double, false>();
+  fill_occ<float, true>();
+  fill_occ<float, false>();
+  g_cus[dev].store(cus, std::memory_order_relaxed);
+}
 
 void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, const ProbDesc* P,
                          const BlockRef* map, int blocks, const CrtConsts* ctab) {
