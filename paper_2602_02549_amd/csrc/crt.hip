@@ -43,6 +43,9 @@ __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw
   // Moduli in groups of 4, loads first (clamped to the last slice); a modulus
   // past N gets weight 0, and fma(0, w, c) = c, so the l-ordered fma chains
   // are unchanged.
+  // An INT8 value w with stored byte b becomes a double without the convert
+  // instruction: the bit pattern 0x43300000:(b ^ 0x80) is 2^52 + w + 128, and
+  // subtracting 2^52 + 128 is exact.
   for (int l0 = 0; l0 < cc.N; l0 += 4) {
     uint64_t wv[4];
 #pragma unroll
@@ -53,9 +56,11 @@ __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw
       const int l = min(l0 + u, cc.N - 1);
       const bool in = l0 + u < cc.N;
       const double s1 = in ? cc.s1[l] : 0.0, s2 = in ? cc.s2[l] : 0.0;
+      const uint64_t biased = wv[u] ^ 0x8080808080808080ull;
 #pragma unroll
       for (int e = 0; e < R; ++e) {
-        const double w = (double)(int8_t)(wv[u] >> (8 * e));
+        const int byte = (int)((biased >> (8 * e)) & 0xFF);
+        const double w = __hiloint2double(0x43300000, byte) - 4503599627370624.0;  // 2^52 + 128
         c1[e] = fma(s1, w, c1[e]);
         if (sizeof(T) == 8) c2[e] = fma(s2, w, c2[e]);
       }

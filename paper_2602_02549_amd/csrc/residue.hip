@@ -18,7 +18,7 @@
 // are exact in FP64.  Up to three 32-bit limbs (N <= 20): v = sum_t v_t 2^(32t)
 // with |v_t| <= 2^31 below the top limb, split once per element; per modulus
 // r = v_0 + sum_t v_t c_t with c_t = mod(2^(32t), p) (exact: |r| < 2^41), and
-// one step r <- fma(-rint(r / p), p, r) lands in [-(p-1)/2, (p-1)/2] for odd
+// one step r <- r - p * round(r / p) lands in [-(p-1)/2, (p-1)/2] for odd
 // p.  Larger N take nsteps such steps from v itself (each exact, shrinking |r|
 // by ~2^-52 relative; the last starts from |r| < 2^50).  For p = 256 the
 // result lies in [-128, 128] and the byte store wraps 128 to -128.
@@ -37,21 +37,50 @@ constexpr int kTK = 128;          // slice tile: k
 constexpr int kRS = kTK + 4;      // LDS row stride (doubles)
 constexpr int kPlanTile = 64;     // planner operand tile
 
+// Rounding to an integer and reading an integer without the FP64 round and
+// convert instructions (which issue at a fraction of the FMA rate): with
+// kRound = 1.5 * 2^52, fma(x, y, kRound) is kRound plus the exact product
+// x*y rounded to the nearest integer (ties to even) whenever |x*y| < 2^51,
+// since doubles in [2^52, 2^53) are the integers; and for an integer-valued
+// |x| < 2^31 the low 32 bits of x + kRound are x in two's complement.
+constexpr double kRound = 0x1.8p52;
+
+__device__ __forceinline__ double round_prod(double x, double y) {
+  return fma(x, y, kRound) - kRound;
+}
+
+__device__ __forceinline__ int int_of(double x) { return __double2loint(x + kRound); }
+
+// One exact reduction step r - p * round(r / p) for |r| < 2^50: the rounded
+// product is the nearest integer to r / p itself, because |r| |pinv - 1/p|
+// <= 2^-3 / p is below the distance 1 / (2p) from r / p to a half-integer
+// (odd p), and pinv is exact for p = 256.  The result lies in
+// [-(p-1)/2, (p-1)/2] for odd p and in [-128, 128] for p = 256.
+__device__ __forceinline__ double reduce_last(double r, double p, double pinv) {
+  return fma(-round_prod(r, pinv), p, r);
+}
+
 // nsteps reduction steps (the last from |r| < 2^50); NS = 1..4 for N <= 49.
+// The earlier steps only shrink |r| exactly, for which rint of the rounded
+// product suffices.
 template <int NS>
 __device__ __forceinline__ int residue_i8(double v, int p, double pinv) {
   double r = v;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
+  for (int s = 0; s + 1 < NS; ++s) {
     const double q = rint(r * pinv);
     r = fma(-q, (double)p, r);
   }
-  return (int)r;
+  return int_of(reduce_last(r, (double)p, pinv));
 }
 
-__device__ inline uint32_t pack4(int a, int b, int c, int d) {
-  return (uint32_t)(a & 0xFF) | ((uint32_t)(b & 0xFF) << 8) | ((uint32_t)(c & 0xFF) << 16) |
-         ((uint32_t)(d & 0xFF) << 24);
+// Low bytes of a, b, c, d as one word (byte 0 = a), three byte permutes:
+// v_perm_b32 picks bytes 0-3 of its second source with selectors 0-3, of its
+// first with 4-7, and zero with 0x0c.
+__device__ __forceinline__ uint32_t pack4(int a, int b, int c, int d) {
+  const uint32_t ab = __builtin_amdgcn_perm((uint32_t)b, (uint32_t)a, 0x0c0c0400u);
+  const uint32_t cd = __builtin_amdgcn_perm((uint32_t)d, (uint32_t)c, 0x0c0c0400u);
+  return __builtin_amdgcn_perm(cd, ab, 0x05040100u);
 }
 
 // The N residue bytes of 16 consecutive k of one row, one 16-byte store per
@@ -75,10 +104,6 @@ __device__ __forceinline__ void store_residues(const double (&v)[16], const CrtC
 }
 
 // Limb form of the residues (L = 2 or 3 limbs of 32 bits).
-__device__ __forceinline__ double reduce_once(double r, double p, double pinv) {
-  return fma(-rint(r * pinv), p, r);
-}
-
 template <int L>
 __device__ __forceinline__ void store_residues_limbs(const double (&v)[16], const CrtConsts& cc,
                                                      int8_t* __restrict__ dst, size_t slice) {
@@ -88,23 +113,23 @@ __device__ __forceinline__ void store_residues_limbs(const double (&v)[16], cons
   for (int e = 0; e < 16; ++e) {
     double rem = v[e];
     if (L == 3) {
-      hi[e] = rint(rem * 0x1p-64);
+      hi[e] = round_prod(rem, 0x1p-64);        // |v| < 2^95
       rem = fma(-hi[e], 0x1p64, rem);          // exact, |rem| <= 2^63
     }
-    mid[e] = rint(rem * 0x1p-32);
+    mid[e] = round_prod(rem, 0x1p-32);
     lo[e] = fma(-mid[e], 0x1p32, rem);         // exact, |lo| <= 2^31
   }
   for (int l = 0; l < cc.N; ++l) {
     const double p = (double)cc.p[l];
     const double pinv = cc.pinv[l];
-    const double c1 = reduce_once(0x1p32, p, pinv);                 // mod(2^32, p)
-    const double c2 = L == 3 ? reduce_once(c1 * c1, p, pinv) : 0.0;  // mod(2^64, p)
+    const double c1 = reduce_last(0x1p32, p, pinv);                 // mod(2^32, p)
+    const double c2 = L == 3 ? reduce_last(c1 * c1, p, pinv) : 0.0;  // mod(2^64, p)
     int b[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       double r = fma(mid[e], c1, lo[e]);
       if (L == 3) r = fma(hi[e], c2, r);
-      b[e] = (int)reduce_once(r, p, pinv);
+      b[e] = int_of(reduce_last(r, p, pinv));
     }
     uint4 w;
     w.x = pack4(b[0], b[1], b[2], b[3]);
