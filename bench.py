@@ -220,6 +220,59 @@ def batched_measurement(torch, oz, steps: int) -> dict:
             "speedup_vs_native": round(res["native"]["ms"] / res["emulated"]["ms"], 3)}
 
 
+def hbm_reference(torch, dev, mib: int = 1024, reps: int = 5) -> dict:
+    """Device copy (read + write) and fill (write) of `mib` MiB timed with
+    events: the practical HBM rates the memory-bound phases are set against."""
+    nel = (mib << 20) // 8
+    src = torch.ones(nel, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    copy_ms = _time_ms(torch, lambda: dst.copy_(src), reps)
+    fill_ms = _time_ms(torch, lambda: dst.fill_(2.0), reps)
+    del src, dst
+    nb = nel * 8
+    return {"copy_GBs": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1),
+            "fill_GBs": round(nb / (fill_ms * 1e-3) / 1e9, 1), "MiB": mib}
+
+
+def memory_phases(torch, dev, phase_ms: dict, m: int, n: int, k: int, N: int, s: int) -> dict:
+    """Achieved GB/s of the memory-bound phases from their algorithmic bytes
+    (s-byte elements; INT8 slices and W without padding) and the HIP-event
+    phase times, against the 8 TB/s peak and a live device copy."""
+    ref = hbm_reference(torch, dev)
+    algo = {
+        "absmax_A": s * m * k, "absmax_B": s * k * n,
+        "bar_A": s * m * k + m * k, "bar_B": s * k * n + k * n,
+        "residue_A": s * m * k + N * m * k, "residue_B": s * k * n + N * k * n,
+        "crt": N * m * n + s * m * n,
+    }
+    out = {"hbm_reference": ref}
+    for name, nbytes in algo.items():
+        if name in phase_ms:
+            gbs = nbytes / (phase_ms[name] * 1e-3) / 1e9
+            out[name] = {"ms": round(phase_ms[name], 4), "GB": round(nbytes / 1e9, 3),
+                         "GBs": round(gbs, 1), "frac_peak": round(gbs / PEAK_HBM_GBS, 3),
+                         "frac_copy": round(gbs / ref["copy_GBs"], 3)}
+    return out
+
+
+def flushed_timing(torch, dev, emulate, N: int, steps: int) -> dict:
+    """Median time of single calls with the 256 MB MALL flushed before each
+    (a 512 MiB fill, outside the event bracket)."""
+    flush = torch.empty((512 << 20) // 8, dtype=torch.float64, device=dev)
+    times = []
+    for _ in range(steps):
+        flush.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        emulate(N)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del flush
+    return {"median_ms": round(float(np.median(times)), 4), "min_ms": round(min(times), 4),
+            "steps": steps, "flush": "512 MiB fill before each call"}
+
+
 def cpu_baseline(size: int, N: int) -> dict:
     """The CPU oracle, as it is, on a bounded sample (size^3, FP64, same
     generator), single-threaded (BLAS limited to one thread)."""
@@ -372,6 +425,9 @@ def main():
         "speedup_vs_native": round(native_ms / ms, 3),
         "phases_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
     }
+    out["int8_fraction_whole_call"] = round((N + 1) * flops / (ms * 1e-3) / 1e12 / PEAK_INT8_TOPS, 4)
+    out["memory_phases"] = memory_phases(torch, dev, phase_ms, m, n, k, N, 8)
+    out["mall_flushed"] = flushed_timing(torch, dev, emulate, N, max(args.steps, 10))
     del Acm, Bcm, Ccm, dA, dB
     torch.cuda.empty_cache()
     if not args.no_batched:

@@ -9,13 +9,14 @@
 // are both read coalesced, then each thread owns 16 consecutive k of one row
 // and writes 16 bytes per slice, 8 threads covering one full 128-byte line.
 // The LDS rows are 132 doubles apart and the low bits of each column index
-// XOR-swizzled (tile_pos): the staging stores and the in-order reads then
-// touch every bank exactly twice per wave (the minimum for 64 x 8 bytes).
+// XOR-swizzled (tile_pos), so that the staging stores and the in-order reads
+// of a wave spread evenly over 64 four-byte banks, and no thread indexes its
+// registers with a per-lane value.
 // Each workgroup walks tiles in a grid-stride loop and issues the loads of
 // its next tile before computing the current one.
 //
 // Residues of the scaled integer v = trunc(2^mu a) (|v| < 2^(6 + floor P'))
-// are exact in FP64.  Up to three 32-bit limbs (N <= 20): v = sum_t v_t 2^(32t)
+// are exact in FP64.  Up to three 32-bit limbs (N <= 23): v = sum_t v_t 2^(32t)
 // with |v_t| <= 2^31 below the top limb, split once per element; per modulus
 // r = v_0 + sum_t v_t c_t with c_t = mod(2^(32t), p) (exact: |r| < 2^41), and
 // one step r <- r - p * round(r / p) lands in [-(p-1)/2, (p-1)/2] for odd
@@ -178,9 +179,9 @@ __device__ __forceinline__ int64_t row_aux(const void* __restrict__ aux, int row
 }
 
 // LDS position of element (r, h) of a tile: rows kRS doubles apart, and the
-// low two bits of h XORed with bits of h / 32 and r / 8.  Both staging
-// patterns and the in-order reads of tile_finish then touch every bank
-// exactly twice per wave (the minimum for 64 lanes x 8 bytes).
+// low two bits of h XORed with bits of h / 32 and r / 8.  Counted over 64
+// four-byte banks, both staging patterns and the in-order reads of
+// tile_finish put exactly two of a wave's 8-byte accesses on each bank.
 __device__ __forceinline__ int tile_pos(int r, int h) {
   return r * kRS + (h ^ (((h >> 5) ^ (r >> 3)) & 3));
 }
