@@ -11,9 +11,11 @@
 // of 4 consecutive rows i are packed into one 32-bit store of the
 // column-major W_l[j][i].
 //
-// Tiling: a 256-thread workgroup (4 waves as 2 x 2) computes a BX x BY tile;
-// each wave owns (BX/2) x (BY/2) as (BX/64) x (BY/64) blocks of 32 x 32
-// (accumulators live in AGPRs for 256 x 256).  K advances in groups of 128
+// Tiling: a workgroup of NWX x NWY waves computes a BX x BY tile; each wave
+// owns (BX/NWX) x (BY/NWY) as blocks of 32 x 32.  A 256 x 256 tile runs 8
+// waves (4 x 2, each 64 x 128: two waves per SIMD, so one wave's MFMAs
+// overlap the other's LDS reads and barrier waits), a 128 x 128 tile 4 waves
+// (2 x 2) with two workgroups per CU.  K advances in groups of 128
 // bytes through two LDS group buffers: direct global->LDS copies fill one
 // (every 128-byte line of an operand row requested as one unit) while the
 // MFMAs consume the other.  BF16 operands (the planner's lower bound of
@@ -98,7 +100,7 @@ __device__ inline int swz(int r) { return (r >> 1) & 7; }
 // rows of 128 bytes.  `bid` is the workgroup's index among the `launched`
 // workgroups of this product (launched >= tiles_x * tiles_y * nz; the
 // surplus exits at once).
-template <int BX, int BY, int EPI, bool BF16>
+template <int BX, int BY, int NWX, int NWY, int EPI, bool BF16>
 __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t sx,
                                           const int8_t* __restrict__ Y, size_t sy, int tiles_x,
                                           int tiles_y, int nz, int k_pad, const CrtConsts& cc,
@@ -106,11 +108,16 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
                                           int* __restrict__ xmax, int* __restrict__ ymax, int bid,
                                           int launched) {
   constexpr int BK = 128;                        // bytes of k per LDS row (one group)
-  constexpr int WX = BX / 2, WY = BY / 2;
+  constexpr int NW = NWX * NWY;                  // waves
+  constexpr int WX = BX / NWX, WY = BY / NWY;
   constexpr int TX = WX / 32, TY = WY / 32;
   constexpr int CPR = BK / 16;                   // 16-byte chunks per LDS row
   constexpr int RPI = 1024 / BK;                 // rows per copy instruction
-  constexpr int IX = BX / RPI / 4, IY = BY / RPI / 4;
+  constexpr int IX = BX / RPI / NW, IY = BY / RPI / NW;
+  // Each wave copies IX (IY) instructions of RPI rows; the chunk swizzle
+  // repeats every 16 rows and the even/odd instruction offsets below assume
+  // that every wave's share starts at a multiple of 16 rows.
+  static_assert(IX % 2 == 0 && IY % 2 == 0 && WX % 32 == 0 && WY % 32 == 0, "tile / wave shape");
   constexpr int GROUP_BYTES = (BX + BY) * BK;    // one 128-k group
   constexpr int GROUP = 8;
   __shared__ __attribute__((aligned(1024))) int8_t lds[2 * GROUP_BYTES];
@@ -134,7 +141,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   const int tx_ = gx0 + t % gsz, ty_ = t / gsz;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wx = wave >> 1, wy = wave & 1;
+  const int wx = wave / NWY, wy = wave % NWY;
   const int x0 = tx_ * BX, y0 = ty_ * BY;
 
   // Copy instruction q of this wave covers rows RPI*q .. RPI*q + RPI - 1 of
@@ -321,45 +328,58 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   finish();
 }
 
-template <int BX, int BY, int OCC, int EPI, bool BF16 = false>
-__global__ __launch_bounds__(256, OCC) void k_gemm_i8(const int8_t* __restrict__ X, size_t sx,
-                                                    const int8_t* __restrict__ Y, size_t sy,
-                                                    int tiles_x, int tiles_y, int nz, int k_pad,
-                                                    CrtConsts cc, int8_t* __restrict__ W, size_t sw,
-                                                    int ldw, int* __restrict__ xmax,
-                                                    int* __restrict__ ymax) {
-  gemm_body<BX, BY, EPI, BF16>(X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax,
-                               ymax, blockIdx.x, gridDim.x);
+// Wave grid and residency of the two tile sizes.
+template <int B>
+struct TileShape;
+template <>
+struct TileShape<256> {
+  static constexpr int NWX = 4, NWY = 2, OCC = 1;
+};
+template <>
+struct TileShape<128> {
+  static constexpr int NWX = 2, NWY = 2, OCC = 2;
+};
+template <int B>
+constexpr int tile_threads() {
+  return 64 * TileShape<B>::NWX * TileShape<B>::NWY;
+}
+
+template <int B, int EPI, bool BF16 = false>
+__global__ __launch_bounds__(tile_threads<B>(), TileShape<B>::OCC) void k_gemm_i8(
+    const int8_t* __restrict__ X, size_t sx, const int8_t* __restrict__ Y, size_t sy, int tiles_x,
+    int tiles_y, int nz, int k_pad, CrtConsts cc, int8_t* __restrict__ W, size_t sw, int ldw,
+    int* __restrict__ xmax, int* __restrict__ ymax) {
+  gemm_body<B, B, TileShape<B>::NWX, TileShape<B>::NWY, EPI, BF16>(
+      X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax, blockIdx.x, gridDim.x);
 }
 
 // Grouped: the scaling product (EPI 1) or the N residue products (EPI 0) of
 // every problem of a batch.
-template <int BX, int BY, int OCC, int EPI>
-__global__ __launch_bounds__(256, OCC) void kg_gemm(const ProbDesc* __restrict__ P,
-                                                    const BlockRef* __restrict__ map,
-                                                    const CrtConsts* __restrict__ ctab) {
-  static_assert(BX == BY, "square tiles");
+template <int B, int EPI>
+__global__ __launch_bounds__(tile_threads<B>(), TileShape<B>::OCC) void kg_gemm(
+    const ProbDesc* __restrict__ P, const BlockRef* __restrict__ map,
+    const CrtConsts* __restrict__ ctab) {
   const BlockRef e = map[blockIdx.x];
   const ProbDesc& d = P[e.x];
   const int nz = EPI == 0 ? d.N : 1;
-  gemm_body<BX, BY, EPI, false>(d.As, EPI == 0 ? (size_t)d.mp * d.kp : 0, d.Bs,
-                                EPI == 0 ? (size_t)d.np * d.kp : 0, d.mp / BX, d.np / BY, nz, d.kp,
-                                ctab[d.N], d.W, (size_t)d.np * d.mp, d.mp, d.rmax, d.cmax, e.y,
-                                group_gemm_blocks(d.mp, d.np, BX, nz));
+  gemm_body<B, B, TileShape<B>::NWX, TileShape<B>::NWY, EPI, false>(
+      d.As, EPI == 0 ? (size_t)d.mp * d.kp : 0, d.Bs, EPI == 0 ? (size_t)d.np * d.kp : 0, d.mp / B,
+      d.np / B, nz, d.kp, ctab[d.N], d.W, (size_t)d.np * d.mp, d.mp, d.rmax, d.cmax, e.y,
+      group_gemm_blocks(d.mp, d.np, B, nz));
 }
 
-template <int BX, int BY, int OCC>
+template <int B>
 void launch_cfg(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                 int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
                 size_t sw, int ldw, int* xmax, int* ymax) {
-  const int tiles_x = nx_pad / BX, tiles_y = ny_pad / BY;
-  dim3 grid((unsigned)(tiles_x * tiles_y * nz));
+  const int tiles_x = nx_pad / B, tiles_y = ny_pad / B;
+  const dim3 grid((unsigned)(tiles_x * tiles_y * nz)), block(tile_threads<B>());
   if (epi == 0)
-    hipLaunchKernelGGL((k_gemm_i8<BX, BY, OCC, 0>), grid, dim3(256), 0, s, X, sx, Y, sy, tiles_x,
-                       tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+    hipLaunchKernelGGL((k_gemm_i8<B, 0>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
+                       k_pad, cc, W, sw, ldw, xmax, ymax);
   else
-    hipLaunchKernelGGL((k_gemm_i8<BX, BY, OCC, 1>), grid, dim3(256), 0, s, X, sx, Y, sy, tiles_x,
-                       tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+    hipLaunchKernelGGL((k_gemm_i8<B, 1>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
+                       k_pad, cc, W, sw, ldw, xmax, ymax);
 }
 
 // Tile configuration: 0 = automatic; 1 = 256x256, 2 = 128x128 (environment
@@ -377,17 +397,19 @@ int forced_cfg() {
 void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const BlockRef* map,
                        int blocks, const CrtConsts* ctab) {
   if (blocks <= 0) return;
-  const dim3 g((unsigned)blocks), b(256);
+  const dim3 g((unsigned)blocks);
   if (tile == 256) {
+    const dim3 b(tile_threads<256>());
     if (epi == 0)
-      hipLaunchKernelGGL((kg_gemm<256, 256, 1, 0>), g, b, 0, s, P, map, ctab);
+      hipLaunchKernelGGL((kg_gemm<256, 0>), g, b, 0, s, P, map, ctab);
     else
-      hipLaunchKernelGGL((kg_gemm<256, 256, 1, 1>), g, b, 0, s, P, map, ctab);
+      hipLaunchKernelGGL((kg_gemm<256, 1>), g, b, 0, s, P, map, ctab);
   } else {
+    const dim3 b(tile_threads<128>());
     if (epi == 0)
-      hipLaunchKernelGGL((kg_gemm<128, 128, 2, 0>), g, b, 0, s, P, map, ctab);
+      hipLaunchKernelGGL((kg_gemm<128, 0>), g, b, 0, s, P, map, ctab);
     else
-      hipLaunchKernelGGL((kg_gemm<128, 128, 2, 1>), g, b, 0, s, P, map, ctab);
+      hipLaunchKernelGGL((kg_gemm<128, 1>), g, b, 0, s, P, map, ctab);
   }
 }
 
@@ -399,14 +421,14 @@ void launch_gemm_bf16_store(hipStream_t s, const uint16_t* X, const uint16_t* Y,
   const long t256 = (long)(nx_pad / 256) * (ny_pad / 256);
   if (nx_pad % 256 == 0 && ny_pad % 256 == 0 && t256 >= 512) {
     const int tiles_x = nx_pad / 256, tiles_y = ny_pad / 256;
-    hipLaunchKernelGGL((k_gemm_i8<256, 256, 1, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
-                       dim3(256), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0, tiles_x, tiles_y,
-                       1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
+    hipLaunchKernelGGL((k_gemm_i8<256, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
+                       dim3(tile_threads<256>()), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0,
+                       tiles_x, tiles_y, 1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
   } else {
     const int tiles_x = nx_pad / 128, tiles_y = ny_pad / 128;
-    hipLaunchKernelGGL((k_gemm_i8<128, 128, 2, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
-                       dim3(256), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0, tiles_x, tiles_y,
-                       1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
+    hipLaunchKernelGGL((k_gemm_i8<128, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
+                       dim3(tile_threads<128>()), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0,
+                       tiles_x, tiles_y, 1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
   }
 }
 
@@ -422,11 +444,9 @@ void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const in
   if (cfg != 1 && cfg != 2) cfg = (fits256 && t256 >= 512) ? 1 : 2;
   if (cfg == 1 && !fits256) cfg = 2;
   if (cfg == 1)
-    launch_cfg<256, 256, 1>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw, xmax,
-                            ymax);
+    launch_cfg<256>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw, xmax, ymax);
   else
-    launch_cfg<128, 128, 2>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw, xmax,
-                            ymax);
+    launch_cfg<128>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw, xmax, ymax);
 }
 
 }  // namespace oz2
