@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
+#include <cstdlib>
 #include <type_traits>
 
 #include "ozaki2_internal.h"
@@ -508,14 +509,22 @@ void fill_occ() {
 }
 
 // Workgroups for `tiles` tiles: all resident slots of the device, or one per
-// tile if the device's figures are unknown.
+// tile if the device's figures are unknown.  The environment variable
+// OZAKI2_SLICE_WORKGROUPS (a test aid, read at every launch) caps the count,
+// so that each workgroup walks many tiles.
 int slice_grid(bool f32, bool trans, int variant, int tiles) {
+  int grid = tiles;
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return tiles;
-  const int cus = g_cus[dev].load(std::memory_order_relaxed);
-  const int occ = g_occ[f32 ? 1 : 0][trans ? 1 : 0][variant].load(std::memory_order_relaxed);
-  if (cus <= 0 || occ <= 0) return tiles;
-  return (int)std::min<int64_t>(tiles, (int64_t)cus * occ);
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
+    const int cus = g_cus[dev].load(std::memory_order_relaxed);
+    const int occ = g_occ[f32 ? 1 : 0][trans ? 1 : 0][variant].load(std::memory_order_relaxed);
+    if (cus > 0 && occ > 0) grid = (int)std::min<int64_t>(tiles, (int64_t)cus * occ);
+  }
+  if (const char* e = getenv("OZAKI2_SLICE_WORKGROUPS")) {
+    const int cap = atoi(e);
+    if (cap > 0) grid = std::min(grid, cap);
+  }
+  return grid;
 }
 
 template <typename T>

@@ -123,6 +123,34 @@ def test_stages_fp32(m, n, k, N, phi):
     run_stage_case(m, n, k, N, phi, seed=m + n + k + N, dtype=np.float32)
 
 
+@pytest.mark.parametrize("cap", ["1", "5"])
+def test_slices_few_workgroups(cap, monkeypatch):
+    # The slice kernels walk their tiles in a grid-stride loop, prefetching the
+    # next tile.  Capped at `cap` workgroups, every workgroup walks many tiles
+    # (with 5, unevenly many).  Every stage stays bit-exact on each residue
+    # path (2 and 3 limbs, one and four exact steps, FP32), and the grouped
+    # kernels of a batch give the oracle's result.
+    monkeypatch.setenv("OZAKI2_SLICE_WORKGROUPS", cap)
+    for m, n, k, N, phi, dt in [(300, 200, 500, 14, 0.5, np.float64), (257, 129, 130, 16, 1.0, np.float64),
+                                (100, 90, 300, 7, 2.0, np.float64), (70, 65, 200, 49, 4.0, np.float64),
+                                (130, 70, 260, 7, 1.0, np.float32)]:
+        run_stage_case(m, n, k, N, phi, seed=int(cap) + m + N, dtype=dt)
+    announce(f"batched with {cap} slice workgroups")
+    cases = [(300, 200, 500, 14), (129, 257, 64, 16), (40, 30, 50, 30)]
+    As, Bs, Ccm = [], [], []
+    for q, (m, n, k, N) in enumerate(cases):
+        A, B = gemm_inputs(m, n, k, phi=1.0, seed=900 + q)
+        As.append(A)
+        Bs.append(B)
+        Ccm.append(torch.full((n, m), float("nan"), dtype=torch.float64, device="cuda:0"))
+    oz.gemm_batched_cm([dev(np.ascontiguousarray(A.T)) for A in As],
+                       [dev(np.ascontiguousarray(B.T)) for B in Bs], Ccm,
+                       [(m, n, k) for m, n, k, _ in cases], [c[3] for c in cases])
+    assert oz.ozaki2_sync_status() == oz.OK
+    for q, (A, B, (m, n, k, N)) in enumerate(zip(As, Bs, cases)):
+        assert np.array_equal(host(Ccm[q]).T, os_ii(A, B, N)), f"batched problem {q}"
+
+
 def test_leading_dimensions_and_views():
     # lda > m, ldb > k, ldc > m through the raw C ABI (submatrices of bigger buffers).
     announce("leading dimensions m=90 n=70 k=110 N=13")
