@@ -415,8 +415,6 @@ struct BatchEntry {
   }
 };
 
-int64_t pad8(int64_t v) { return (v + 7) / 8 * 8; }
-
 int env_int(const char* name, int dflt) {
   const char* e = getenv(name);
   return e ? atoi(e) : dflt;

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void kg_or_status(const ProbDesc* __restrict__
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_fill_zero(T* __restrict__ C, int ldc, int m, int n,
+__global__ __launch_bounds__(256) void k_fill_zero(T* __restrict__ C, int ldc, int m,
                                                    int iblocks) {
   const int j = blockIdx.x / iblocks;
   const int i = (blockIdx.x % iblocks) * 256 + threadIdx.x;
@@ -186,9 +186,9 @@ void launch_fill_zero(hipStream_t s, Prec pr, void* C, int ldc, int m, int n) {
   const int iblocks = (m + 255) / 256;
   dim3 grid((unsigned)iblocks * (unsigned)n);
   if (pr == Prec::F64)
-    hipLaunchKernelGGL(k_fill_zero<double>, grid, dim3(256), 0, s, (double*)C, ldc, m, n, iblocks);
+    hipLaunchKernelGGL(k_fill_zero<double>, grid, dim3(256), 0, s, (double*)C, ldc, m, iblocks);
   else
-    hipLaunchKernelGGL(k_fill_zero<float>, grid, dim3(256), 0, s, (float*)C, ldc, m, n, iblocks);
+    hipLaunchKernelGGL(k_fill_zero<float>, grid, dim3(256), 0, s, (float*)C, ldc, m, iblocks);
 }
 
 }  // namespace oz2

@@ -9,7 +9,7 @@
 // are both read coalesced, then each thread owns 16 consecutive k of one row
 // and writes 16 bytes per slice, 8 threads covering one full 128-byte line.
 // The LDS rows are 132 doubles apart and the low bits of each column index
-// XOR-swizzled (tile_pos), so that the staging stores and the in-order reads
+// XOR-swizzled, so that the staging stores and the in-order reads
 // of a wave spread evenly over 64 four-byte banks, and no thread indexes its
 // registers with a per-lane value.
 // Each workgroup walks tiles in a grid-stride loop and issues the loads of
@@ -179,23 +179,24 @@ __device__ __forceinline__ int64_t row_aux(const void* __restrict__ aux, int row
   return static_cast<const int*>(aux)[rg];
 }
 
-// LDS position of element (r, h) of a tile: rows kRS doubles apart, and the
-// low two bits of h XORed with bits of h / 32 and r / 8.  Counted over 64
-// four-byte banks, both staging patterns and the in-order reads of
-// tile_finish put exactly two of a wave's 8-byte accesses on each bank.
-__device__ __forceinline__ int tile_pos(int r, int h) {
-  return r * kRS + (h ^ (((h >> 5) ^ (r >> 3)) & 3));
-}
+// LDS position of element (r, h) of a tile:
+//   r * kRS + (h ^ (((h / 32) ^ (r / 8)) & 3)),
+// rows kRS doubles apart and the low two bits of h XORed with bits of h / 32
+// and r / 8.  Counted over 64 four-byte banks, both staging patterns and the
+// in-order reads of tile_finish put exactly two of a wave's 8-byte accesses
+// on each bank.  tile_stage and tile_finish address it as four base
+// addresses plus constant offsets (the XOR term is constant within each
+// group of four steps).
 
 // Writes the thread's 16 elements into the LDS tile (zero outside the matrix).
-// Within each group of four steps q the XOR term of tile_pos is constant
+// Within each group of four steps q the XOR term of the position map is constant
 // (h / 32 and r / 8 depend on q / 4 only), so the positions are four bases
 // plus constant offsets.
 template <typename T, bool TRANS>
 __device__ __forceinline__ void tile_stage(const T (&x)[16], int rows, int k, int r0, int h0,
                                            double* tile) {
   const int t = threadIdx.x;
-  if (TRANS) {  // element (r, h = hb + 8q): tile_pos = r*kRS + 8q + (hb ^ ((q/4 ^ r/8) & 3))
+  if (TRANS) {  // element (r, h = hb + 8q): position r*kRS + 8q + (hb ^ ((q/4 ^ r/8) & 3))
     const int r = t & 31, rg = r0 + r, hb = t >> 5;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -206,7 +207,7 @@ __device__ __forceinline__ void tile_stage(const T (&x)[16], int rows, int k, in
         base[8 * q] = (rg < rows && h0 + h < k) ? (double)x[q] : 0.0;
       }
     }
-  } else {      // element (r = 2q + t/128, h): tile_pos = r*kRS + (h ^ ((h/32 ^ q/4) & 3))
+  } else {      // element (r = 2q + t/128, h): position r*kRS + (h ^ ((h/32 ^ q/4) & 3))
     const int h = t & 127, hg = h0 + h, rb = t >> 7;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -265,7 +266,7 @@ __device__ __forceinline__ void tile_finish(const double* tile, int64_t aux, int
                                             int8_t* __restrict__ out, int r0, int h0) {
   const int t = threadIdx.x;
   const int r = t >> 3, c = t & 7, rg = r0 + r;
-  // element (r, 16c + e): tile_pos = r*kRS + 16c + 4(e/4) + ((e%4) ^ g)
+  // element (r, 16c + e): position r*kRS + 16c + 4(e/4) + ((e%4) ^ g)
   const int g = ((c >> 1) ^ (r >> 3)) & 3;
   double v[16];
 #pragma unroll
