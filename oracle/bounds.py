@@ -20,6 +20,12 @@ the N-dependent part
 relative to S_ij = (|A||B|)_ij: N is the smallest value in [2, 49] with
 max_ij T_ij(N) / S_ij <= eps (entries with S_ij = 0 are exact and skipped).
 Row and column powers of two are factored out (R18) so nothing overflows.
+
+A-posteriori certification: after a run, Lemma 4 bounds the unknown |A'B'| of
+est1 by the computed C'' (|A'B'| <= (|C''| + R_const) / (1 - R_rel)), so est1
+itself, output rounding included, can be evaluated from the output; a target
+eps is certified when est1_ij <= eps (|A||B|)_ij on every entry with
+(|A||B|)_ij > 0, and adaptive N steps N up until it is.
 """
 from __future__ import annotations
 
@@ -50,39 +56,106 @@ def R_rel(const) -> Fraction:
     return 3 * U64 if const.b == 64 else U32
 
 
-def theorem1(A: np.ndarray, B: np.ndarray, st: dict, ApBp=None):
-    """Per-entry est1 (if ApBp, the exact A'B', is given) and est2 as mpf arrays.
-
-    `st` is the stage dict of oracle.ozaki2.os_ii (full or row/col subset).
-    """
+def _bound_parts(A: np.ndarray, B: np.ndarray, st: dict):
+    """The N-dependent pieces of eq. (thm:err-1) per entry, as mpf arrays:
+    base = t |A| v (2^beta')^T + t 2^alpha' v^T |B| and tt = t^2 2^alpha' (2^beta')^T,
+    plus the constants R_const and R_rel of Lemma 4 and k.  Entries whose row
+    or column maximum of Cbar is 0 are exact zeros (R7) and get None."""
     const = st["const"]
     rows, cols = st["rows"], st["cols"]
     k = A.shape[1]
     A64, B64 = np.abs(A.astype(np.float64)), np.abs(B.astype(np.float64))
     alpha = _alpha(A64.max(axis=1))[rows]
     beta = _alpha(B64.max(axis=0))[cols]
+    P = mpmath.mpf(const.P)
+    t = 1 / mpmath.sqrt(32 * (P - 1))
+    Rc = mpmath.mpf(R_const(const).numerator) / R_const(const).denominator
+    Rr = mpmath.mpf(R_rel(const).numerator) / R_rel(const).denominator
+    rsum = [mpmath.fsum(mpmath.mpf(float(v)) for v in A64[i]) for i in rows]
+    csum = [mpmath.fsum(mpmath.mpf(float(v)) for v in B64[:, j]) for j in cols]
+    a2 = [mpmath.ldexp(mpmath.sqrt(int(M)), int(al)) for M, al in zip(st["rmax"], alpha)]
+    b2 = [mpmath.ldexp(mpmath.sqrt(int(M)), int(be)) for M, be in zip(st["cmax"], beta)]
+    base = np.empty((len(rows), len(cols)), dtype=object)
+    tt = np.empty((len(rows), len(cols)), dtype=object)
+    for x in range(len(rows)):
+        for y in range(len(cols)):
+            if st["rmax"][x] == 0 or st["cmax"][y] == 0:
+                base[x, y] = tt[x, y] = None
+                continue
+            base[x, y] = t * rsum[x] * b2[y] + t * a2[x] * csum[y]
+            tt[x, y] = t * t * a2[x] * b2[y]
+    return base, tt, Rc, Rr, P, k
+
+
+def theorem1(A: np.ndarray, B: np.ndarray, st: dict, ApBp=None):
+    """Per-entry est1 (if ApBp, the exact A'B', is given) and est2 as mpf arrays.
+
+    `st` is the stage dict of oracle.ozaki2.os_ii (full or row/col subset).
+    """
     with mpmath.workprec(160):
-        P = mpmath.mpf(const.P)
-        t = 1 / mpmath.sqrt(32 * (P - 1))
-        Rc = mpmath.mpf(R_const(const).numerator) / R_const(const).denominator
-        Rr = mpmath.mpf(R_rel(const).numerator) / R_rel(const).denominator
-        rsum = [mpmath.fsum(mpmath.mpf(float(v)) for v in A64[i]) for i in rows]
-        csum = [mpmath.fsum(mpmath.mpf(float(v)) for v in B64[:, j]) for j in cols]
-        a2 = [mpmath.ldexp(mpmath.sqrt(int(M)), int(al)) for M, al in zip(st["rmax"], alpha)]
-        b2 = [mpmath.ldexp(mpmath.sqrt(int(M)), int(be)) for M, be in zip(st["cmax"], beta)]
-        est1 = np.empty((len(rows), len(cols)), dtype=object)
-        est2 = np.empty((len(rows), len(cols)), dtype=object)
-        for x in range(len(rows)):
-            for y in range(len(cols)):
-                if st["rmax"][x] == 0 or st["cmax"][y] == 0:
-                    est1[x, y] = est2[x, y] = mpmath.mpf(0)   # exact zero output (R7)
-                    continue
-                base = t * rsum[x] * b2[y] + t * a2[x] * csum[y]
-                tt = t * t * a2[x] * b2[y]
-                est2[x, y] = base + (k + Rc + Rr * P / 2) * tt
-                if ApBp is not None:
-                    est1[x, y] = base + (k + Rc + Rr * abs(int(ApBp[x, y]))) * tt
+        base, tt, Rc, Rr, P, k = _bound_parts(A, B, st)
+        est1 = np.empty(base.shape, dtype=object)
+        est2 = np.empty(base.shape, dtype=object)
+        for idx in np.ndindex(base.shape):
+            if base[idx] is None:
+                est1[idx] = est2[idx] = mpmath.mpf(0)   # exact zero output (R7)
+                continue
+            est2[idx] = base[idx] + (k + Rc + Rr * P / 2) * tt[idx]
+            if ApBp is not None:
+                est1[idx] = base[idx] + (k + Rc + Rr * abs(int(ApBp[idx]))) * tt[idx]
         return (est1 if ApBp is not None else None), est2
+
+
+def est1_a_posteriori(A: np.ndarray, B: np.ndarray, st: dict):
+    """est1 of eq. (thm:err-1) evaluated after the run, per entry (mpf).
+
+    |A'B'| is not known, but Lemma 4, |A'B' - C''| <= R_const + R_rel |A'B'|,
+    bounds it by the computed C'': |A'B'| <= (|C''| + R_const) / (1 - R_rel).
+    The result is therefore a bound on |AB - C| that needs only the output
+    (and is at least est1 with the exact |A'B'|)."""
+    with mpmath.workprec(160):
+        base, tt, Rc, Rr, P, k = _bound_parts(A, B, st)
+        out = np.empty(base.shape, dtype=object)
+        for idx in np.ndindex(base.shape):
+            if base[idx] is None:
+                out[idx] = mpmath.mpf(0)
+                continue
+            cpp = abs(mpmath.mpf(float(st["Cpp"][idx])))
+            apbp = (cpp + Rc) / (1 - Rr)
+            out[idx] = base[idx] + (k + Rc + Rr * apbp) * tt[idx]
+        return out
+
+
+def certified_ratio(A: np.ndarray, B: np.ndarray, st: dict) -> float:
+    """max_ij est1_ij / (|A||B|)_ij over the entries of `st` with (|A||B|)_ij > 0
+    (a-posteriori est1; exact |A||B|); 0.0 if there is none."""
+    from .exact import exact_abs_product
+    est = est1_a_posteriori(A, B, st)
+    S = exact_abs_product(A, B, st["rows"], st["cols"])
+    best = mpmath.mpf(0)
+    with mpmath.workprec(160):
+        for idx in np.ndindex(est.shape):
+            if S[idx] > 0:
+                s = mpmath.mpf(S[idx].numerator) / S[idx].denominator
+                best = max(best, est[idx] / s)
+    return float(best)
+
+
+def certified_moduli(A: np.ndarray, B: np.ndarray, eps: float, N_start: int, rows=None, cols=None):
+    """Adaptive N (a-posteriori certification): starting at N_start, run
+    Algorithm 1 and step N up until certified_ratio <= eps.  Returns
+    (N, certified, ratio at N); N = the largest admissible N when the target
+    is never certified.  With rows/cols the check covers only those entries."""
+    from .ozaki2 import os_ii
+    b = 64 if A.dtype == np.float64 else 32
+    nmax = N_MAX if b == 64 else 16
+    ratio = None
+    for N in range(max(N_start, N_MIN), nmax + 1):
+        _, st = os_ii(A, B, N, rows=rows, cols=cols, stages=True)
+        ratio = certified_ratio(A, B, st)
+        if ratio <= eps:
+            return N, True, ratio
+    return nmax, False, ratio
 
 
 def planner_terms(A: np.ndarray, B: np.ndarray):
