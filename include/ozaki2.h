@@ -93,6 +93,40 @@ int ozaki2_sgemm(int m, int n, int k, const float *A, int lda, const float *B, i
 int ozaki2_required_moduli(int prec, int m, int n, int k, const void *A, int lda, const void *B,
                            int ldb, double eps, int *N_out);
 
+/*
+ * ozaki2_gemm_certified - C := A*B like ozaki2_gemm (prec 64) or ozaki2_sgemm
+ * (prec 32), with N chosen so that the whole Theorem 1 bound est1
+ * (eq. thm:err-1, output rounding included) is at most eps times
+ * (|A||B|)_ij on every entry with a nonzero (|A||B|)_ij, certified after the
+ * run: the |A'B'| that est1 contains is bounded through Lemma 4 by the
+ * computed C'', |A'B'| <= (|C''| + R_const) / (1 - R_rel).  Starting at
+ * N_start (0: the N of ozaki2_required_moduli, never above the certified
+ * one), the call runs Algorithm 1, evaluates est1 and, if some entry misses
+ * eps, runs again with N + 1.
+ *   eps     : target (> 0).  FP64 output rounding alone makes est1 exceed
+ *             about 1e-15 (|A||B|)_ij, so targets near 1e-15 are
+ *             unreachable; 1e-14 is typical.
+ *   N_start : 0, or the first N to try (range as for ozaki2_gemm / sgemm).
+ *   N_used  : HOST pointer; receives the N of the C returned.
+ *   ratio   : HOST pointer or NULL; receives max_ij est1_ij / S_ij at N_used,
+ *             with S_ij a certified lower bound of (|A||B|)_ij (as in
+ *             ozaki2_required_moduli), every rounding taken upward.
+ * Returns OZAKI2_OK when certified; OZAKI2_ERR_UNREACHABLE when no N up to
+ * the maximum (49, or 16 for prec 32) certifies eps (C then holds the result
+ * at that N); OZAKI2_ERR_NONFINITE for a non-finite input entry (C is NaN);
+ * argument / workspace / HIP errors as ozaki2_gemm.  k == 0 writes C = 0.
+ * An output entry that is subnormal keeps only a bound on C'', so such
+ * entries can fail to certify.  Synchronises the stream.  The workspace
+ * needed is ozaki2_certified_workspace_bytes at the largest N tried.
+ */
+int ozaki2_gemm_certified(int prec, int m, int n, int k, const void *A, int lda, const void *B,
+                          int ldb, void *C, int ldc, double eps, int N_start, int *N_used,
+                          double *ratio);
+
+/* Bytes of device workspace ozaki2_gemm_certified needs at N (0 for
+ * arguments the call would reject, and for m, n or k == 0). */
+size_t ozaki2_certified_workspace_bytes(int prec, int m, int n, int k, int N);
+
 /* Work queue: every later call on this host thread enqueues on `stream`
  * (a hipStream_t; NULL = the null stream). */
 int ozaki2_set_stream(void *stream);

@@ -37,6 +37,9 @@ _SIGS = {
     "ozaki2_sgemm": ([_c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int], _c_int),
     "ozaki2_required_moduli": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_double,
                                 ctypes.POINTER(_c_int)], _c_int),
+    "ozaki2_gemm_certified": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int,
+                               _c_double, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)], _c_int),
+    "ozaki2_certified_workspace_bytes": ([_c_int, _c_int, _c_int, _c_int, _c_int], _c_size),
     "ozaki2_set_stream": ([_c_ptr], _c_int),
     "ozaki2_workspace_bytes": ([_c_int, _c_int, _c_int, _c_int, _c_int], _c_size),
     "ozaki2_set_workspace": ([_c_ptr, _c_size], _c_int),
@@ -93,6 +96,18 @@ def ozaki2_required_moduli(prec, m, n, k, A, lda, B, ldb, eps):
     out = _c_int(0)
     rc = _call("ozaki2_required_moduli", prec, m, n, k, A, lda, B, ldb, eps, ctypes.byref(out))
     return rc, out.value
+
+
+def ozaki2_gemm_certified(prec, m, n, k, A, lda, B, ldb, C, ldc, eps, N_start):
+    """(rc, N_used, ratio)."""
+    n_used, ratio = _c_int(0), _c_double(0.0)
+    rc = _call("ozaki2_gemm_certified", prec, m, n, k, A, lda, B, ldb, C, ldc, eps, N_start,
+               ctypes.byref(n_used), ctypes.byref(ratio))
+    return rc, n_used.value, ratio.value
+
+
+def ozaki2_certified_workspace_bytes(prec, m, n, k, N):
+    return _call("ozaki2_certified_workspace_bytes", prec, m, n, k, N)
 
 
 def ozaki2_set_stream(stream):
@@ -194,6 +209,21 @@ def required_moduli(A, B, eps: float):
     _set_current_stream()
     prec = 64 if A.dtype == torch.float64 else 32
     return ozaki2_required_moduli(prec, m, n, k, Acm.data_ptr(), max(m, 1), Bcm.data_ptr(), max(k, 1), eps)
+
+
+def gemm_certified(A, B, eps: float, N_start: int = 0):
+    """(C, rc, N_used, ratio) from ozaki2_gemm_certified for logical A (m x k), B (k x n);
+    C is A @ B at N_used as a (transposed view of a) column-major tensor."""
+    torch = _torch()
+    m, k = A.shape
+    n = B.shape[1]
+    Acm, Bcm = col_major(A), col_major(B)
+    Ccm = torch.empty((n, m), dtype=A.dtype, device=A.device)
+    _set_current_stream()
+    prec = 64 if A.dtype == torch.float64 else 32
+    rc, N, ratio = ozaki2_gemm_certified(prec, m, n, k, Acm.data_ptr(), max(m, 1), Bcm.data_ptr(),
+                                         max(k, 1), Ccm.data_ptr(), max(m, 1), eps, N_start)
+    return Ccm.t(), rc, N, ratio
 
 
 def debug_stages(A, B, N: int):

@@ -797,6 +797,117 @@ size_t ozaki2_batched_workspace_bytes(int prec, int count, const int* mnkN) {
   return batch_layout(count, mnkN, nullptr, nullptr);
 }
 
+}  // extern "C" (reopened below)
+
+namespace {
+
+// The N-independent planner terms (Algorithm 2's scaling pass, row and column
+// sums of the scaled |A| and |B|, the BF16 lower bound of S) into the planner
+// region `ws` with layout L; enqueued on s.
+void plan_terms(Prec pr, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+                const PlanLayout& L, char* ws, hipStream_t s) {
+  uint64_t* rowbits = at<uint64_t>(ws, L.rowbits);
+  uint64_t* colbits = at<uint64_t>(ws, L.colbits);
+  int* rmax = at<int>(ws, L.rmax);
+  int* cmax = at<int>(ws, L.cmax);
+  int* flag = at<int>(ws, L.flag);
+  CrtConsts cc;
+  std::memset(&cc, 0, sizeof(cc));
+  Scope sc(PH_PLAN, s);
+  launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
+  launch_absmax_rows(s, pr, A, lda, m, k, rowbits, flag);
+  launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag);
+  // Cbar maxima exactly as the emulation computes them (Algorithm 2)
+  launch_slices(s, pr, 0, true, A, lda, m, k, L.mp, L.kp, rowbits, nullptr, cc,
+                at<int8_t>(ws, L.Abar));
+  launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc,
+                at<int8_t>(ws, L.Bbar));
+  launch_gemm_i8(s, 1, at<int8_t>(ws, L.Abar), 0, at<int8_t>(ws, L.Bbar), 0, L.mp, L.np, L.kp, 1,
+                 cc, nullptr, 0, 0, rmax, cmax);
+  // scaled |A|, |B| as BF16 lower bounds, with upward row / column sums
+  launch_plan_slices(s, pr, true, A, lda, m, k, L.mp, L.kp, rowbits, at<uint16_t>(ws, L.Abf),
+                     at<double>(ws, L.pr));
+  launch_plan_slices(s, pr, false, B, ldb, n, k, L.np, L.kp, colbits, at<uint16_t>(ws, L.Bbf),
+                     at<double>(ws, L.pc));
+  launch_plan_vectors(s, at<double>(ws, L.pr), L.mp, at<double>(ws, L.pc), L.np, L.kp / 64, rmax,
+                      cmax, m, n, at<double>(ws, L.rs), at<double>(ws, L.cs), at<double>(ws, L.sr),
+                      at<double>(ws, L.sc));
+  launch_gemm_bf16_store(s, at<uint16_t>(ws, L.Abf), at<uint16_t>(ws, L.Bbf), L.mp, L.np, L.kp,
+                         at<float>(ws, L.S), L.mp);
+}
+
+// BF16 products of the truncated operands are exact in FP32; each of the k
+// accumulation steps loses at most 2^-23 relative (all terms >= 0).
+double bf16_acc_scale(int k) { return 1.0 - (double)k * 0x1p-22; }
+
+// The smallest N in [2, nhi] whose N-dependent bound is within eps of S on
+// every entry (reading R16), from terms that plan_terms has enqueued.
+// Synchronises.  OZAKI2_ERR_UNREACHABLE (N_out = nhi) if there is none,
+// OZAKI2_ERR_NONFINITE if an input entry was not finite.
+int plan_search(const PlanLayout& L, char* ws, int m, int n, int k, double eps, const PlanCoef& pc,
+                int nhi, hipStream_t s, int* N_out) {
+  int* flag = at<int>(ws, L.flag);
+  int* res = at<int>(ws, L.res);
+  PlanTable pt;
+  std::memset(&pt, 0, sizeof(pt));
+  pt.nlo = 2;
+  pt.nhi = nhi;
+  pt.k = (double)k;
+  pt.eps = eps;
+  pt.acc_scale = bf16_acc_scale(k);
+  for (int N = 2; N <= kMaxModuli; ++N) {
+    pt.t[N] = pc.t[N];
+    pt.tt[N] = pc.tt[N];
+    pt.extra[N] = pc.extra[N];
+  }
+  const float* S = at<float>(ws, L.S);
+  const double *rs = at<double>(ws, L.rs), *cs = at<double>(ws, L.cs);
+  const double *sr = at<double>(ws, L.sr), *scv = at<double>(ws, L.sc);
+  if (hipMemsetAsync(res, 0, 2 * sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
+  launch_plan_entries(s, S, L.mp, m, n, rs, cs, sr, scv, pt, res);
+  int host = 0;
+  int hflag = 0;
+  if (hipMemcpyAsync(&host, res, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return OZAKI2_ERR_HIP;
+  if (hflag) {
+    *N_out = nhi;
+    return OZAKI2_ERR_NONFINITE;
+  }
+  // The smallest N that satisfies every entry: start at the largest
+  // per-entry minimum and check all entries (the bound is not monotone in N
+  // once the N-dependent accumulation term dominates).
+  int N = host < 2 ? 2 : host;
+  for (; N <= nhi; ++N) {
+    if (hipMemsetAsync(res + 1, 0, sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
+    launch_plan_verify(s, S, L.mp, m, n, rs, cs, sr, scv, pt, N, res + 1);
+    int bad = 0;
+    if (hipMemcpyAsync(&bad, res + 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return OZAKI2_ERR_HIP;
+    if (!bad) break;
+  }
+  if (N > nhi) {
+    *N_out = nhi;
+    return OZAKI2_ERR_UNREACHABLE;
+  }
+  *N_out = N;
+  return OZAKI2_OK;
+}
+
+// Workspace of the certified call at N: the planner region, then the
+// single-problem layout.
+size_t certified_bytes(int m, int n, int k, int N, size_t* gemm_off) {
+  const size_t off = rup(plan_layout(m, n, k).total, 256);
+  if (gemm_off) *gemm_off = off;
+  return off + layout(m, n, k, N, single_row_pad(m, n, N)).total;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ozaki2_required_moduli(int prec, int m, int n, int k, const void* A, int lda, const void* B,
                            int ldb, double eps, int* N_out) {
   if (prec != 64 && prec != 32) return OZAKI2_ERR_INVALID_ARG;
@@ -816,85 +927,99 @@ int ozaki2_required_moduli(int prec, int m, int n, int k, const void* A, int lda
   int* status;
   if ((rc = get_workspace(L.total, &ws, &status))) return rc;
   hipStream_t s = g_stream;
-  uint64_t* rowbits = at<uint64_t>(ws, L.rowbits);
-  uint64_t* colbits = at<uint64_t>(ws, L.colbits);
-  int* rmax = at<int>(ws, L.rmax);
-  int* cmax = at<int>(ws, L.cmax);
-  int* flag = at<int>(ws, L.flag);
-  int* res = at<int>(ws, L.res);
-  CrtConsts cc;
-  std::memset(&cc, 0, sizeof(cc));
-  {
-    Scope sc(PH_PLAN, s);
-    launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
-    if (hipMemsetAsync(res, 0, 2 * sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
-    launch_absmax_rows(s, pr, A, lda, m, k, rowbits, flag);
-    launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag);
-    // Cbar maxima exactly as the emulation computes them (Algorithm 2)
-    launch_slices(s, pr, 0, true, A, lda, m, k, L.mp, L.kp, rowbits, nullptr, cc,
-                  at<int8_t>(ws, L.Abar));
-    launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc,
-                  at<int8_t>(ws, L.Bbar));
-    launch_gemm_i8(s, 1, at<int8_t>(ws, L.Abar), 0, at<int8_t>(ws, L.Bbar), 0, L.mp, L.np, L.kp, 1,
-                   cc, nullptr, 0, 0, rmax, cmax);
-    // scaled |A|, |B| as BF16 lower bounds, with upward row / column sums
-    launch_plan_slices(s, pr, true, A, lda, m, k, L.mp, L.kp, rowbits, at<uint16_t>(ws, L.Abf),
-                       at<double>(ws, L.pr));
-    launch_plan_slices(s, pr, false, B, ldb, n, k, L.np, L.kp, colbits, at<uint16_t>(ws, L.Bbf),
-                       at<double>(ws, L.pc));
-    launch_plan_vectors(s, at<double>(ws, L.pr), L.mp, at<double>(ws, L.pc), L.np, L.kp / 64, rmax,
-                        cmax, m, n, at<double>(ws, L.rs), at<double>(ws, L.cs),
-                        at<double>(ws, L.sr), at<double>(ws, L.sc));
-    launch_gemm_bf16_store(s, at<uint16_t>(ws, L.Abf), at<uint16_t>(ws, L.Bbf), L.mp, L.np, L.kp,
-                           at<float>(ws, L.S), L.mp);
+  plan_terms(pr, m, n, k, A, lda, B, ldb, L, ws, s);
+  return plan_search(L, ws, m, n, k, eps, pc, nhi, s, N_out);
+}
+
+size_t ozaki2_certified_workspace_bytes(int prec, int m, int n, int k, int N) {
+  if (prec != 64 && prec != 32) return 0;
+  if (m < 0 || n < 0 || k < 0 || k > kMaxK || N < 2 || N > (prec == 64 ? kMaxModuli : 16))
+    return 0;
+  if (m == 0 || n == 0 || k == 0) return 0;
+  return certified_bytes(m, n, k, N, nullptr);
+}
+
+int ozaki2_gemm_certified(int prec, int m, int n, int k, const void* A, int lda, const void* B,
+                          int ldb, void* C, int ldc, double eps, int N_start, int* N_used,
+                          double* ratio) {
+  if (prec != 64 && prec != 32) return OZAKI2_ERR_INVALID_ARG;
+  if (!N_used || !(eps > 0.0) || !(eps < INFINITY)) return OZAKI2_ERR_INVALID_ARG;
+  int rc = check_args(m, n, k, A, lda, B, ldb, C, ldc, true);
+  if (rc) return rc;
+  const int b = prec, nhi = prec == 64 ? kMaxModuli : 16;
+  if (N_start != 0 && (rc = check_N(N_start, b))) return rc;
+  const Prec pr = prec == 64 ? Prec::F64 : Prec::F32;
+  hipStream_t s = g_stream;
+  if (m == 0 || n == 0 || k == 0) {  // AB = 0 is represented exactly
+    *N_used = N_start ? N_start : 2;
+    if (ratio) *ratio = 0.0;
+    if (m == 0 || n == 0) return OZAKI2_OK;
+    launch_fill_zero(s, pr, C, ldc, m, n);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return OZAKI2_ERR_HIP;
+    return OZAKI2_OK;
   }
-  PlanTable pt;
-  std::memset(&pt, 0, sizeof(pt));
-  pt.nlo = 2;
-  pt.nhi = nhi;
-  pt.k = (double)k;
-  pt.eps = eps;
-  // BF16 products of the truncated operands are exact in FP32; each of the k
-  // accumulation steps loses at most 2^-23 relative (all terms >= 0).
-  pt.acc_scale = 1.0 - (double)k * 0x1p-22;
-  for (int N = 2; N <= kMaxModuli; ++N) {
-    pt.t[N] = pc.t[N];
-    pt.tt[N] = pc.tt[N];
-    pt.extra[N] = pc.extra[N];
-  }
-  const float* S = at<float>(ws, L.S);
-  const double *rs = at<double>(ws, L.rs), *cs = at<double>(ws, L.cs);
-  const double *sr = at<double>(ws, L.sr), *scv = at<double>(ws, L.sc);
-  launch_plan_entries(s, S, L.mp, m, n, rs, cs, sr, scv, pt, res);
-  int host[2] = {0, 0};
-  int hflag = 0;
-  if (hipMemcpyAsync(host, res, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return OZAKI2_ERR_HIP;
-  if (hflag) {
-    *N_out = nhi;
-    return OZAKI2_ERR_NONFINITE;
-  }
-  // The smallest N that satisfies every entry: start at the largest
-  // per-entry minimum and check all entries (the bound is not monotone in N
-  // once the N-dependent accumulation term dominates).
-  int N = host[0] < 2 ? 2 : host[0];
-  for (; N <= nhi; ++N) {
-    if (hipMemsetAsync(res + 1, 0, sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
-    launch_plan_verify(s, S, L.mp, m, n, rs, cs, sr, scv, pt, N, res + 1);
-    int bad = 0;
-    if (hipMemcpyAsync(&bad, res + 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  PlanCoef pc;
+  if ((rc = get_plan_coef(prec, &pc))) return rc;
+  const PlanLayout Lp = plan_layout(m, n, k);
+  uint64_t terms_gen = 0;  // workspace generation the planner terms were computed in
+  int N = N_start;
+  for (;;) {
+    const int Nw = N ? N : 2;
+    size_t off;
+    const size_t total = certified_bytes(m, n, k, Nw, &off);
+    char* ws;
+    int* status;
+    uint64_t gen = 0;
+    if ((rc = get_workspace(total, &ws, &status, &gen))) return rc;
+    if (gen != terms_gen) {  // first pass, or the workspace moved
+      plan_terms(pr, m, n, k, A, lda, B, ldb, Lp, ws, s);
+      terms_gen = gen;
+      if (N == 0) {
+        rc = plan_search(Lp, ws, m, n, k, eps, pc, nhi, s, &N);
+        // A non-finite input: one run at N = 2 writes the NaN output and
+        // records the status, and the check below returns the error.
+        if (rc == OZAKI2_ERR_NONFINITE) N = 2;
+        else if (rc != OZAKI2_OK && rc != OZAKI2_ERR_UNREACHABLE) return rc;
+        continue;  // the layout depends on N
+      }
+    }
+    CrtConsts cc;
+    if ((rc = get_consts(N, b, &cc))) return rc;
+    const Layout Lg = layout(m, n, k, N, single_row_pad(m, n, N));
+    char* wg = ws + off;
+    if ((rc = run_pipeline(pr, m, n, k, A, lda, B, ldb, C, ldc, cc, Lg, wg, status, s, false)))
+      return rc;
+    CertTable ct;
+    ct.t = pc.t[N];
+    ct.tt = pc.tt[N];
+    ct.extra = pc.extra[N];
+    ct.rconst = pc.rconst[N];
+    ct.rel = pc.rel[N];
+    ct.k = (double)k;
+    ct.acc_scale = bf16_acc_scale(k);
+    ct.tiny = prec == 64 ? 0x1p-1074 : 0x1p-149;
+    unsigned long long* word = at<unsigned long long>(ws, Lp.res);
+    if (hipMemsetAsync(word, 0, sizeof(*word), s) != hipSuccess) return OZAKI2_ERR_HIP;
+    launch_certify(s, pr, C, ldc, at<int>(wg, Lg.mu), at<int>(wg, Lg.nu), at<float>(ws, Lp.S),
+                   Lp.mp, m, n, at<double>(ws, Lp.rs), at<double>(ws, Lp.cs),
+                   at<double>(ws, Lp.sr), at<double>(ws, Lp.sc), ct, word);
+    unsigned long long bits = 0;
+    int hflag = 0;
+    if (hipMemcpyAsync(&bits, word, sizeof(bits), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&hflag, at<int>(wg, Lg.flag), sizeof(int), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return OZAKI2_ERR_HIP;
-    if (!bad) break;
+    double r;
+    std::memcpy(&r, &bits, sizeof(r));
+    *N_used = N;
+    if (ratio) *ratio = r;
+    if (hflag) return OZAKI2_ERR_NONFINITE;
+    if (r <= eps) return OZAKI2_OK;
+    if (N >= nhi) return OZAKI2_ERR_UNREACHABLE;
+    ++N;
   }
-  if (N > nhi) {
-    *N_out = nhi;
-    return OZAKI2_ERR_UNREACHABLE;
-  }
-  *N_out = N;
-  return OZAKI2_OK;
 }
 
 int ozaki2_debug_stages(int prec, int m, int n, int k, const void* A, int lda, const void* B,

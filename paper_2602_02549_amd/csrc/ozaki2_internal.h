@@ -41,8 +41,20 @@ struct PlanCoef {
   double tt[kMaxModuli + 1];
   double extra[kMaxModuli + 1];
   double rnd[kMaxModuli + 1];
+  double rconst[kMaxModuli + 1];  // R_const of Lemma 4
+  double rel[kMaxModuli + 1];     // R_rel t^2 / (1 - R_rel)
 };
 bool build_plan_coef(int b, PlanCoef* out);
+
+// The a-posteriori est1 of Theorem 1 at one N, in the planner's factored form
+// (passed by value to the certification kernel).
+struct CertTable {
+  double t, tt, extra;  // t(N), t(N)^2, R_const t(N)^2
+  double rconst, rel;   // R_const; R_rel t(N)^2 / (1 - R_rel)
+  double k;             // inner dimension
+  double acc_scale;     // lower-bound factor of the BF16 product S
+  double tiny;          // smallest positive subnormal of the output type
+};
 
 // Everything the per-entry planner kernels need (passed by value).
 struct PlanTable {
@@ -181,6 +193,12 @@ void launch_plan_entries(hipStream_t s, const float* S, int lds_, int m, int n, 
 void launch_plan_verify(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
                         const double* cs, const double* sr, const double* sc, const PlanTable& pt,
                         int N, int* bad);
+// Maximum over entries of the a-posteriori est1 / S (bit pattern into *out,
+// which the caller zeroes); C is the output of the run whose shifts are mu, nu.
+void launch_certify(hipStream_t s, Prec pr, const void* C, int ldc, const int* mu, const int* nu,
+                    const float* S, int lds_, int m, int n, const double* rs, const double* cs,
+                    const double* sr, const double* sc, const CertTable& ct,
+                    unsigned long long* out);
 
 // Grouped launches (one per phase for a whole batch of `count` problems);
 // `map` holds `blocks` entries, one per workgroup.

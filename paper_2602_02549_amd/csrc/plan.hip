@@ -101,7 +101,67 @@ __global__ __launch_bounds__(256) void k_plan_verify(const float* __restrict__ S
   }
 }
 
+// A-posteriori est1 of Theorem 1 (eq. thm:err-1) relative to the lower bound
+// of S, per entry.  |A'B'| is bounded through Lemma 4 by the computed C'':
+// |A'B'| <= (|C''| + R_const) / (1 - R_rel).  C'' is recovered from the output
+// and the shifts: C = C'' 2^-(mu_i + nu_j) rounded once, exactly unless C is
+// subnormal, so |C''| <= (|C| + tiny) 2^(mu_i + nu_j) in every case (for b = 32
+// this is the FP32 C'' of Algorithm 3, to which Lemma 4 refers).  In factored
+// form (row and column powers of two removed, as in the planner):
+//   est1 = t A1 + (k t^2 + R_const t^2 + rel (|C''| + R_const)) P2,
+// every rounding pushed upward.  The maximum of est1 / S over entries with
+// S > 0 goes to *out as the bit pattern of a nonnegative double (whose order
+// is that of the unsigned integers).
+template <typename T>
+__global__ __launch_bounds__(256) void k_certify(const T* __restrict__ C, int ldc,
+                                                 const int* __restrict__ mu,
+                                                 const int* __restrict__ nu,
+                                                 const float* __restrict__ S, int lds_, int m,
+                                                 int n, int iblocks, const double* __restrict__ rs,
+                                                 const double* __restrict__ cs,
+                                                 const double* __restrict__ sr,
+                                                 const double* __restrict__ sc, CertTable ct,
+                                                 unsigned long long* __restrict__ out) {
+  const int j = blockIdx.x / iblocks;
+  const int i = (blockIdx.x % iblocks) * 256 + threadIdx.x;
+  double ratio = 0.0;
+  if (i < m && j < n) {
+    const double Sl = (double)S[(size_t)j * lds_ + i] * ct.acc_scale;
+    if (Sl > 0.0) {
+      const double c = fabs((double)C[i + (size_t)j * ldc]) + ct.tiny;
+      const double cpp = ldexp(c, mu[i] + nu[j]);
+      const double A1 = rs[i] * sc[j] + sr[i] * cs[j];
+      const double P2 = sr[i] * sc[j];
+      const double est =
+          (ct.t * A1 + (ct.k * ct.tt + ct.extra + ct.rel * (cpp + ct.rconst) * kTUp) * P2) * kTUp;
+      ratio = est / Sl * kTUp;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) ratio = fmax(ratio, __shfl_xor(ratio, off));
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ratio;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(out, (unsigned long long)__double_as_longlong(r));
+  }
+}
+
 }  // namespace
+
+void launch_certify(hipStream_t s, Prec pr, const void* C, int ldc, const int* mu, const int* nu,
+                    const float* S, int lds_, int m, int n, const double* rs, const double* cs,
+                    const double* sr, const double* sc, const CertTable& ct,
+                    unsigned long long* out) {
+  const int iblocks = (m + 255) / 256;
+  const dim3 grid((unsigned)iblocks * (unsigned)n), block(256);
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL(k_certify<double>, grid, block, 0, s, (const double*)C, ldc, mu, nu, S,
+                       lds_, m, n, iblocks, rs, cs, sr, sc, ct, out);
+  else
+    hipLaunchKernelGGL(k_certify<float>, grid, block, 0, s, (const float*)C, ldc, mu, nu, S, lds_,
+                       m, n, iblocks, rs, cs, sr, sc, ct, out);
+}
 
 void launch_plan_vectors(hipStream_t s, const double* pr, int m_pad, const double* pc, int n_pad,
                          int tiles, const int* rmax, const int* cmax, int m, int n, double* rs,

@@ -292,22 +292,29 @@ bool build_plan_coef(int b, PlanCoef* out) {
     Pm1 = std::ldexp(Pm1, sh);                        // P - 1 (relative error < 2^-63)
     long double PP = std::ldexp(P.top64(&sh), sh);    // P
     long double tt = 1.0L / (32.0L * Pm1);            // t^2 = 1 / (2^5 (P - 1))
-    long double extra, rnd;
+    long double extra, rnd, rconst, rrel;
     if (b == 64) {
       // r_64 - (3/2) u P = (1 + 3u) 2^(1 + ceil(log2 rho)) (N + 2) u^2 rho P
-      extra = (1 + 3 * u64) * std::ldexp((long double)1, 1 + clog2rho) * (N + 2) * u64 * u64 *
-              rho * PP * tt;
+      rconst = (1 + 3 * u64) * std::ldexp((long double)1, 1 + clog2rho) * (N + 2) * u64 * u64 *
+               rho * PP;
+      rrel = 3 * u64;
       rnd = 1.5L * u64 * PP * tt;
     } else {
       // r_32 - (1/2) u_32 P = (1 + u_32) (N + 2) u_64 rho P
-      extra = (1 + u32) * (N + 2) * u64 * rho * PP * tt;
+      rconst = (1 + u32) * (N + 2) * u64 * rho * PP;
+      rrel = u32;
       rnd = 0.5L * u32 * PP * tt;
     }
+    extra = rconst * tt;
     // Round every coefficient up so that the bound stays an upper bound.
     out->tt[N] = std::nextafter((double)tt, INFINITY);
     out->t[N] = std::nextafter(std::sqrt((double)tt), INFINITY);
     out->extra[N] = std::nextafter((double)extra, INFINITY);
     out->rnd[N] = std::nextafter((double)rnd, INFINITY);
+    // Lemma 4 in the form |A'B' - C''| <= R_const + R_rel |A'B'|: R_const, and
+    // R_rel t^2 / (1 - R_rel), the coefficient of (|C''| + R_const) in est1.
+    out->rconst[N] = std::nextafter((double)rconst, INFINITY);
+    out->rel[N] = std::nextafter((double)(rrel * tt / (1 - rrel)), INFINITY);
   }
   return true;
 }

@@ -110,3 +110,21 @@ def test_batched_workspace_query():
     assert q(16, [300, 200, 500, 14]) == 0
     # at least the moduli slices and W of every active problem
     assert two >= 20 * (128 * 384 + 128 * 384 + 128 * 128) + 14 * (384 * 512 + 256 * 512 + 256 * 384)
+
+
+def test_certified_argument_errors_and_workspace_query():
+    # Host-side validation of ozaki2_gemm_certified (nothing reaches the device).
+    c = oz.ozaki2_gemm_certified
+    assert c(16, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1e-14, 0)[0] == oz.ERR_INVALID_ARG
+    assert c(64, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 0.0, 0)[0] == oz.ERR_INVALID_ARG
+    assert c(64, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, float("nan"), 0)[0] == oz.ERR_INVALID_ARG
+    assert c(64, 4, 4, 4, FAKE, 3, FAKE, 4, FAKE, 4, 1e-14, 0)[0] == oz.ERR_INVALID_ARG   # lda < m
+    assert c(64, 4, 4, 4, FAKE, 4, FAKE, 4, None, 4, 1e-14, 0)[0] == oz.ERR_INVALID_ARG   # NULL C
+    assert c(64, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1e-14, 1)[0] == oz.ERR_N_RANGE
+    assert c(32, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1e-6, 17)[0] == oz.ERR_N_RANGE
+    assert c(64, 4, 4, 2 ** 17 + 1, FAKE, 4, FAKE, 2 ** 17 + 1, FAKE, 4, 1e-14, 0)[0] == oz.ERR_K_RANGE
+    assert c(64, 0, 4, 4, None, 1, FAKE, 4, None, 1, 1e-14, 0) == (oz.OK, 2, 0.0)   # m = 0: no-op
+    q = oz.ozaki2_certified_workspace_bytes
+    assert q(64, 300, 200, 500, 14) > oz.ozaki2_workspace_bytes(64, 300, 200, 500, 14)
+    assert q(64, 300, 200, 500, 20) > q(64, 300, 200, 500, 14)
+    assert q(64, 300, 200, 500, 50) == 0 and q(32, 300, 200, 500, 17) == 0 and q(64, 0, 4, 4, 14) == 0
