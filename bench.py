@@ -46,8 +46,9 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device copy of MIB MiB first (HBM counter calibration)")
     ap.add_argument("--extras", action="store_true",
-                    help="also measure the 4096^3 phi sweep (N from the bound at 1e-15) and the "
-                         "FP32 16384^3 emulated SGEMM against native SGEMM at matched error")
+                    help="also measure the 4096^3 phi sweep (N from the bound at 1e-15), the "
+                         "certified call at 1e-14 on the same inputs, and the FP32 16384^3 "
+                         "emulated SGEMM against native SGEMM at matched error")
     return ap.parse_args()
 
 
@@ -108,6 +109,7 @@ def extras_measurement(torch, oz) -> dict:
             "rel_err_sampled": err, "native_ms": round(nat_ms, 4), "native_rel_err_sampled": nat_err})
         del dA, dB, Acm, Bcm, Ccm, Cn
         torch.cuda.empty_cache()
+    out["certified_4096"] = certified_measurement(torch, oz, rng)
     # FP32 16384^3
     n = 16384
     A, B = gemm_inputs(n, n, n, phi=0.5, seed=0, dtype=np.float32)
@@ -137,6 +139,54 @@ def extras_measurement(torch, oz) -> dict:
                          "native_tflops": round(2.0 * n ** 3 / (nat_ms * 1e-3) / 1e12, 2),
                          "native_rel_err_sampled": nat_err, "emulated": res, "matched_N": matched}
     return out
+
+
+def certified_measurement(torch, oz, rng) -> list:
+    """ozaki2_gemm_certified on the FP64 4096^3 workloads (phi in {0, 1, 2, 4})
+    at eps = 1e-14: the planner's N for the same eps, the certified N, the
+    certified max est1 / |A||B|, the observed error on sampled entries, and
+    the wall time of the whole call (planner terms, runs, certification;
+    best of two) against one plain emulated GEMM at the certified N."""
+    from workload import gemm_inputs
+    from workload.reference import ExactSamples
+
+    dev = torch.device("cuda:0")
+    n, eps = 4096, 1e-14
+    res = []
+    for phi in (0.0, 1.0, 2.0, 4.0):
+        A, B = gemm_inputs(n, n, n, phi=phi, seed=0)
+        rows = np.sort(rng.choice(n, 16, replace=False))
+        cols = np.sort(rng.choice(n, 16, replace=False))
+        ex = ExactSamples(A, B, rows, cols)
+        dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        Acm, Bcm = oz.col_major(dA), oz.col_major(dB)
+        Ccm = torch.empty((n, n), dtype=torch.float64, device=dev)
+        oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        rc_p, N_plan = oz.ozaki2_required_moduli(64, n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, eps)
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, N, ratio = oz.ozaki2_gemm_certified(64, n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n,
+                                                    Ccm.data_ptr(), n, eps, 0)
+            dt = (time.perf_counter() - t0) * 1e3
+            best = dt if best is None else min(best, dt)
+        if rc not in (oz.OK, oz.ERR_UNREACHABLE):
+            raise oz.Ozaki2Error("ozaki2_gemm_certified", rc)
+        sub = Ccm.t()[torch.as_tensor(rows, device=dev)][:, torch.as_tensor(cols, device=dev)]
+        err = ex.rel_error(sub.cpu().numpy())
+
+        def emu():
+            r = oz.ozaki2_gemm(n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, Ccm.data_ptr(), n, N)
+            if r != oz.OK:
+                raise oz.Ozaki2Error("ozaki2_gemm", r)
+
+        res.append({"phi": phi, "eps": eps, "N_planner": N_plan, "N_certified": N,
+                    "certified": rc == oz.OK, "ratio": ratio, "rel_err_sampled": err,
+                    "call_ms": round(best, 3), "gemm_ms_at_N": round(_time_ms(torch, emu, 3), 4)})
+        del dA, dB, Acm, Bcm, Ccm
+        torch.cuda.empty_cache()
+    return res
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_i8_residue_fp64_8192_N14_traffic.txt")
