@@ -89,3 +89,26 @@ def test_certified_nonfinite_and_k0():
     Z = torch.zeros((5, 0), dtype=torch.float64, device="cuda:0")
     C, rc, N_used, ratio = oz.gemm_certified(Z, torch.zeros((0, 4), dtype=torch.float64, device="cuda:0"), 1e-14)
     assert rc == oz.OK and ratio == 0.0 and torch.all(C == 0).item()
+
+
+def test_certified_caller_owned_workspace():
+    # A caller-installed workspace of exactly ozaki2_certified_workspace_bytes
+    # at the N used is enough (same bits as on the library's); one byte less
+    # is refused before anything runs.
+    announce("certified: caller-owned workspace")
+    A, B = gemm_inputs(70, 60, 90, phi=1.0, seed=8)
+    ref, rc, N, _ = oz.gemm_certified(dev(A), dev(B), 1.0, 18)
+    assert rc == oz.OK and N == 18
+    ref = host(ref)
+    try:
+        nbytes = oz.ozaki2_certified_workspace_bytes(64, 70, 60, 90, 18)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+        assert oz.ozaki2_set_workspace(ws.data_ptr(), nbytes) == oz.OK
+        C, rc, N, _ = oz.gemm_certified(dev(A), dev(B), 1.0, 18)
+        assert rc == oz.OK and N == 18 and np.array_equal(host(C), ref)
+        assert oz.ozaki2_set_workspace(ws.data_ptr(), nbytes - 1) == oz.OK
+        _, rc, _, _ = oz.gemm_certified(dev(A), dev(B), 1.0, 18)
+        assert rc == oz.ERR_WORKSPACE
+        torch.cuda.synchronize()
+    finally:
+        oz.ozaki2_set_workspace(None, 0)
