@@ -30,6 +30,10 @@
  *     hipMalloc unless the caller installs its own with ozaki2_set_workspace.
  *     Calls that overlap on one device race on that workspace; the library
  *     is meant to be driven from one host thread per device.
+ *   - ozaki2_gemm and ozaki2_sgemm enqueue kernels only (no memset or copy):
+ *     after one call on the device has set up its state, and with a
+ *     workspace already large enough, a call can be captured into a graph
+ *     by the caller and replayed.
  */
 #ifndef OZAKI2_H
 #define OZAKI2_H

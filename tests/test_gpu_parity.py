@@ -151,6 +151,36 @@ def test_slices_few_workgroups(cap, monkeypatch):
         assert np.array_equal(host(Ccm[q]).T, os_ii(A, B, N)), f"batched problem {q}"
 
 
+def test_gemm_captured_in_a_graph():
+    # ozaki2_gemm enqueues kernels only (no memset or copy nodes), so once the
+    # workspace has grown a caller can capture it.  The graph is replayed three
+    # times with other library work, synchronisation and a reset of C between
+    # the replays; every replay must give the eager call's bits.
+    announce("ozaki2_gemm captured in a graph")
+    m, n, k, N = 300, 200, 500, 14
+    A, B = gemm_inputs(m, n, k, phi=1.0, seed=21)
+    ref = host(oz.gemm(dev(A), dev(B), N))          # grows the workspace
+    dA = dev(np.ascontiguousarray(A.T))
+    dB = dev(np.ascontiguousarray(B.T))
+    C = torch.full((n, m), float("nan"), dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        rc = oz.ozaki2_gemm(m, n, k, dA.data_ptr(), m, dB.data_ptr(), k, C.data_ptr(), m, N)
+    assert rc == oz.OK
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    for rep in range(3):
+        C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(C).T, ref), f"replay {rep}"
+        X, Y = gemm_inputs(120, 90, 150, seed=30 + rep)
+        assert np.array_equal(host(oz.gemm(dev(X), dev(Y), 12)), os_ii(X, Y, 12))
+    assert oz.ozaki2_sync_status() == oz.OK
+
+
 def test_leading_dimensions_and_views():
     # lda > m, ldb > k, ldc > m through the raw C ABI (submatrices of bigger buffers).
     announce("leading dimensions m=90 n=70 k=110 N=13")
