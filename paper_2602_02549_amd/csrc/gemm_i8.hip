@@ -302,6 +302,17 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   // reading group gi-1.  No branch encloses an MFMA, so the accumulators stay
   // in place across iterations.
   const int NG = k_pad / 128;
+  // Within each 32-k sub-step the fragment reads of the next sub-step (into
+  // the other register set) alternate one for one with the MFMAs of the
+  // current one; the remaining MFMAs follow.
+  auto interleave = [&]() {
+#pragma unroll
+    for (int q = 0; q < TX + TY; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+    }
+    if constexpr (TX * TY > TX + TY) __builtin_amdgcn_sched_group_barrier(0x008, TX * TY - (TX + TY), 0);
+  };
   issue_group(lds, z, 0);
   for (int gi = 0; gi < NG; ++gi) {
     int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
@@ -312,17 +323,19 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
     // issued, so their LDS latency overlaps the copy issue
     load_frags(buf, 0, a0, b0);
     if (gi + 1 < NG) issue_group(lds + ((gi + 1) & 1) * GROUP_BYTES, z, (gi + 1) * 128);
+    __builtin_amdgcn_sched_barrier(0);
     load_frags(buf, 1, a1, b1);
-    __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the MFMAs
     mfmas(a0, b0);
+    interleave();
     __builtin_amdgcn_sched_barrier(0);
     load_frags(buf, 2, a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
     mfmas(a1, b1);
+    interleave();
     __builtin_amdgcn_sched_barrier(0);
     load_frags(buf, 3, a1, b1);
-    __builtin_amdgcn_sched_barrier(0);
     mfmas(a0, b0);
+    interleave();
+    __builtin_amdgcn_sched_barrier(0);
     mfmas(a1, b1);
   }
   finish();
