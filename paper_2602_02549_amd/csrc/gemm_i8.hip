@@ -154,13 +154,17 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   const size_t rowstep = (size_t)RPI * k_pad;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
 
-  auto issue_group = [&](int8_t* buf, int z, int k0) {
+  // The copies of one group: the X rows (issue_x) and the Y rows (issue_y).
+  auto issue_x = [&](int8_t* buf, int z, int k0) {
     const uint32_t b = lds_addr(buf);
     const int8_t* xs = xsrc + (size_t)z * sx + k0;
-    const int8_t* ys = ysrc + (size_t)z * sy + k0;
 #pragma unroll
     for (int q = 0; q < IX; ++q)
       dma16(xs + q * rowstep + ((q & 1) ? ch_o : ch_e), b + (uint32_t)((wave_u * IX + q) * 1024));
+  };
+  auto issue_y = [&](int8_t* buf, int z, int k0) {
+    const uint32_t b = lds_addr(buf);
+    const int8_t* ys = ysrc + (size_t)z * sy + k0;
 #pragma unroll
     for (int q = 0; q < IY; ++q)
       dma16(ys + q * rowstep + ((q & 1) ? ch_o : ch_e),
@@ -313,20 +317,26 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
     }
     if constexpr (TX * TY > TX + TY) __builtin_amdgcn_sched_group_barrier(0x008, TX * TY - (TX + TY), 0);
   };
-  issue_group(lds, z, 0);
+  issue_x(lds, z, 0);
+  issue_y(lds, z, 0);
   for (int gi = 0; gi < NG; ++gi) {
     int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
+    int8_t* const next = lds + ((gi + 1) & 1) * GROUP_BYTES;
     wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
     v4i a0[TX], b0[TY], a1[TX], b1[TY];
-    // the first fragment reads go out before the next group's copies are
-    // issued, so their LDS latency overlaps the copy issue
+    // The first fragment reads go out before the next group's copies, so
+    // their LDS latency overlaps the copy issue; the X-row copies follow
+    // them and the Y-row copies come one sub-step later, spreading the
+    // copies over the first half of the group.
     load_frags(buf, 0, a0, b0);
-    if (gi + 1 < NG) issue_group(lds + ((gi + 1) & 1) * GROUP_BYTES, z, (gi + 1) * 128);
+    if (gi + 1 < NG) issue_x(next, z, (gi + 1) * 128);
     __builtin_amdgcn_sched_barrier(0);
     load_frags(buf, 1, a1, b1);
     mfmas(a0, b0);
     interleave();
+    __builtin_amdgcn_sched_barrier(0);
+    if (gi + 1 < NG) issue_y(next, z, (gi + 1) * 128);
     __builtin_amdgcn_sched_barrier(0);
     load_frags(buf, 2, a0, b0);
     mfmas(a1, b1);
