@@ -345,7 +345,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs the emulated GEMM on one GPU; --gpus {args.gpus} is not supported "
-              "(how the path would shard across GPUs is described in DESIGN.md).", file=sys.stderr)
+              "(the library has no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
 
     import torch

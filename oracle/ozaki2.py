@@ -13,7 +13,7 @@ emulation).  Every step follows the paper's order and notation:
                           W_l = mod(C'_l, p_l), C'(1), C'(2), Q, C''
   Algorithm 1:            C = fl(diag(2^-mu) C'' diag(2^-nu))
 
-Readings where the paper is silent (each one is listed in the design doc):
+Readings where the paper is silent (R numbers shared with the library's documentation):
   R4  a zero row of A (column of B) gets mu' = 0; its outputs are exact zeros.
   R5  Abar is the ceiling of the exact |a| 2^mu'; it is >= 1 for every a != 0.
   R6  log2f is the correctly rounded (nearest-even) FP32 logarithm; it meets
