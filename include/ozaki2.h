@@ -46,8 +46,9 @@ extern "C" {
 
 typedef enum {
   OZAKI2_OK = 0,
-  OZAKI2_ERR_INVALID_ARG = -1, /* m,n,k < 0; lda < max(1,m); ldb < max(1,k); ldc < max(1,m);
-                                  NULL pointer for a matrix with a nonzero extent            */
+  OZAKI2_ERR_INVALID_ARG = -1, /* m,n,k < 0; m or n > 2^31 - 256; lda < max(1,m);
+                                  ldb < max(1,k); ldc < max(1,m); NULL pointer for a matrix
+                                  with a nonzero extent                                      */
   OZAKI2_ERR_N_RANGE = -2,     /* N outside [2, 49] (FP64) or [2, 16] (FP32)                  */
   OZAKI2_ERR_K_RANGE = -3,     /* k > 2^17 (the analysis of Sections 3-4 assumes k <= 2^17)   */
   OZAKI2_ERR_WORKSPACE = -4,   /* caller-installed workspace smaller than required            */

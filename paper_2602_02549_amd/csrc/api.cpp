@@ -139,7 +139,7 @@ Layout layout(int m, int n, int k, int N, int pad) {
 
 int check_args(int m, int n, int k, const void* A, int lda, const void* B, int ldb, const void* C,
                int ldc, bool needC) {
-  if (m < 0 || n < 0 || k < 0) return OZAKI2_ERR_INVALID_ARG;
+  if (m < 0 || n < 0 || k < 0 || m > kMaxDim || n > kMaxDim) return OZAKI2_ERR_INVALID_ARG;
   if (lda < (m > 1 ? m : 1) || ldb < (k > 1 ? k : 1)) return OZAKI2_ERR_INVALID_ARG;
   if (needC && ldc < (m > 1 ? m : 1)) return OZAKI2_ERR_INVALID_ARG;
   if ((size_t)m * k > 0 && !A) return OZAKI2_ERR_INVALID_ARG;
@@ -748,7 +748,7 @@ int ozaki2_set_stream(void* stream) {
 
 size_t ozaki2_workspace_bytes(int prec, int m, int n, int k, int N) {
   if ((prec != 64 && prec != 32) || m < 0 || n < 0 || k < 0 || k > kMaxK) return 0;
-  if (check_N(N, prec) != OZAKI2_OK) return 0;
+  if (m > kMaxDim || n > kMaxDim || check_N(N, prec) != OZAKI2_OK) return 0;
   return layout(m, n, k, N, single_row_pad(m, n, N)).total;
 }
 
@@ -793,6 +793,7 @@ size_t ozaki2_batched_workspace_bytes(int prec, int count, const int* mnkN) {
   for (int p = 0; p < count; ++p) {
     const int m = mnkN[4 * p], n = mnkN[4 * p + 1], k = mnkN[4 * p + 2], N = mnkN[4 * p + 3];
     if (m < 0 || n < 0 || k < 0 || k > kMaxK || N < 2 || N > nmax) return 0;
+    if (m > kMaxDim || n > kMaxDim) return 0;
   }
   return batch_layout(count, mnkN, nullptr, nullptr);
 }
@@ -935,6 +936,7 @@ size_t ozaki2_certified_workspace_bytes(int prec, int m, int n, int k, int N) {
   if (prec != 64 && prec != 32) return 0;
   if (m < 0 || n < 0 || k < 0 || k > kMaxK || N < 2 || N > (prec == 64 ? kMaxModuli : 16))
     return 0;
+  if (m > kMaxDim || n > kMaxDim) return 0;
   if (m == 0 || n == 0 || k == 0) return 0;
   return certified_bytes(m, n, k, N, nullptr);
 }

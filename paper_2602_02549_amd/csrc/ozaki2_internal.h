@@ -9,6 +9,7 @@ namespace oz2 {
 constexpr int kMaxModuli = 49;   // Section 3.1: p_l <= 256 pairwise coprime => N <= 49
 constexpr int kMaxK = 1 << 17;   // Section 3: k <= 2^17
 constexpr int kRowPad = 256;     // m and n are padded to this multiple in the workspace
+constexpr int kMaxDim = 0x7FFFFF00; // largest m, n whose padding to kRowPad fits in int
 constexpr int kKPad = 128;       // k is padded to this multiple (bytes of INT8 per row)
 constexpr int kCrtRows = 4;      // CRT: consecutive rows per thread (256 threads per block)
 

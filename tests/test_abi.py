@@ -47,6 +47,10 @@ def test_version_and_workspace_query():
     assert oz.ozaki2_workspace_bytes(32, 10, 10, 10, 16) > 0
     assert oz.ozaki2_workspace_bytes(64, 10, 10, (1 << 17) + 1, 14) == 0
     assert oz.ozaki2_workspace_bytes(16, 10, 10, 10, 5) == 0
+    # m and n stay at or below 2^31 - 256, so that their padding fits in int
+    assert oz.ozaki2_workspace_bytes(64, 2 ** 31 - 255, 10, 10, 14) == 0
+    assert oz.ozaki2_workspace_bytes(64, 10, 2 ** 31 - 255, 10, 14) == 0
+    assert oz.ozaki2_workspace_bytes(64, 2 ** 31 - 256, 10, 10, 14) >= 14 * (2 ** 31 - 256) * 128
 
 
 FAKE = 0x1000  # never dereferenced: every case below fails validation first
@@ -59,6 +63,8 @@ FAKE = 0x1000  # never dereferenced: every case below fails validation first
     ((4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 3, 10), oz.ERR_INVALID_ARG),     # ldc < m
     ((4, 4, 4, None, 4, FAKE, 4, FAKE, 4, 10), oz.ERR_INVALID_ARG),     # NULL A
     ((4, 4, 4, FAKE, 4, FAKE, 4, None, 4, 10), oz.ERR_INVALID_ARG),     # NULL C
+    ((2 ** 31 - 255, 4, 4, FAKE, 2 ** 31 - 1, FAKE, 4, FAKE, 2 ** 31 - 1, 10), oz.ERR_INVALID_ARG),  # m > 2^31 - 256
+    ((4, 2 ** 31 - 255, 4, FAKE, 4, FAKE, 4, FAKE, 4, 10), oz.ERR_INVALID_ARG),  # n > 2^31 - 256
     ((4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1), oz.ERR_N_RANGE),
     ((4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 50), oz.ERR_N_RANGE),
     ((4, 4, 2 ** 17 + 1, FAKE, 4, FAKE, 2 ** 17 + 1, FAKE, 4, 10), oz.ERR_K_RANGE),
