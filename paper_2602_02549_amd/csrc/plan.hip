@@ -52,6 +52,32 @@ __device__ inline bool plan_ok(const PlanTable& pt, int N, double A1, double P2,
   return T <= target;
 }
 
+// The per-entry kernels below walk the m x n entries in a grid-stride loop
+// over tasks of 256 consecutive i of one column j, and combine their results
+// with one atomic per workgroup: one per 256 entries would serialise on the
+// single result word (about 11 ns each).
+constexpr int kEntryWorkgroups = 2048;
+
+template <typename F>
+__device__ __forceinline__ void for_entries(int m, int n, int iblocks, F&& f) {
+  const int64_t tasks = (int64_t)iblocks * n;
+  for (int64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
+    const int j = (int)(task / iblocks);
+    const int i = (int)(task % iblocks) * 256 + (int)threadIdx.x;
+    if (i < m) f(i, j);
+  }
+}
+
+// Maximum of v over the workgroup (256 threads), valid in thread 0.
+template <typename T>
+__device__ __forceinline__ T block_max(T v) {
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
+  __shared__ T red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
 // Pass 1: for every entry with S > 0, the smallest N in [nlo, nhi] with
 // T(N) <= eps S (nhi + 1 if none); the maximum over all entries goes to *out.
 __global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ S, int lds_,
@@ -61,25 +87,29 @@ __global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ 
                                                       const double* __restrict__ sr,
                                                       const double* __restrict__ sc, PlanTable pt,
                                                       int* __restrict__ out) {
-  const int j = blockIdx.x / iblocks;
-  const int i = (blockIdx.x % iblocks) * 256 + threadIdx.x;
   int need = 0;
-  if (i < m && j < n) {
+  for_entries(m, n, iblocks, [&](int i, int j) {
     const double Sl = (double)S[(size_t)j * lds_ + i] * pt.acc_scale;
-    if (Sl > 0.0) {
-      const double A1 = rs[i] * sc[j] + sr[i] * cs[j];
-      const double P2 = sr[i] * sc[j];
-      const double target = pt.eps * Sl;
-      int N = pt.nlo;
-      while (N <= pt.nhi && !plan_ok(pt, N, A1, P2, target)) ++N;
-      need = N;
+    bool live = Sl > 0.0;
+    const double A1 = rs[i] * sc[j] + sr[i] * cs[j];
+    const double P2 = sr[i] * sc[j];
+    const double target = pt.eps * Sl;
+    // N advances in step across the wave, so the per-N coefficients are
+    // wave-uniform (scalar) loads; each lane keeps the first N that
+    // satisfies its entry, and the wave stops once every lane has one.
+    int first = 0;
+    for (int N = pt.nlo; N <= pt.nhi; ++N) {
+      if (!__any(live)) break;
+      if (live && plan_ok(pt, N, A1, P2, target)) {
+        first = N;
+        live = false;
+      }
     }
-  }
-  for (int off = 32; off >= 1; off >>= 1) need = max(need, __shfl_xor(need, off));
-  __shared__ int red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = need;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicMax(out, max(max(red[0], red[1]), max(red[2], red[3])));
+    if (live) first = pt.nhi + 1;
+    need = max(need, first);
+  });
+  need = block_max(need);
+  if (threadIdx.x == 0 && need > 0) atomicMax(out, need);
 }
 
 // Pass 2: does N satisfy every entry?  Any failure sets *bad.
@@ -90,15 +120,17 @@ __global__ __launch_bounds__(256) void k_plan_verify(const float* __restrict__ S
                                                      const double* __restrict__ sr,
                                                      const double* __restrict__ sc, PlanTable pt,
                                                      int N, int* __restrict__ bad) {
-  const int j = blockIdx.x / iblocks;
-  const int i = (blockIdx.x % iblocks) * 256 + threadIdx.x;
-  if (i >= m || j >= n) return;
-  const double Sl = (double)S[(size_t)j * lds_ + i] * pt.acc_scale;
-  if (Sl > 0.0) {
-    const double A1 = rs[i] * sc[j] + sr[i] * cs[j];
-    const double P2 = sr[i] * sc[j];
-    if (!plan_ok(pt, N, A1, P2, pt.eps * Sl)) atomicOr(bad, 1);
-  }
+  int fail = 0;
+  for_entries(m, n, iblocks, [&](int i, int j) {
+    const double Sl = (double)S[(size_t)j * lds_ + i] * pt.acc_scale;
+    if (Sl > 0.0) {
+      const double A1 = rs[i] * sc[j] + sr[i] * cs[j];
+      const double P2 = sr[i] * sc[j];
+      if (!plan_ok(pt, N, A1, P2, pt.eps * Sl)) fail = 1;
+    }
+  });
+  fail = block_max(fail);
+  if (threadIdx.x == 0 && fail) atomicOr(bad, 1);
 }
 
 // A-posteriori est1 of Theorem 1 (eq. thm:err-1) relative to the lower bound
@@ -122,10 +154,8 @@ __global__ __launch_bounds__(256) void k_certify(const T* __restrict__ C, int ld
                                                  const double* __restrict__ sr,
                                                  const double* __restrict__ sc, CertTable ct,
                                                  unsigned long long* __restrict__ out) {
-  const int j = blockIdx.x / iblocks;
-  const int i = (blockIdx.x % iblocks) * 256 + threadIdx.x;
   double ratio = 0.0;
-  if (i < m && j < n) {
+  for_entries(m, n, iblocks, [&](int i, int j) {
     const double Sl = (double)S[(size_t)j * lds_ + i] * ct.acc_scale;
     if (Sl > 0.0) {
       const double c = fabs((double)C[i + (size_t)j * ldc]) + ct.tiny;
@@ -134,17 +164,17 @@ __global__ __launch_bounds__(256) void k_certify(const T* __restrict__ C, int ld
       const double P2 = sr[i] * sc[j];
       const double est =
           (ct.t * A1 + (ct.k * ct.tt + ct.extra + ct.rel * (cpp + ct.rconst) * kTUp) * P2) * kTUp;
-      ratio = est / Sl * kTUp;
+      ratio = fmax(ratio, est / Sl * kTUp);
     }
-  }
-  for (int off = 32; off >= 1; off >>= 1) ratio = fmax(ratio, __shfl_xor(ratio, off));
-  __shared__ double red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ratio;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    atomicMax(out, (unsigned long long)__double_as_longlong(r));
-  }
+  });
+  ratio = block_max(ratio);
+  if (threadIdx.x == 0 && ratio > 0.0)
+    atomicMax(out, (unsigned long long)__double_as_longlong(ratio));
+}
+
+unsigned entry_grid(int iblocks, int n) {
+  const int64_t tasks = (int64_t)iblocks * n;
+  return (unsigned)(tasks < kEntryWorkgroups ? tasks : kEntryWorkgroups);
 }
 
 }  // namespace
@@ -154,7 +184,7 @@ void launch_certify(hipStream_t s, Prec pr, const void* C, int ldc, const int* m
                     const double* sr, const double* sc, const CertTable& ct,
                     unsigned long long* out) {
   const int iblocks = (m + 255) / 256;
-  const dim3 grid((unsigned)iblocks * (unsigned)n), block(256);
+  const dim3 grid(entry_grid(iblocks, n)), block(256);
   if (pr == Prec::F64)
     hipLaunchKernelGGL(k_certify<double>, grid, block, 0, s, (const double*)C, ldc, mu, nu, S,
                        lds_, m, n, iblocks, rs, cs, sr, sc, ct, out);
@@ -174,7 +204,7 @@ void launch_plan_entries(hipStream_t s, const float* S, int lds_, int m, int n, 
                          const double* cs, const double* sr, const double* sc,
                          const PlanTable& pt, int* out) {
   const int iblocks = (m + 255) / 256;
-  hipLaunchKernelGGL(k_plan_entries, dim3((unsigned)iblocks * (unsigned)n), dim3(256), 0, s, S,
+  hipLaunchKernelGGL(k_plan_entries, dim3(entry_grid(iblocks, n)), dim3(256), 0, s, S,
                      lds_, m, n, iblocks, rs, cs, sr, sc, pt, out);
 }
 
@@ -182,7 +212,7 @@ void launch_plan_verify(hipStream_t s, const float* S, int lds_, int m, int n, c
                         const double* cs, const double* sr, const double* sc, const PlanTable& pt,
                         int N, int* bad) {
   const int iblocks = (m + 255) / 256;
-  hipLaunchKernelGGL(k_plan_verify, dim3((unsigned)iblocks * (unsigned)n), dim3(256), 0, s, S,
+  hipLaunchKernelGGL(k_plan_verify, dim3(entry_grid(iblocks, n)), dim3(256), 0, s, S,
                      lds_, m, n, iblocks, rs, cs, sr, sc, pt, N, bad);
 }
 
