@@ -91,13 +91,18 @@ struct Layout {
   size_t rowbits, colbits, rmax, cmax, mu_p, nu_p, mu, nu, ef, flag, A, B, W, total;
 };
 
-// Row padding of one problem's layout.  The residue products use 256x256
-// tiles when there are at least 512 of them (two per CU), which needs m and n
-// padded to 256; otherwise 128x128 tiles, and padding to 128 wastes less.
+// Row padding of one problem's layout.  The products use 256x256 tiles when
+// there are more than 128 of them, which needs m and n padded to 256.  Below
+// 512 such tiles the padding to 256 is taken only if it adds at most 1/8 to
+// the output area of the padding to 128; otherwise 128x128 tiles on the
+// smaller padding.
 int single_row_pad(int m, int n, int N) {
-  const int64_t t = (int64_t)rup((size_t)(m > 0 ? m : 1), 256) / 256 *
-                    ((int64_t)rup((size_t)(n > 0 ? n : 1), 256) / 256) * N;
-  return t >= 512 ? 256 : 128;
+  const int64_t m1 = m > 0 ? m : 1, n1 = n > 0 ? n : 1;
+  const int64_t a256 = (int64_t)rup((size_t)m1, 256) * (int64_t)rup((size_t)n1, 256);
+  const int64_t a128 = (int64_t)rup((size_t)m1, 128) * (int64_t)rup((size_t)n1, 128);
+  const int64_t t = a256 / (256 * 256) * N;
+  if (t >= 512) return 256;
+  return (t > 128 && 8 * a256 <= 9 * a128) ? 256 : 128;
 }
 
 // In a batch, a problem may use 256x256 tiles only if padding it to 256

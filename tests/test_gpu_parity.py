@@ -96,6 +96,28 @@ def test_int32_wrap_at_k_max(monkeypatch):
         assert np.array_equal(host(Cc).T, ref), f"split {split}"
 
 
+def test_single_call_256_tiles_ragged(monkeypatch):
+    # 768 x 1000, k = 130, N = 16: padding n to 256 costs nothing over 128,
+    # and the 16 residue products have 3 x 4 x 16 = 192 tiles of 256 x 256,
+    # so the single call takes the 256 x 256 kernel for them (the scaling
+    # product, 12 tiles, the 128 x 128 one).  The result has the bits of the
+    # batched path with all tiles 128 x 128, and the oracle's on sampled
+    # entries.
+    m, n, k, N = 768, 1000, 130, 16
+    announce(f"single call, 256x256 residue tiles, m={m} n={n} k={k} N={N}")
+    A, B = gemm_inputs(m, n, k, phi=1.0, seed=11)
+    C = host(oz.gemm(dev(A), dev(B), N))
+    assert oz.ozaki2_sync_status() == oz.OK
+    rows, cols = np.array([0, 255, 256, 511, 767]), np.array([0, 255, 256, 767, 768, 999])
+    assert np.array_equal(C[np.ix_(rows, cols)], os_ii(A, B, N, rows=rows, cols=cols))
+    monkeypatch.setenv("OZAKI2_BATCH_SPLIT", "1000000")
+    dA, dB = dev(np.ascontiguousarray(A.T)), dev(np.ascontiguousarray(B.T))
+    Cc = torch.full((n, m), float("nan"), dtype=torch.float64, device="cuda:0")
+    oz.gemm_batched_cm([dA], [dB], [Cc], [(m, n, k)], [N])
+    assert oz.ozaki2_sync_status() == oz.OK
+    assert np.array_equal(host(Cc).T, C)
+
+
 @pytest.mark.parametrize("m,n,k,N,phi", [
     (300, 200, 500, 14, 0.5),     # several 128-tiles in each direction, ragged tails
     (64, 64, 64, 2, 0.5),
