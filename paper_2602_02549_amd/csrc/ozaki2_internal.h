@@ -20,7 +20,7 @@ struct CrtConsts {
   int N;
   int b;            // 64 or 32
   int nsteps;       // exact-reduction steps for |A'| < 2^(6 + floor(P'))
-  int nlimbs;       // 2 or 3: residues from 32-bit limbs of A' (0: use nsteps)
+  int nlimbs;       // 2 or 3: residues from limbs of A' (0: use nsteps)
   float Pprime;     // P' = single_down(log2(P-1)/2 - 0.5)
   float c;          // single_down(-0.5 / (1 - 4 u_32))
   double P1, P2;    // double-double P (P2 = 0 for b = 32)

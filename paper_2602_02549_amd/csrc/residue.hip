@@ -15,14 +15,20 @@
 // Each workgroup walks tiles in a grid-stride loop and issues the loads of
 // its next tile before computing the current one.
 //
-// Residues of the scaled integer v = trunc(2^mu a) (|v| < 2^(6 + floor P'))
-// are exact in FP64.  Up to three 32-bit limbs (N <= 23): v = sum_t v_t 2^(32t)
-// with |v_t| <= 2^31 below the top limb, split once per element; per modulus
-// r = v_0 + sum_t v_t c_t with c_t = mod(2^(32t), p) (exact: |r| < 2^41), and
-// one step r <- r - p * round(r / p) lands in [-(p-1)/2, (p-1)/2] for odd
-// p.  Larger N take nsteps such steps from v itself (each exact, shrinking |r|
-// by ~2^-52 relative; the last starts from |r| < 2^50).  For p = 256 the
-// result lies in [-128, 128] and the byte store wraps 128 to -128.
+// Residues of the scaled integer v = trunc(2^mu a) (|v| < 2^B, B = 6 + floor P')
+// are exact in FP64.  v is split once per element into limbs, and per modulus
+// r = sum_t v_t c_t with c_0 = 1, c_t = mod(2^(s t), p), |c_t| <= 127, is
+// exact and below 2^50; one step r <- r - p * round(r / p) then lands in
+// [-(p-1)/2, (p-1)/2] for odd p.
+//   two limbs (B <= 90, N = 12..22): v = v_1 2^48 + v_0, |v_0| <= 2^47,
+//     |v_1| <= 2^42, so |r| <= 2^47 + 127 * 2^42 < 2^49.4;
+//   three limbs (B <= 122, N = 23..31): v = v_2 2^80 + v_1 2^40 + v_0,
+//     |v_0|, |v_1| <= 2^39, |v_2| <= 2^42, so |r| <= 128 * 2^39 + 127 * 2^42
+//     < 2^49.2.
+// Other N take nsteps such steps from v itself (each exact, shrinking |r| by
+// ~2^-52 relative; the last starts from |r| < 2^50).  For p = 256 the result
+// lies in [-128, 128] and the byte store wraps 128 to -128; 2^48, 2^40 and
+// 2^80 are 0 mod 256.
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
@@ -105,27 +111,29 @@ __device__ __forceinline__ void store_residues(const double (&v)[16], const CrtC
   }
 }
 
-// Limb form of the residues (L = 2 or 3 limbs of 32 bits).
+// Limb form of the residues: L = 2 limbs split at 2^48, or L = 3 limbs
+// split at 2^80 and 2^40 (bounds in the file header).
 template <int L>
 __device__ __forceinline__ void store_residues_limbs(const double (&v)[16], const CrtConsts& cc,
                                                      int8_t* __restrict__ dst, size_t slice) {
   static_assert(L == 2 || L == 3, "limbs");
+  constexpr double kS = L == 2 ? 0x1p48 : 0x1p40, kSinv = L == 2 ? 0x1p-48 : 0x1p-40;
   double lo[16], mid[16], hi[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     double rem = v[e];
     if (L == 3) {
-      hi[e] = round_prod(rem, 0x1p-64);        // |v| < 2^95
-      rem = fma(-hi[e], 0x1p64, rem);          // exact, |rem| <= 2^63
+      hi[e] = round_prod(rem, 0x1p-80);        // |v| < 2^122: |hi| <= 2^42
+      rem = fma(-hi[e], 0x1p80, rem);          // exact, |rem| <= 2^79
     }
-    mid[e] = round_prod(rem, 0x1p-32);
-    lo[e] = fma(-mid[e], 0x1p32, rem);         // exact, |lo| <= 2^31
+    mid[e] = round_prod(rem, kSinv);
+    lo[e] = fma(-mid[e], kS, rem);             // exact, |lo| <= 2^47 (L = 2), 2^39 (L = 3)
   }
   for (int l = 0; l < cc.N; ++l) {
     const double p = (double)cc.p[l];
     const double pinv = cc.pinv[l];
-    const double c1 = reduce_last(0x1p32, p, pinv);                 // mod(2^32, p)
-    const double c2 = L == 3 ? reduce_last(c1 * c1, p, pinv) : 0.0;  // mod(2^64, p)
+    const double c1 = reduce_last(kS, p, pinv);                     // mod(2^s, p)
+    const double c2 = L == 3 ? reduce_last(c1 * c1, p, pinv) : 0.0;  // mod(2^80, p)
     int b[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -223,15 +231,16 @@ __device__ __forceinline__ void tile_stage(const T (&x)[16], int rows, int k, in
 
 // Each thread reads 16 consecutive k of one row from the staged tile and
 // writes 16 bytes per slice (mode 0: Abar; mode 1: the N residues).
-// Residue paths of mode 1: limbs (2 or 3) or exact reduction steps (1-4);
-// kAnyPath chooses at run time from the constants (grouped launches, whose
-// problems differ in N).
-enum ResiduePath { kLimbs2, kLimbs3, kSteps1, kSteps2, kSteps3, kSteps4, kAnyPath };
+// Residue paths of mode 1: limbs (2 or 3) or exact reduction steps (1, 3 or
+// 4; the limbs cover every N that would take two steps, and an extra step is
+// exact anyway); kAnyPath chooses at run time from the constants (grouped
+// launches, whose problems differ in N).
+enum ResiduePath { kLimbs2, kLimbs3, kSteps1, kSteps3, kSteps4, kAnyPath };
 
 int residue_path(const CrtConsts& cc) {
   if (cc.nlimbs == 2) return kLimbs2;
   if (cc.nlimbs == 3) return kLimbs3;
-  return cc.nsteps <= 1 ? kSteps1 : cc.nsteps == 2 ? kSteps2 : cc.nsteps == 3 ? kSteps3 : kSteps4;
+  return cc.nsteps <= 1 ? kSteps1 : cc.nsteps <= 3 ? kSteps3 : kSteps4;
 }
 
 template <int PATH>
@@ -241,7 +250,6 @@ __device__ __forceinline__ void store_residues_path(const double (&v)[16], const
     case kLimbs2: store_residues_limbs<2>(v, cc, dst, slice); break;
     case kLimbs3: store_residues_limbs<3>(v, cc, dst, slice); break;
     case kSteps1: store_residues<1>(v, cc, dst, slice); break;
-    case kSteps2: store_residues<2>(v, cc, dst, slice); break;
     case kSteps3: store_residues<3>(v, cc, dst, slice); break;
     case kSteps4: store_residues<4>(v, cc, dst, slice); break;
     default:
@@ -249,13 +257,12 @@ __device__ __forceinline__ void store_residues_path(const double (&v)[16], const
         store_residues_limbs<2>(v, cc, dst, slice);
       } else if (cc.nlimbs == 3) {
         store_residues_limbs<3>(v, cc, dst, slice);
+      } else if (cc.nsteps <= 1) {
+        store_residues<1>(v, cc, dst, slice);
+      } else if (cc.nsteps <= 3) {
+        store_residues<3>(v, cc, dst, slice);
       } else {
-        switch (cc.nsteps) {
-          case 1: store_residues<1>(v, cc, dst, slice); break;
-          case 2: store_residues<2>(v, cc, dst, slice); break;
-          case 3: store_residues<3>(v, cc, dst, slice); break;
-          default: store_residues<4>(v, cc, dst, slice); break;
-        }
+        store_residues<4>(v, cc, dst, slice);
       }
   }
 }
@@ -479,9 +486,10 @@ __global__ __launch_bounds__(256) void k_plan_slices(const T* __restrict__ src, 
 // units per device, filled once per device by init_slice_launch (outside
 // any stream capture); a grid-stride launch uses at most that many
 // workgroups.  Index: [float][trans / A side][variant], variant 0 = mode 0,
-// 1 + path = mode 1 on that residue path, 7 / 8 = grouped mode 0 / 1.
+// 1 + path = mode 1 on that residue path, kGrouped + mode = grouped.
 constexpr int kMaxDevices = 64;
-constexpr int kVariants = 9;
+constexpr int kGrouped = 1 + kAnyPath;
+constexpr int kVariants = kGrouped + 2;
 std::atomic<int> g_cus[kMaxDevices];
 std::atomic<int> g_occ[2][2][kVariants];
 
@@ -502,11 +510,10 @@ void fill_occ() {
   o[1 + kLimbs2] = resident_per_cu(k_slices<T, TR, 1, kLimbs2>);
   o[1 + kLimbs3] = resident_per_cu(k_slices<T, TR, 1, kLimbs3>);
   o[1 + kSteps1] = resident_per_cu(k_slices<T, TR, 1, kSteps1>);
-  o[1 + kSteps2] = resident_per_cu(k_slices<T, TR, 1, kSteps2>);
   o[1 + kSteps3] = resident_per_cu(k_slices<T, TR, 1, kSteps3>);
   o[1 + kSteps4] = resident_per_cu(k_slices<T, TR, 1, kSteps4>);
-  o[7] = resident_per_cu(kg_slices<T, TR, 0>);
-  o[8] = resident_per_cu(kg_slices<T, TR, 1>);
+  o[kGrouped] = resident_per_cu(kg_slices<T, TR, 0>);
+  o[kGrouped + 1] = resident_per_cu(kg_slices<T, TR, 1>);
 }
 
 // Workgroups for `tiles` tiles: all resident slots of the device, or one per
@@ -555,7 +562,6 @@ void launch_side(hipStream_t s, int mode, const SliceLaunch<T>& L, const CrtCons
     case kLimbs2: launch_one<T, TR, 1, kLimbs2>(s, L, cc); break;
     case kLimbs3: launch_one<T, TR, 1, kLimbs3>(s, L, cc); break;
     case kSteps1: launch_one<T, TR, 1, kSteps1>(s, L, cc); break;
-    case kSteps2: launch_one<T, TR, 1, kSteps2>(s, L, cc); break;
     case kSteps3: launch_one<T, TR, 1, kSteps3>(s, L, cc); break;
     default: launch_one<T, TR, 1, kSteps4>(s, L, cc); break;
   }
@@ -586,7 +592,7 @@ void launch_t(hipStream_t s, int mode, bool trans, const T* src, int ld, int row
 template <typename T, int MODE>
 void group_slices_t(hipStream_t s, bool aside, const ProbDesc* P, const BlockRef* map, int blocks,
                     const CrtConsts* ctab) {
-  const dim3 g((unsigned)slice_grid(std::is_same<T, float>::value, aside, 7 + MODE, blocks)), b(256);
+  const dim3 g((unsigned)slice_grid(std::is_same<T, float>::value, aside, kGrouped + MODE, blocks)), b(256);
   if (aside)
     hipLaunchKernelGGL((kg_slices<T, true, MODE>), g, b, 0, s, P, map, blocks, ctab);
   else

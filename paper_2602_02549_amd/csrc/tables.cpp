@@ -267,10 +267,11 @@ bool build_consts(int N, int b, CrtConsts* out) {
   }
   if (steps > 4) return false;   // the residue kernels instantiate 1..4 steps
   cc.nsteps = steps;
-  // 32-bit limbs of |A'| < 2^B: two limbs keep the upper one within 2^31 for
-  // B <= 63, three for B <= 95; for B <= 50 one reduction step is cheaper.
+  // Limbs of |A'| < 2^B: two (split at 2^48) keep the per-modulus sum below
+  // 2^50 for B <= 90, three (split at 2^80 and 2^40) for B <= 122; for
+  // B <= 50 one reduction step is cheaper.
   const int B = 6 + (int)std::floor((double)cc.Pprime);
-  cc.nlimbs = B <= 50 ? 0 : (B <= 63 ? 2 : (B <= 95 ? 3 : 0));
+  cc.nlimbs = B <= 50 ? 0 : (B <= 90 ? 2 : (B <= 122 ? 3 : 0));
   *out = cc;
   return true;
 }

@@ -125,12 +125,18 @@ def test_single_call_256_tiles_ragged(monkeypatch):
     (257, 129, 130, 20, 1.0),
     (100, 90, 300, 49, 2.0),
     (33, 300, 129, 11, 4.0),
-    # residue paths: two limbs from N = 12, three from N = 15, then 2 and 3
-    # exact reduction steps (N = 24, 30)
+    # residue paths at the ends of their N ranges: two limbs (N = 12..22),
+    # three limbs (N = 23..31), three exact steps (N = 32..40), four (from 41)
     (70, 65, 200, 12, 1.0),
     (70, 65, 200, 15, 1.0),
+    (70, 65, 200, 22, 2.0),
+    (70, 65, 200, 23, 2.0),
     (70, 65, 200, 24, 3.0),
     (70, 65, 200, 30, 4.0),
+    (70, 65, 200, 31, 4.0),
+    (70, 65, 200, 32, 4.0),
+    (70, 65, 200, 40, 4.0),
+    (70, 65, 200, 41, 4.0),
 ])
 def test_stages_fp64(m, n, k, N, phi):
     run_stage_case(m, n, k, N, phi, seed=m + n + k + N, dtype=np.float64)
@@ -150,15 +156,16 @@ def test_slices_few_workgroups(cap, monkeypatch):
     # The slice kernels walk their tiles in a grid-stride loop, prefetching the
     # next tile.  Capped at `cap` workgroups, every workgroup walks many tiles
     # (with 5, unevenly many).  Every stage stays bit-exact on each residue
-    # path (2 and 3 limbs, one and four exact steps, FP32), and the grouped
-    # kernels of a batch give the oracle's result.
+    # path (2 and 3 limbs, one, three and four exact steps, FP32), and the
+    # grouped kernels of a batch give the oracle's result.
     monkeypatch.setenv("OZAKI2_SLICE_WORKGROUPS", cap)
     for m, n, k, N, phi, dt in [(300, 200, 500, 14, 0.5, np.float64), (257, 129, 130, 16, 1.0, np.float64),
-                                (100, 90, 300, 7, 2.0, np.float64), (70, 65, 200, 49, 4.0, np.float64),
+                                (100, 90, 300, 7, 2.0, np.float64), (90, 70, 150, 28, 3.0, np.float64),
+                                (60, 50, 100, 36, 4.0, np.float64), (70, 65, 200, 49, 4.0, np.float64),
                                 (130, 70, 260, 7, 1.0, np.float32)]:
         run_stage_case(m, n, k, N, phi, seed=int(cap) + m + N, dtype=dt)
     announce(f"batched with {cap} slice workgroups")
-    cases = [(300, 200, 500, 14), (129, 257, 64, 16), (40, 30, 50, 30)]
+    cases = [(300, 200, 500, 14), (129, 257, 64, 16), (40, 30, 50, 30), (33, 20, 40, 36)]
     As, Bs, Ccm = [], [], []
     for q, (m, n, k, N) in enumerate(cases):
         A, B = gemm_inputs(m, n, k, phi=1.0, seed=900 + q)
