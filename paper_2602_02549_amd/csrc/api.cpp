@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -403,6 +404,7 @@ struct BatchEntry {
   int blocks[BS_COUNT] = {};             // grid size per slot
   size_t map_off[BS_COUNT] = {};         // byte offset of each slot's block map
   int split = 0;                         // problems with >= split 256x256 tiles use them
+  int res_path = -1;                     // residue path code for the grouped slice kernels
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // The last reference may drop while a replay is still running: wait for
@@ -520,13 +522,13 @@ void enqueue_batch(Prec pr, const BatchEntry& e, const CrtConsts* ctab, int* sta
   launch_group_scale(s, pr, GP_INIT, D, M(BS_INIT), B(BS_INIT), ctab);
   launch_group_scale(s, pr, GP_ABSMAX_A, D, M(BS_ABS_A), B(BS_ABS_A), ctab);
   launch_group_scale(s, pr, GP_ABSMAX_B, D, M(BS_ABS_B), B(BS_ABS_B), ctab);
-  launch_group_slices(s, pr, 0, true, D, M(BS_SL_A), B(BS_SL_A), ctab);
-  launch_group_slices(s, pr, 0, false, D, M(BS_SL_B), B(BS_SL_B), ctab);
+  launch_group_slices(s, pr, 0, true, -1, D, M(BS_SL_A), B(BS_SL_A), ctab);
+  launch_group_slices(s, pr, 0, false, -1, D, M(BS_SL_B), B(BS_SL_B), ctab);
   launch_group_gemm(s, 1, 256, D, M(BS_GS_BIG), B(BS_GS_BIG), ctab);
   launch_group_gemm(s, 1, 128, D, M(BS_GS_SMALL), B(BS_GS_SMALL), ctab);
   launch_group_scale(s, pr, GP_SHIFTS, D, M(BS_SHIFTS), B(BS_SHIFTS), ctab);
-  launch_group_slices(s, pr, 1, true, D, M(BS_SL_A), B(BS_SL_A), ctab);
-  launch_group_slices(s, pr, 1, false, D, M(BS_SL_B), B(BS_SL_B), ctab);
+  launch_group_slices(s, pr, 1, true, e.res_path, D, M(BS_SL_A), B(BS_SL_A), ctab);
+  launch_group_slices(s, pr, 1, false, e.res_path, D, M(BS_SL_B), B(BS_SL_B), ctab);
   launch_group_gemm(s, 0, 256, D, M(BS_GR_BIG), B(BS_GR_BIG), ctab);
   launch_group_gemm(s, 0, 128, D, M(BS_GR_SMALL), B(BS_GR_SMALL), ctab);
   launch_group_crt(s, pr, D, M(BS_CRT), B(BS_CRT), e.active, ctab, status);
@@ -680,6 +682,20 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
       d.As = at<int8_t>(w, L.A);
       d.Bs = at<int8_t>(w, L.B);
       d.W = at<int8_t>(w, L.W);
+    }
+    {
+      // one residue kernel for the whole batch when every N takes the same path
+      std::vector<CrtConsts> cs;
+      std::vector<int> seen;
+      for (const ProbDesc& d : D) {
+        if (std::find(seen.begin(), seen.end(), d.N) != seen.end()) continue;
+        seen.push_back(d.N);
+        cs.emplace_back();
+        if ((rc = get_consts(d.N, pr == Prec::F64 ? 64 : 32, &cs.back()))) return rc;
+      }
+      std::vector<const CrtConsts*> ptrs;
+      for (const CrtConsts& c : cs) ptrs.push_back(&c);
+      e->res_path = group_residue_path(ptrs.data(), (int)ptrs.size());
     }
     std::vector<char> host;
     e->split = forced >= 0 ? forced : 1 << 30;

@@ -205,8 +205,12 @@ void launch_certify(hipStream_t s, Prec pr, const void* C, int ldc, const int* m
 // `map` holds `blocks` entries, one per workgroup.
 void launch_group_scale(hipStream_t s, Prec pr, int phase, const ProbDesc* P, const BlockRef* map,
                         int blocks, const CrtConsts* ctab);
-void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, const ProbDesc* P,
-                         const BlockRef* map, int blocks, const CrtConsts* ctab);
+// The residue path every problem of a batch shares (a code for
+// launch_group_slices), or the per-tile choice when they differ.
+int group_residue_path(const CrtConsts* const* cc, int count);
+void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, int path,
+                         const ProbDesc* P, const BlockRef* map, int blocks,
+                         const CrtConsts* ctab);
 void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const BlockRef* map,
                        int blocks, const CrtConsts* ctab);
 void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const BlockRef* map, int blocks,

@@ -397,7 +397,7 @@ __device__ __forceinline__ bool tile_job(const ProbDesc* __restrict__ P,
 
 // Grouped: A side (TRANS, rows = m) or B side (rows = n) of every problem;
 // the same grid-stride loop over the `tiles` entries of the block map.
-template <typename T, bool ASIDE, int MODE>
+template <typename T, bool ASIDE, int MODE, int PATH>
 __global__ __launch_bounds__(256) void kg_slices(const ProbDesc* __restrict__ P,
                                                  const BlockRef* __restrict__ map, int tiles,
                                                  const CrtConsts* __restrict__ ctab) {
@@ -424,8 +424,8 @@ __global__ __launch_bounds__(256) void kg_slices(const ProbDesc* __restrict__ P,
       xa = row_aux<MODE>(nxt.aux, nxt.rows, nxt.r0);
     }
     lds_barrier();
-    tile_finish<MODE, kAnyPath>(tile, a, cur.rows, cur.k_pad, cur.slice, ctab[cur.N], cur.out, cur.r0,
-                      cur.h0);
+    tile_finish<MODE, PATH>(tile, a, cur.rows, cur.k_pad, cur.slice, ctab[cur.N], cur.out, cur.r0,
+                            cur.h0);
     if (ni >= tiles) break;
     i = ni;
     cur = nxt;
@@ -486,10 +486,11 @@ __global__ __launch_bounds__(256) void k_plan_slices(const T* __restrict__ src, 
 // units per device, filled once per device by init_slice_launch (outside
 // any stream capture); a grid-stride launch uses at most that many
 // workgroups.  Index: [float][trans / A side][variant], variant 0 = mode 0,
-// 1 + path = mode 1 on that residue path, kGrouped + mode = grouped.
+// 1 + path = mode 1 on that residue path (kAnyPath: chosen per tile), and
+// the same plus kGrouped for the grouped kernels.
 constexpr int kMaxDevices = 64;
-constexpr int kGrouped = 1 + kAnyPath;
-constexpr int kVariants = kGrouped + 2;
+constexpr int kGrouped = 2 + kAnyPath;
+constexpr int kVariants = 2 * kGrouped;
 std::atomic<int> g_cus[kMaxDevices];
 std::atomic<int> g_occ[2][2][kVariants];
 
@@ -512,8 +513,13 @@ void fill_occ() {
   o[1 + kSteps1] = resident_per_cu(k_slices<T, TR, 1, kSteps1>);
   o[1 + kSteps3] = resident_per_cu(k_slices<T, TR, 1, kSteps3>);
   o[1 + kSteps4] = resident_per_cu(k_slices<T, TR, 1, kSteps4>);
-  o[kGrouped] = resident_per_cu(kg_slices<T, TR, 0>);
-  o[kGrouped + 1] = resident_per_cu(kg_slices<T, TR, 1>);
+  o[kGrouped] = resident_per_cu(kg_slices<T, TR, 0, kAnyPath>);
+  o[kGrouped + 1 + kLimbs2] = resident_per_cu(kg_slices<T, TR, 1, kLimbs2>);
+  o[kGrouped + 1 + kLimbs3] = resident_per_cu(kg_slices<T, TR, 1, kLimbs3>);
+  o[kGrouped + 1 + kSteps1] = resident_per_cu(kg_slices<T, TR, 1, kSteps1>);
+  o[kGrouped + 1 + kSteps3] = resident_per_cu(kg_slices<T, TR, 1, kSteps3>);
+  o[kGrouped + 1 + kSteps4] = resident_per_cu(kg_slices<T, TR, 1, kSteps4>);
+  o[kGrouped + 1 + kAnyPath] = resident_per_cu(kg_slices<T, TR, 1, kAnyPath>);
 }
 
 // Workgroups for `tiles` tiles: all resident slots of the device, or one per
@@ -589,14 +595,29 @@ void launch_t(hipStream_t s, int mode, bool trans, const T* src, int ld, int row
     launch_side<T, false>(s, mode, L, cc);
 }
 
-template <typename T, int MODE>
-void group_slices_t(hipStream_t s, bool aside, const ProbDesc* P, const BlockRef* map, int blocks,
-                    const CrtConsts* ctab) {
-  const dim3 g((unsigned)slice_grid(std::is_same<T, float>::value, aside, kGrouped + MODE, blocks)), b(256);
-  if (aside)
-    hipLaunchKernelGGL((kg_slices<T, true, MODE>), g, b, 0, s, P, map, blocks, ctab);
-  else
-    hipLaunchKernelGGL((kg_slices<T, false, MODE>), g, b, 0, s, P, map, blocks, ctab);
+template <typename T, bool TR, int MODE, int PATH>
+void launch_group_one(hipStream_t s, const ProbDesc* P, const BlockRef* map, int blocks,
+                      const CrtConsts* ctab) {
+  const int variant = kGrouped + (MODE == 0 ? 0 : 1 + PATH);
+  const dim3 g((unsigned)slice_grid(std::is_same<T, float>::value, TR, variant, blocks)), b(256);
+  hipLaunchKernelGGL((kg_slices<T, TR, MODE, PATH>), g, b, 0, s, P, map, blocks, ctab);
+}
+
+template <typename T, bool TR>
+void group_slices_t(hipStream_t s, int mode, int path, const ProbDesc* P, const BlockRef* map,
+                    int blocks, const CrtConsts* ctab) {
+  if (mode == 0) {
+    launch_group_one<T, TR, 0, kAnyPath>(s, P, map, blocks, ctab);
+    return;
+  }
+  switch (path) {
+    case kLimbs2: launch_group_one<T, TR, 1, kLimbs2>(s, P, map, blocks, ctab); break;
+    case kLimbs3: launch_group_one<T, TR, 1, kLimbs3>(s, P, map, blocks, ctab); break;
+    case kSteps1: launch_group_one<T, TR, 1, kSteps1>(s, P, map, blocks, ctab); break;
+    case kSteps3: launch_group_one<T, TR, 1, kSteps3>(s, P, map, blocks, ctab); break;
+    case kSteps4: launch_group_one<T, TR, 1, kSteps4>(s, P, map, blocks, ctab); break;
+    default: launch_group_one<T, TR, 1, kAnyPath>(s, P, map, blocks, ctab); break;
+  }
 }
 
 }  // namespace
@@ -612,19 +633,31 @@ void init_slice_launch(int dev) {
   g_cus[dev].store(cus, std::memory_order_relaxed);
 }
 
-void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, const ProbDesc* P,
-                         const BlockRef* map, int blocks, const CrtConsts* ctab) {
+int group_residue_path(const CrtConsts* const* cc, int count) {
+  int path = -1;
+  for (int q = 0; q < count; ++q) {
+    const int r = residue_path(*cc[q]);
+    if (path >= 0 && r != path) return kAnyPath;
+    path = r;
+  }
+  return path < 0 ? kAnyPath : path;
+}
+
+void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, int path,
+                         const ProbDesc* P, const BlockRef* map, int blocks,
+                         const CrtConsts* ctab) {
   if (blocks <= 0) return;
+  if (path < 0 || path > kAnyPath) path = kAnyPath;
   if (pr == Prec::F64) {
-    if (mode == 0)
-      group_slices_t<double, 0>(s, aside, P, map, blocks, ctab);
+    if (aside)
+      group_slices_t<double, true>(s, mode, path, P, map, blocks, ctab);
     else
-      group_slices_t<double, 1>(s, aside, P, map, blocks, ctab);
+      group_slices_t<double, false>(s, mode, path, P, map, blocks, ctab);
   } else {
-    if (mode == 0)
-      group_slices_t<float, 0>(s, aside, P, map, blocks, ctab);
+    if (aside)
+      group_slices_t<float, true>(s, mode, path, P, map, blocks, ctab);
     else
-      group_slices_t<float, 1>(s, aside, P, map, blocks, ctab);
+      group_slices_t<float, false>(s, mode, path, P, map, blocks, ctab);
   }
 }
 

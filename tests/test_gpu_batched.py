@@ -69,6 +69,26 @@ def test_batched_matches_single_and_oracle(dtype):
             assert np.array_equal(got, os_ii(A, B, N)), f"problem {q} {cases[q]} vs oracle"
 
 
+@pytest.mark.parametrize("N,dtype", [(7, np.float64), (14, np.float64), (28, np.float64),
+                                     (36, np.float64), (45, np.float64), (16, np.float32)])
+def test_batched_one_residue_path(N, dtype):
+    # Every problem takes the same residue path (one exact step, two limbs,
+    # three limbs, three and four exact steps; FP32 on two limbs), so the
+    # batch runs the grouped residue kernel built for that path alone.  A
+    # problem of another N in the same batch brings back the per-tile choice.
+    cases = [(70, 50, 90, N), (129, 257, 64, N), (33, 20, 300, N), (1, 3, 2, N)]
+    announce(f"batched, one residue path: N={N} {np.dtype(dtype).name}")
+    As, Bs = make_batch(cases, dtype, seed=300 + N)
+    for Ns in ([N] * 4, [N, N, N, 2]):
+        _, _, Ccm, _ = run_batched(As, Bs, Ns)
+        assert oz.ozaki2_sync_status() == oz.OK
+        for q, (A, B, Nq) in enumerate(zip(As, Bs, Ns)):
+            got = host(Ccm[q]).T
+            assert np.array_equal(got, single(A, B, Nq)), f"problem {q} {cases[q][:3]} N={Nq}"
+            if q == 3:
+                assert np.array_equal(got, os_ii(A, B, Nq)), f"problem {q} vs oracle"
+
+
 @pytest.mark.parametrize("split", ["0", "1000000", "4"])
 def test_batched_tile_splits_and_eager(split, monkeypatch):
     # Every tile split (all 256x256, all 128x128, mixed) and the eager
