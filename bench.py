@@ -478,6 +478,14 @@ def main():
     out["int8_fraction_whole_call"] = round((N + 1) * flops / (ms * 1e-3) / 1e12 / PEAK_INT8_TOPS, 4)
     out["memory_phases"] = memory_phases(torch, dev, phase_ms, m, n, k, N, 8)
     out["mall_flushed"] = flushed_timing(torch, dev, emulate, N, max(args.steps, 10))
+    # The N that Theorem 1's bound demands for 1e-15 (reading R16), planned
+    # outside the timed region, as the paper reports planning separately.
+    times = []
+    for _ in range(3):
+        t_plan = time.perf_counter()
+        rc_b, N_b = oz.ozaki2_required_moduli(64, m, n, k, Acm.data_ptr(), m, Bcm.data_ptr(), k, 1e-15)
+        times.append((time.perf_counter() - t_plan) * 1e3)
+    out["bound_N_1e-15"] = {"N": N_b, "reachable": rc_b == oz.OK, "plan_ms": round(min(times), 3)}
     del Acm, Bcm, Ccm, dA, dB
     torch.cuda.empty_cache()
     if not args.no_batched:

@@ -22,6 +22,9 @@ constexpr double kSumUp = 1.0 + 0x1p-30;
 constexpr double kSqrtUp = 1.0 + 0x1p-50;
 constexpr double kTUp = 1.0 + 0x1p-40;   // a few roundings in T itself
 
+// One workgroup per 64 entries (rows of A first, then columns of B); its four
+// waves sum every fourth tile of the partial sums, coalesced across the 64
+// entries, and the four partial sums are added in a fixed order.
 __global__ __launch_bounds__(256) void k_plan_vectors(const double* __restrict__ pr, int m_pad,
                                                       const double* __restrict__ pc, int n_pad,
                                                       int tiles, const int* __restrict__ rmax,
@@ -29,14 +32,22 @@ __global__ __launch_bounds__(256) void k_plan_vectors(const double* __restrict__
                                                       double* __restrict__ rs, double* __restrict__ cs,
                                                       double* __restrict__ sr,
                                                       double* __restrict__ sc) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= m + n) return;
+  __shared__ double part[4][64];
+  const int e = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + e;
+  const bool valid = t < m + n;
   const bool row = t < m;
   const int idx = row ? t : t - m;
-  const double* p = row ? pr + idx : pc + idx;
-  const int stride = row ? m_pad : n_pad;
   double s = 0.0;
-  for (int q = 0; q < tiles; ++q) s += p[(size_t)q * stride];     // fixed order
+  if (valid) {
+    const double* p = row ? pr + idx : pc + idx;
+    const int stride = row ? m_pad : n_pad;
+    for (int q = g; q < tiles; q += 4) s += p[(size_t)q * stride];
+  }
+  part[g][e] = s;
+  __syncthreads();
+  if (g != 0 || !valid) return;
+  s = (part[0][e] + part[1][e]) + (part[2][e] + part[3][e]);
   const double M = (double)(row ? rmax[idx] : cmax[idx]);
   if (row) {
     rs[idx] = s * kSumUp;
@@ -196,7 +207,7 @@ void launch_certify(hipStream_t s, Prec pr, const void* C, int ldc, const int* m
 void launch_plan_vectors(hipStream_t s, const double* pr, int m_pad, const double* pc, int n_pad,
                          int tiles, const int* rmax, const int* cmax, int m, int n, double* rs,
                          double* cs, double* sr, double* sc) {
-  hipLaunchKernelGGL(k_plan_vectors, dim3((m + n + 255) / 256), dim3(256), 0, s, pr, m_pad, pc,
+  hipLaunchKernelGGL(k_plan_vectors, dim3((m + n + 63) / 64), dim3(256), 0, s, pr, m_pad, pc,
                      n_pad, tiles, rmax, cmax, m, n, rs, cs, sr, sc);
 }
 
