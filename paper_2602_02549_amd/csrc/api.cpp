@@ -264,10 +264,22 @@ P* at(char* base, size_t off) {
   return reinterpret_cast<P*>(base + off);
 }
 
-// The launch sequence of Algorithm 1 for one problem (m, n, k >= 1).
+// Results of the scaling pass (Algorithm 2 up to the maxima of Cbar) that a
+// caller has already computed for the same A and B: the row and column
+// abs-max bit patterns, the maxima of Cbar and the non-finite flag.
+struct PreScale {
+  const uint64_t* rowbits;
+  const uint64_t* colbits;
+  const int* rmax;
+  const int* cmax;
+  int* flag;
+};
+
+// The launch sequence of Algorithm 1 for one problem (m, n, k >= 1).  With
+// `pre`, the scaling pass is taken from there and not run again.
 int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
                  void* C, int ldc, const CrtConsts& cc, const Layout& L, char* ws, int* status,
-                 hipStream_t s, bool want_ef) {
+                 hipStream_t s, bool want_ef, const PreScale* pre = nullptr) {
   uint64_t* rowbits = at<uint64_t>(ws, L.rowbits);
   uint64_t* colbits = at<uint64_t>(ws, L.colbits);
   int* rmax = at<int>(ws, L.rmax);
@@ -278,31 +290,39 @@ int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   int8_t* W = at<int8_t>(ws, L.W);
   int* mu = at<int>(ws, L.mu);
   int* nu = at<int>(ws, L.nu);
-  {
-    Scope sc(PH_INIT, s);
-    launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
-  }
-  {
-    Scope sc(PH_ABSMAX_A, s);
-    launch_absmax_rows(s, pr, A, lda, m, k, rowbits, flag);
-  }
-  {
-    Scope sc(PH_ABSMAX_B, s);
-    launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag);
-  }
-  // Abar = ceil(2^mu' |A|), Bbar = ceil(|B| 2^nu') into slice 0 of the operand buffers.
-  {
-    Scope sc(PH_BAR_A, s);
-    launch_slices(s, pr, 0, true, A, lda, m, k, L.mp, L.kp, rowbits, nullptr, cc, As);
-  }
-  {
-    Scope sc(PH_BAR_B, s);
-    launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc, Bs);
-  }
-  // Cbar = Abar Bbar; keep row maxima (over j) and column maxima (over i).
-  {
-    Scope sc(PH_GEMM_SCALE, s);
-    launch_gemm_i8(s, 1, As, 0, Bs, 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax);
+  if (pre) {
+    rowbits = const_cast<uint64_t*>(pre->rowbits);
+    colbits = const_cast<uint64_t*>(pre->colbits);
+    rmax = const_cast<int*>(pre->rmax);
+    cmax = const_cast<int*>(pre->cmax);
+    flag = pre->flag;
+  } else {
+    {
+      Scope sc(PH_INIT, s);
+      launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
+    }
+    {
+      Scope sc(PH_ABSMAX_A, s);
+      launch_absmax_rows(s, pr, A, lda, m, k, rowbits, flag);
+    }
+    {
+      Scope sc(PH_ABSMAX_B, s);
+      launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag);
+    }
+    // Abar = ceil(2^mu' |A|), Bbar = ceil(|B| 2^nu') into slice 0 of the operand buffers.
+    {
+      Scope sc(PH_BAR_A, s);
+      launch_slices(s, pr, 0, true, A, lda, m, k, L.mp, L.kp, rowbits, nullptr, cc, As);
+    }
+    {
+      Scope sc(PH_BAR_B, s);
+      launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc, Bs);
+    }
+    // Cbar = Abar Bbar; keep row maxima (over j) and column maxima (over i).
+    {
+      Scope sc(PH_GEMM_SCALE, s);
+      launch_gemm_i8(s, 1, As, 0, Bs, 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax);
+    }
   }
   {
     Scope sc(PH_SHIFTS, s);
@@ -1011,7 +1031,12 @@ int ozaki2_gemm_certified(int prec, int m, int n, int k, const void* A, int lda,
     if ((rc = get_consts(N, b, &cc))) return rc;
     const Layout Lg = layout(m, n, k, N, single_row_pad(m, n, N));
     char* wg = ws + off;
-    if ((rc = run_pipeline(pr, m, n, k, A, lda, B, ldb, C, ldc, cc, Lg, wg, status, s, false)))
+    // The planner terms include the scaling pass of Algorithm 2 on the same
+    // inputs (the same kernels, so the same bits): the runs start from it.
+    const PreScale pre{at<uint64_t>(ws, Lp.rowbits), at<uint64_t>(ws, Lp.colbits),
+                       at<int>(ws, Lp.rmax), at<int>(ws, Lp.cmax), at<int>(ws, Lp.flag)};
+    if ((rc = run_pipeline(pr, m, n, k, A, lda, B, ldb, C, ldc, cc, Lg, wg, status, s, false,
+                           &pre)))
       return rc;
     CertTable ct;
     ct.t = pc.t[N];
@@ -1030,7 +1055,7 @@ int ozaki2_gemm_certified(int prec, int m, int n, int k, const void* A, int lda,
     unsigned long long bits = 0;
     int hflag = 0;
     if (hipMemcpyAsync(&bits, word, sizeof(bits), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&hflag, at<int>(wg, Lg.flag), sizeof(int), hipMemcpyDeviceToHost, s) !=
+        hipMemcpyAsync(&hflag, pre.flag, sizeof(int), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return OZAKI2_ERR_HIP;
