@@ -907,9 +907,13 @@ int plan_search(const PlanLayout& L, char* ws, int m, int n, int k, double eps, 
   const double *sr = at<double>(ws, L.sr), *scv = at<double>(ws, L.sc);
   if (hipMemsetAsync(res, 0, 2 * sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
   launch_plan_entries(s, S, L.mp, m, n, rs, cs, sr, scv, pt, res);
-  int host = 0;
+  // The largest per-entry minimum is checked on every entry in the same
+  // round trip (the bound is not monotone in N once the N-dependent
+  // accumulation term dominates, so it may fail somewhere).
+  launch_plan_verify(s, S, L.mp, m, n, rs, cs, sr, scv, pt, 0, res, res + 1);
+  int host[2] = {0, 0};
   int hflag = 0;
-  if (hipMemcpyAsync(&host, res, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(host, res, 2 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return OZAKI2_ERR_HIP;
@@ -917,18 +921,18 @@ int plan_search(const PlanLayout& L, char* ws, int m, int n, int k, double eps, 
     *N_out = nhi;
     return OZAKI2_ERR_NONFINITE;
   }
-  // The smallest N that satisfies every entry: start at the largest
-  // per-entry minimum and check all entries (the bound is not monotone in N
-  // once the N-dependent accumulation term dominates).
-  int N = host < 2 ? 2 : host;
-  for (; N <= nhi; ++N) {
-    if (hipMemsetAsync(res + 1, 0, sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
-    launch_plan_verify(s, S, L.mp, m, n, rs, cs, sr, scv, pt, N, res + 1);
-    int bad = 0;
-    if (hipMemcpyAsync(&bad, res + 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return OZAKI2_ERR_HIP;
-    if (!bad) break;
+  int N = host[0] < 2 ? 2 : host[0];
+  if (N <= nhi && host[1]) {
+    // N failed on some entry: the smallest larger N that satisfies all.
+    for (++N; N <= nhi; ++N) {
+      if (hipMemsetAsync(res + 1, 0, sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
+      launch_plan_verify(s, S, L.mp, m, n, rs, cs, sr, scv, pt, N, nullptr, res + 1);
+      int bad = 0;
+      if (hipMemcpyAsync(&bad, res + 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return OZAKI2_ERR_HIP;
+      if (!bad) break;
+    }
   }
   if (N > nhi) {
     *N_out = nhi;

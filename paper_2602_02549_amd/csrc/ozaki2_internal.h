@@ -191,9 +191,10 @@ void launch_plan_vectors(hipStream_t s, const double* pr, int m_pad, const doubl
 void launch_plan_entries(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
                          const double* cs, const double* sr, const double* sc,
                          const PlanTable& pt, int* out);
+// N from Nsrc (device) when it is not null; see k_plan_verify.
 void launch_plan_verify(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
                         const double* cs, const double* sr, const double* sc, const PlanTable& pt,
-                        int N, int* bad);
+                        int N, const int* Nsrc, int* bad);
 // Maximum over entries of the a-posteriori est1 / S (bit pattern into *out,
 // which the caller zeroes); C is the output of the run whose shifts are mu, nu.
 void launch_certify(hipStream_t s, Prec pr, const void* C, int ldc, const int* mu, const int* nu,

@@ -123,14 +123,19 @@ __global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ 
   if (threadIdx.x == 0 && need > 0) atomicMax(out, need);
 }
 
-// Pass 2: does N satisfy every entry?  Any failure sets *bad.
+// Pass 2: does N satisfy every entry?  Any failure sets *bad.  With Nsrc,
+// N is read from there (pass 1's result, at least nlo), and nothing is
+// checked if it exceeds nhi.
 __global__ __launch_bounds__(256) void k_plan_verify(const float* __restrict__ S, int lds_, int m,
                                                      int n, int iblocks,
                                                      const double* __restrict__ rs,
                                                      const double* __restrict__ cs,
                                                      const double* __restrict__ sr,
                                                      const double* __restrict__ sc, PlanTable pt,
-                                                     int N, int* __restrict__ bad) {
+                                                     int N, const int* __restrict__ Nsrc,
+                                                     int* __restrict__ bad) {
+  if (Nsrc) N = max(__builtin_amdgcn_readfirstlane(*Nsrc), pt.nlo);
+  if (N > pt.nhi) return;   // uniform: before any barrier
   int fail = 0;
   for_entries(m, n, iblocks, [&](int i, int j) {
     const double Sl = (double)S[(size_t)j * lds_ + i] * pt.acc_scale;
@@ -221,10 +226,10 @@ void launch_plan_entries(hipStream_t s, const float* S, int lds_, int m, int n, 
 
 void launch_plan_verify(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
                         const double* cs, const double* sr, const double* sc, const PlanTable& pt,
-                        int N, int* bad) {
+                        int N, const int* Nsrc, int* bad) {
   const int iblocks = (m + 255) / 256;
   hipLaunchKernelGGL(k_plan_verify, dim3(entry_grid(iblocks, n)), dim3(256), 0, s, S,
-                     lds_, m, n, iblocks, rs, cs, sr, sc, pt, N, bad);
+                     lds_, m, n, iblocks, rs, cs, sr, sc, pt, N, Nsrc, bad);
 }
 
 }  // namespace oz2
