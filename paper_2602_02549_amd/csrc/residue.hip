@@ -435,7 +435,9 @@ __global__ __launch_bounds__(256) void kg_slices(const ProbDesc* __restrict__ P,
 // Planner operands: x = |a| 2^-alpha (alpha = floor(log2 max_h |a_ih|), so
 // x < 2) truncated toward zero to BF16 -- every stored value is a lower bound
 // of the exact one -- and, per 64-k tile, the FP64 sum of the exact x of each
-// row (partial[tile][row], reduced in a fixed order).
+// row (partial[tile][row], reduced in a fixed order).  Workgroups walk the
+// 64 x 64 tiles in a grid-stride loop and load the next tile into registers
+// before they convert the current one.
 template <typename T, bool TRANS>
 __global__ __launch_bounds__(256) void k_plan_slices(const T* __restrict__ src, int ld, int rows,
                                                      int k, int k_pad, int rows_pad,
@@ -444,42 +446,60 @@ __global__ __launch_bounds__(256) void k_plan_slices(const T* __restrict__ src, 
                                                      double* __restrict__ partial) {
   __shared__ double tile[kPlanTile][kPlanTile + 1];
   const int t = threadIdx.x;
-  const int r0 = blockIdx.y * kPlanTile, h0 = blockIdx.x * kPlanTile;
-  if (TRANS) {
-    const int r = t & 63, rg = r0 + r;
+  const int tk = k_pad / kPlanTile;
+  const int ntiles = tk * (rows_pad / kPlanTile);
+  int id = blockIdx.x;
+  if (id >= ntiles) return;   // whole workgroup, before any barrier
+  // thread t stages element (r, h) = (t & 63, (t >> 6) + 4q) of the tile
+  // (TRANS: rows contiguous in memory) or (r, h) = ((t >> 6) + 4q, t & 63)
+  auto load = [&](int tid, T (&x)[16]) {
+    const int r0 = (tid / tk) * kPlanTile, h0 = (tid % tk) * kPlanTile;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int h = (t >> 6) + 4 * q, hg = h0 + h;
-      tile[r][h] = (rg < rows && hg < k) ? (double)src[rg + (size_t)hg * ld] : 0.0;
+      const int a = t & 63, b = (t >> 6) + 4 * q;
+      const int rg = r0 + (TRANS ? a : b), hg = h0 + (TRANS ? b : a);
+      x[q] = (rg < rows && hg < k) ? (TRANS ? src[rg + (size_t)hg * ld] : src[hg + (size_t)rg * ld])
+                                   : (T)0;
     }
-  } else {
-    const int h = t & 63, hg = h0 + h;
+  };
+  T x[16];
+  load(id, x);
+  for (;;) {
+    __syncthreads();   // the previous tile has been read
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int r = (t >> 6) + 4 * q, rg = r0 + r;
-      tile[r][h] = (rg < rows && hg < k) ? (double)src[hg + (size_t)rg * ld] : 0.0;
+      const int a = t & 63, b = (t >> 6) + 4 * q;
+      if (TRANS)
+        tile[a][b] = (double)x[q];
+      else
+        tile[b][a] = (double)x[q];
     }
-  }
-  __syncthreads();
-  const int r = t >> 2, hc = (t & 3) * 16, rg = r0 + r;
-  const int sh = rg < rows ? shift_prime_bits(bits[rg]) - 5 : 0;   // -alpha
-  uint32_t packed[8];
-  double sum = 0.0;
+    __syncthreads();
+    const int cur = id;
+    id += (int)gridDim.x;
+    if (id < ntiles) load(id, x);
+    const int r0 = (cur / tk) * kPlanTile, h0 = (cur % tk) * kPlanTile;
+    const int r = t >> 2, hc = (t & 3) * 16, rg = r0 + r;
+    const int sh = rg < rows ? shift_prime_bits(bits[rg]) - 5 : 0;   // -alpha
+    uint32_t packed[8];
+    double sum = 0.0;
 #pragma unroll
-  for (int e = 0; e < 16; e += 2) {
-    const double x0 = ldexp(fabs(tile[r][hc + e]), sh), x1 = ldexp(fabs(tile[r][hc + e + 1]), sh);
-    sum += x0;
-    sum += x1;
-    const uint32_t b0 = __float_as_uint(__double2float_rz(x0)) >> 16;
-    const uint32_t b1 = __float_as_uint(__double2float_rz(x1)) >> 16;
-    packed[e >> 1] = b0 | (b1 << 16);
+    for (int e = 0; e < 16; e += 2) {
+      const double x0 = ldexp(fabs(tile[r][hc + e]), sh), x1 = ldexp(fabs(tile[r][hc + e + 1]), sh);
+      sum += x0;
+      sum += x1;
+      const uint32_t b0 = __float_as_uint(__double2float_rz(x0)) >> 16;
+      const uint32_t b1 = __float_as_uint(__double2float_rz(x1)) >> 16;
+      packed[e >> 1] = b0 | (b1 << 16);
+    }
+    uint4* dst = reinterpret_cast<uint4*>(out + (size_t)rg * k_pad + h0 + hc);
+    dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+    dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+    sum += __shfl_xor(sum, 1);
+    sum += __shfl_xor(sum, 2);
+    if ((t & 3) == 0) partial[(size_t)(cur % tk) * rows_pad + rg] = sum;
+    if (id >= ntiles) break;
   }
-  uint4* dst = reinterpret_cast<uint4*>(out + (size_t)rg * k_pad + h0 + hc);
-  dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-  dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
-  sum += __shfl_xor(sum, 1);
-  sum += __shfl_xor(sum, 2);
-  if ((t & 3) == 0) partial[(size_t)blockIdx.x * rows_pad + rg] = sum;
 }
 
 // Resident workgroups per compute unit of each slice kernel and compute
@@ -664,7 +684,14 @@ void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, int path,
 void launch_plan_slices(hipStream_t s, Prec pr, bool trans, const void* src, int ld, int rows,
                         int k, int rows_pad, int k_pad, const uint64_t* bits, uint16_t* out,
                         double* partial) {
-  dim3 grid(k_pad / kPlanTile, rows_pad / kPlanTile);
+  // Four workgroups per CU (33 KB of LDS each) walk the tiles.
+  const int64_t tiles = (int64_t)(k_pad / kPlanTile) * (rows_pad / kPlanTile);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices)
+    cus = g_cus[dev].load(std::memory_order_relaxed);
+  if (tiles <= 0) return;
+  const int64_t cap = 4 * (int64_t)(cus > 0 ? cus : 256);
+  const dim3 grid((unsigned)(tiles < cap ? tiles : cap));
   if (pr == Prec::F64) {
     if (trans)
       hipLaunchKernelGGL((k_plan_slices<double, true>), grid, dim3(256), 0, s, (const double*)src,
