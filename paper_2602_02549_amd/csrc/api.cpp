@@ -305,18 +305,23 @@ int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const voi
       Scope sc(PH_ABSMAX_A, s);
       launch_absmax_rows(s, pr, A, lda, m, k, rowbits, flag);
     }
-    {
+    // Abar = ceil(2^mu' |A|), Bbar = ceil(|B| 2^nu') into slice 0 of the operand buffers.
+    // Up to kAbsBarMaxK the abs-max of B and Bbar come from one read of B.
+    const bool fuse_b = L.kp <= kAbsBarMaxK;
+    if (!fuse_b) {
       Scope sc(PH_ABSMAX_B, s);
       launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag);
     }
-    // Abar = ceil(2^mu' |A|), Bbar = ceil(|B| 2^nu') into slice 0 of the operand buffers.
     {
       Scope sc(PH_BAR_A, s);
       launch_slices(s, pr, 0, true, A, lda, m, k, L.mp, L.kp, rowbits, nullptr, cc, As);
     }
     {
       Scope sc(PH_BAR_B, s);
-      launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc, Bs);
+      if (fuse_b)
+        launch_absbar_cols(s, pr, B, ldb, k, n, L.np, L.kp, colbits, flag, Bs);
+      else
+        launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc, Bs);
     }
     // Cbar = Abar Bbar; keep row maxima (over j) and column maxima (over i).
     {
@@ -858,12 +863,16 @@ void plan_terms(Prec pr, int m, int n, int k, const void* A, int lda, const void
   Scope sc(PH_PLAN, s);
   launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
   launch_absmax_rows(s, pr, A, lda, m, k, rowbits, flag);
-  launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag);
   // Cbar maxima exactly as the emulation computes them (Algorithm 2)
   launch_slices(s, pr, 0, true, A, lda, m, k, L.mp, L.kp, rowbits, nullptr, cc,
                 at<int8_t>(ws, L.Abar));
-  launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc,
-                at<int8_t>(ws, L.Bbar));
+  if (L.kp <= kAbsBarMaxK) {
+    launch_absbar_cols(s, pr, B, ldb, k, n, L.np, L.kp, colbits, flag, at<int8_t>(ws, L.Bbar));
+  } else {
+    launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag);
+    launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc,
+                  at<int8_t>(ws, L.Bbar));
+  }
   launch_gemm_i8(s, 1, at<int8_t>(ws, L.Abar), 0, at<int8_t>(ws, L.Bbar), 0, L.mp, L.np, L.kp, 1,
                  cc, nullptr, 0, 0, rmax, cmax);
   // scaled |A|, |B| as BF16 lower bounds, with upward row / column sums

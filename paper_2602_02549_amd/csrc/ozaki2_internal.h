@@ -146,6 +146,11 @@ void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, i
                         uint64_t* rowbits, int* flag);
 void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,
                         uint64_t* colbits, int* flag);
+// Abs-max of the columns of B and Bbar (slice 0, K-major [n_pad][k_pad]) in
+// one read of B; for k_pad <= kAbsBarMaxK.
+constexpr int kAbsBarMaxK = 8192;
+void launch_absbar_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n, int n_pad,
+                        int k_pad, uint64_t* colbits, int* flag, int8_t* out);
 void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int m,
                    const uint64_t* colbits, const int* cmax, int n, float Pprime, float c,
                    int* mu_p, int* nu_p, int* mu, int* nu, float* ef);

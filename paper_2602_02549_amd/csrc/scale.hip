@@ -108,6 +108,72 @@ __global__ __launch_bounds__(256) void k_absmax_cols(const T* __restrict__ B, in
   absmax_cols_body<T>(B, ldb, k, n, colbits, flag, blockIdx.x);
 }
 
+// B column-major (k x n) with k_pad <= kAbsBarMaxK: the abs-max pass and the
+// Bbar pass of Algorithm 2 in one read of B.  One workgroup per row j of the
+// padded K-major Bbar (n_pad of them): the column is held in registers (two
+// consecutive k per lane, 512 per workgroup pass), its abs-max bit pattern
+// is reduced over the workgroup, and Bbar = ceil(2^nu'_j |b|) (1 for a tiny
+// nonzero b, 0 for b = 0) is written from the same registers, zero beyond k
+// and for the padding rows j >= n.
+constexpr int kAbsBarPasses = kAbsBarMaxK / 512;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_absbar_cols(const T* __restrict__ B, int ldb, int k, int n,
+                                                     int k_pad, uint64_t* __restrict__ colbits,
+                                                     int* __restrict__ flag,
+                                                     int8_t* __restrict__ out) {
+  const int j = blockIdx.x, t = threadIdx.x;
+  double x[2 * kAbsBarPasses];
+  uint64_t mx = 0;
+  if (j < n) {
+    const T* col = B + (size_t)j * ldb;
+#pragma unroll
+    for (int q = 0; q < kAbsBarPasses; ++q) {
+      const int h = 2 * t + 512 * q;
+      x[2 * q] = h < k ? (double)col[h] : 0.0;
+      x[2 * q + 1] = h + 1 < k ? (double)col[h + 1] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 2 * kAbsBarPasses; ++e) {
+      const uint64_t b = (uint64_t)__double_as_longlong(fabs(x[e]));
+      mx = b > mx ? b : mx;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 2 * kAbsBarPasses; ++e) x[e] = 0.0;
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor((unsigned long long)mx, off);
+    mx = o > mx ? o : mx;
+  }
+  __shared__ unsigned long long red[4];
+  if ((t & 63) == 0) red[t >> 6] = mx;
+  __syncthreads();
+  mx = red[0];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) mx = red[w] > mx ? red[w] : mx;
+  if (j < n && t == 0) {
+    if ((mx & kExpMask) == kExpMask) atomicOr(flag, 1);
+    colbits[j] = mx;
+  }
+  const int sh = j < n ? shift_prime_bits(mx) : 0;
+  int8_t* dst = out + (size_t)j * k_pad;
+#pragma unroll
+  for (int q = 0; q < kAbsBarPasses; ++q) {
+    const int h = 2 * t + 512 * q;
+    if (h < k_pad) {
+      int b[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double a = fabs(x[2 * q + u]);
+        const double cl = ceil(ldexp(a, sh));
+        b[u] = a == 0.0 ? 0 : (cl < 1.0 ? 1 : (int)cl);
+      }
+      *reinterpret_cast<uint16_t*>(dst + h) = (uint16_t)((b[0] & 0xFF) | ((b[1] & 0xFF) << 8));
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // double-double helpers (Dekker / Knuth error-free transformations)
 // ---------------------------------------------------------------------------
@@ -310,6 +376,17 @@ void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, i
   else
     hipLaunchKernelGGL(k_absmax_cols<float>, grid, dim3(256), 0, s, (const float*)B, ldb, k, n,
                        colbits, flag);
+}
+
+void launch_absbar_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n, int n_pad,
+                        int k_pad, uint64_t* colbits, int* flag, int8_t* out) {
+  if (n_pad <= 0) return;
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL(k_absbar_cols<double>, dim3((unsigned)n_pad), dim3(256), 0, s,
+                       (const double*)B, ldb, k, n, k_pad, colbits, flag, out);
+  else
+    hipLaunchKernelGGL(k_absbar_cols<float>, dim3((unsigned)n_pad), dim3(256), 0, s,
+                       (const float*)B, ldb, k, n, k_pad, colbits, flag, out);
 }
 
 void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int m,
