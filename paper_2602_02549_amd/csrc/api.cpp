@@ -413,9 +413,12 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
 // phase, a prefix array of workgroup counts).  The launch sequence is captured
 // once per batch signature into a hipGraph and replayed on later calls.
 // ---------------------------------------------------------------------------
+// BS_ABB: abs-max of B with Bbar in one read (k_pad <= kAbsBarMaxK);
+// BS_ABS_B and BS_BAR_B: the two passes for the other problems; BS_SL_B: the
+// residues of B for every problem.
 enum BatchSlot {
-  BS_INIT, BS_ABS_A, BS_ABS_B, BS_SL_A, BS_SL_B, BS_GS_BIG, BS_GS_SMALL, BS_SHIFTS, BS_GR_BIG,
-  BS_GR_SMALL, BS_CRT, BS_COUNT
+  BS_INIT, BS_ABS_A, BS_ABS_B, BS_ABB, BS_SL_A, BS_BAR_B, BS_SL_B, BS_GS_BIG, BS_GS_SMALL,
+  BS_SHIFTS, BS_GR_BIG, BS_GR_SMALL, BS_CRT, BS_COUNT
 };
 constexpr int kMaxBatchEntries = 8;
 
@@ -501,8 +504,11 @@ void build_table(const std::vector<ProbDesc>& D, int split, std::vector<char>* o
     int* cp = &c[(size_t)p * BS_COUNT];
     cp[BS_INIT] = group_init_blocks(d.mp, d.np);
     cp[BS_ABS_A] = cdiv_i(d.m, 256) * cdiv_i(d.k, 64);
-    cp[BS_ABS_B] = absmax_cols_blocks(d.n);
+    const bool fuse_b = d.kp <= kAbsBarMaxK;
+    cp[BS_ABS_B] = fuse_b ? 0 : absmax_cols_blocks(d.n);
+    cp[BS_ABB] = fuse_b ? absbar_group_blocks(d.np, d.kp) : 0;
     cp[BS_SL_A] = (d.kp / 128) * (d.mp / 32);
+    cp[BS_BAR_B] = fuse_b ? 0 : (d.kp / 128) * (d.np / 32);
     cp[BS_SL_B] = (d.kp / 128) * (d.np / 32);
     cp[BS_GS_BIG] = big ? group_gemm_blocks(d.mp, d.np, 256, 1) : 0;
     cp[BS_GS_SMALL] = big ? 0 : group_gemm_blocks(d.mp, d.np, 128, 1);
@@ -547,8 +553,9 @@ void enqueue_batch(Prec pr, const BatchEntry& e, const CrtConsts* ctab, int* sta
   launch_group_scale(s, pr, GP_INIT, D, M(BS_INIT), B(BS_INIT), ctab);
   launch_group_scale(s, pr, GP_ABSMAX_A, D, M(BS_ABS_A), B(BS_ABS_A), ctab);
   launch_group_scale(s, pr, GP_ABSMAX_B, D, M(BS_ABS_B), B(BS_ABS_B), ctab);
+  launch_group_scale(s, pr, GP_ABSBAR_B, D, M(BS_ABB), B(BS_ABB), ctab);
   launch_group_slices(s, pr, 0, true, -1, D, M(BS_SL_A), B(BS_SL_A), ctab);
-  launch_group_slices(s, pr, 0, false, -1, D, M(BS_SL_B), B(BS_SL_B), ctab);
+  launch_group_slices(s, pr, 0, false, -1, D, M(BS_BAR_B), B(BS_BAR_B), ctab);
   launch_group_gemm(s, 1, 256, D, M(BS_GS_BIG), B(BS_GS_BIG), ctab);
   launch_group_gemm(s, 1, 128, D, M(BS_GS_SMALL), B(BS_GS_SMALL), ctab);
   launch_group_scale(s, pr, GP_SHIFTS, D, M(BS_SHIFTS), B(BS_SHIFTS), ctab);

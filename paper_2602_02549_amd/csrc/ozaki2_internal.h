@@ -111,7 +111,7 @@ struct ProbDesc {
 typedef int2 BlockRef;
 
 enum GroupPhase {
-  GP_INIT, GP_ABSMAX_A, GP_ABSMAX_B, GP_SLICE_A, GP_SLICE_B, GP_GEMM_SCALE, GP_SHIFTS,
+  GP_INIT, GP_ABSMAX_A, GP_ABSMAX_B, GP_ABSBAR_B, GP_SLICE_A, GP_SLICE_B, GP_GEMM_SCALE, GP_SHIFTS,
   GP_GEMM_RES, GP_CRT, GP_COUNT
 };
 
@@ -149,6 +149,8 @@ void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, i
 // Abs-max of the columns of B and Bbar (slice 0, K-major [n_pad][k_pad]) in
 // one read of B; for k_pad <= kAbsBarMaxK.
 constexpr int kAbsBarMaxK = 8192;
+constexpr int kAbsBarWaveK = 2048;   // up to here one wave per column, else a workgroup
+int absbar_group_blocks(int n_pad, int k_pad);
 void launch_absbar_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n, int n_pad,
                         int k_pad, uint64_t* colbits, int* flag, int8_t* out);
 void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int m,

@@ -109,27 +109,41 @@ __global__ __launch_bounds__(256) void k_absmax_cols(const T* __restrict__ B, in
 }
 
 // B column-major (k x n) with k_pad <= kAbsBarMaxK: the abs-max pass and the
-// Bbar pass of Algorithm 2 in one read of B.  One workgroup per row j of the
-// padded K-major Bbar (n_pad of them): the column is held in registers (two
-// consecutive k per lane, 512 per workgroup pass), its abs-max bit pattern
-// is reduced over the workgroup, and Bbar = ceil(2^nu'_j |b|) (1 for a tiny
-// nonzero b, 0 for b = 0) is written from the same registers, zero beyond k
-// and for the padding rows j >= n.
+// Bbar pass of Algorithm 2 in one read of B.  Each row j of the padded
+// K-major Bbar (n_pad of them) is one column of B, held in registers (two
+// consecutive k per lane, 32 per lane): a whole workgroup per column for
+// k_pad > kAbsBarWaveK, one wave per column (four per workgroup) below.  The
+// column's abs-max bit pattern is reduced over its threads, and
+// Bbar = ceil(2^nu'_j |b|) (1 for a tiny nonzero b, 0 for b = 0) is written
+// from the same registers, zero beyond k and for the padding rows j >= n.
 constexpr int kAbsBarPasses = kAbsBarMaxK / 512;
+static_assert(kAbsBarWaveK == kAbsBarPasses * 128, "a wave covers kAbsBarWaveK in the same passes");
+
+__device__ __forceinline__ bool absbar_per_wave(int k_pad) { return k_pad <= kAbsBarWaveK; }
+
+// Workgroups of absbar_cols_body for n_pad columns.
+__host__ __device__ inline int absbar_blocks(int n_pad, int k_pad) {
+  return k_pad <= kAbsBarWaveK ? (n_pad + 3) / 4 : n_pad;
+}
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_absbar_cols(const T* __restrict__ B, int ldb, int k, int n,
-                                                     int k_pad, uint64_t* __restrict__ colbits,
-                                                     int* __restrict__ flag,
-                                                     int8_t* __restrict__ out) {
-  const int j = blockIdx.x, t = threadIdx.x;
+__device__ __forceinline__ void absbar_cols_body(const T* __restrict__ B, int ldb, int k, int n,
+                                                 int n_pad, int k_pad,
+                                                 uint64_t* __restrict__ colbits,
+                                                 int* __restrict__ flag, int8_t* __restrict__ out,
+                                                 int blk) {
+  const bool per_wave = absbar_per_wave(k_pad);   // uniform over the launch
+  const int tpc = per_wave ? 64 : 256;              // threads per column
+  const int t = per_wave ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  const int j = per_wave ? blk * 4 + (int)(threadIdx.x >> 6) : blk;
+  if (per_wave && j >= n_pad) return;               // whole wave; no barrier below for waves
   double x[2 * kAbsBarPasses];
   uint64_t mx = 0;
   if (j < n) {
     const T* col = B + (size_t)j * ldb;
 #pragma unroll
     for (int q = 0; q < kAbsBarPasses; ++q) {
-      const int h = 2 * t + 512 * q;
+      const int h = 2 * t + 2 * tpc * q;
       x[2 * q] = h < k ? (double)col[h] : 0.0;
       x[2 * q + 1] = h + 1 < k ? (double)col[h + 1] : 0.0;
     }
@@ -146,12 +160,14 @@ __global__ __launch_bounds__(256) void k_absbar_cols(const T* __restrict__ B, in
     const unsigned long long o = __shfl_xor((unsigned long long)mx, off);
     mx = o > mx ? o : mx;
   }
-  __shared__ unsigned long long red[4];
-  if ((t & 63) == 0) red[t >> 6] = mx;
-  __syncthreads();
-  mx = red[0];
+  if (!per_wave) {
+    __shared__ unsigned long long red[4];
+    if ((t & 63) == 0) red[t >> 6] = mx;
+    __syncthreads();
+    mx = red[0];
 #pragma unroll
-  for (int w = 1; w < 4; ++w) mx = red[w] > mx ? red[w] : mx;
+    for (int w = 1; w < 4; ++w) mx = red[w] > mx ? red[w] : mx;
+  }
   if (j < n && t == 0) {
     if ((mx & kExpMask) == kExpMask) atomicOr(flag, 1);
     colbits[j] = mx;
@@ -160,7 +176,7 @@ __global__ __launch_bounds__(256) void k_absbar_cols(const T* __restrict__ B, in
   int8_t* dst = out + (size_t)j * k_pad;
 #pragma unroll
   for (int q = 0; q < kAbsBarPasses; ++q) {
-    const int h = 2 * t + 512 * q;
+    const int h = 2 * t + 2 * tpc * q;
     if (h < k_pad) {
       int b[2];
 #pragma unroll
@@ -172,6 +188,15 @@ __global__ __launch_bounds__(256) void k_absbar_cols(const T* __restrict__ B, in
       *reinterpret_cast<uint16_t*>(dst + h) = (uint16_t)((b[0] & 0xFF) | ((b[1] & 0xFF) << 8));
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_absbar_cols(const T* __restrict__ B, int ldb, int k, int n,
+                                                     int n_pad, int k_pad,
+                                                     uint64_t* __restrict__ colbits,
+                                                     int* __restrict__ flag,
+                                                     int8_t* __restrict__ out) {
+  absbar_cols_body<T>(B, ldb, k, n, n_pad, k_pad, colbits, flag, out, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,6 +351,15 @@ __global__ __launch_bounds__(256) void kg_absmax_cols(const ProbDesc* __restrict
   absmax_cols_body<T>((const T*)d.B, d.ldb, d.k, d.n, d.colbits, d.flag, e.y);
 }
 
+// absbar_blocks(np, kp) workgroups per problem with k_pad <= kAbsBarMaxK.
+template <typename T>
+__global__ __launch_bounds__(256) void kg_absbar_cols(const ProbDesc* __restrict__ P,
+                                                      const BlockRef* __restrict__ map) {
+  const BlockRef e = map[blockIdx.x];
+  const ProbDesc& d = P[e.x];
+  absbar_cols_body<T>((const T*)d.B, d.ldb, d.k, d.n, d.np, d.kp, d.colbits, d.flag, d.Bs, e.y);
+}
+
 __global__ __launch_bounds__(256) void kg_shifts(const ProbDesc* __restrict__ P,
                                                  const BlockRef* __restrict__ map,
                                                  const CrtConsts* __restrict__ ctab) {
@@ -378,15 +412,18 @@ void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, i
                        colbits, flag);
 }
 
+int absbar_group_blocks(int n_pad, int k_pad) { return absbar_blocks(n_pad, k_pad); }
+
 void launch_absbar_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n, int n_pad,
                         int k_pad, uint64_t* colbits, int* flag, int8_t* out) {
   if (n_pad <= 0) return;
+  const dim3 grid((unsigned)absbar_blocks(n_pad, k_pad));
   if (pr == Prec::F64)
-    hipLaunchKernelGGL(k_absbar_cols<double>, dim3((unsigned)n_pad), dim3(256), 0, s,
-                       (const double*)B, ldb, k, n, k_pad, colbits, flag, out);
+    hipLaunchKernelGGL(k_absbar_cols<double>, grid, dim3(256), 0, s, (const double*)B, ldb, k, n,
+                       n_pad, k_pad, colbits, flag, out);
   else
-    hipLaunchKernelGGL(k_absbar_cols<float>, dim3((unsigned)n_pad), dim3(256), 0, s,
-                       (const float*)B, ldb, k, n, k_pad, colbits, flag, out);
+    hipLaunchKernelGGL(k_absbar_cols<float>, grid, dim3(256), 0, s, (const float*)B, ldb, k, n,
+                       n_pad, k_pad, colbits, flag, out);
 }
 
 void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int m,
@@ -419,6 +456,12 @@ void launch_group_scale(hipStream_t s, Prec pr, int phase, const ProbDesc* P, co
         hipLaunchKernelGGL(kg_absmax_cols<double>, g, b, 0, s, P, map);
       else
         hipLaunchKernelGGL(kg_absmax_cols<float>, g, b, 0, s, P, map);
+      break;
+    case GP_ABSBAR_B:
+      if (pr == Prec::F64)
+        hipLaunchKernelGGL(kg_absbar_cols<double>, g, b, 0, s, P, map);
+      else
+        hipLaunchKernelGGL(kg_absbar_cols<float>, g, b, 0, s, P, map);
       break;
     case GP_SHIFTS:
       hipLaunchKernelGGL(kg_shifts, g, b, 0, s, P, map, ctab);
