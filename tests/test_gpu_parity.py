@@ -137,6 +137,13 @@ def test_single_call_256_tiles_ragged(monkeypatch):
     (70, 65, 200, 32, 4.0),
     (70, 65, 200, 40, 4.0),
     (70, 65, 200, 41, 4.0),
+    # the fused column abs-max and Bbar kernel: a wave per column up to
+    # k_pad = 2048, a workgroup per column above (ragged k), two passes
+    # beyond 8192
+    (33, 70, 2048, 7, 0.5),
+    (33, 70, 2049, 7, 0.5),
+    (40, 33, 3001, 14, 1.0),
+    (20, 17, 8300, 9, 1.0),
 ])
 def test_stages_fp64(m, n, k, N, phi):
     run_stage_case(m, n, k, N, phi, seed=m + n + k + N, dtype=np.float64)
@@ -146,6 +153,7 @@ def test_stages_fp64(m, n, k, N, phi):
     (300, 200, 500, 7, 0.5),
     (130, 70, 260, 2, 1.0),
     (64, 257, 100, 16, 0.5),
+    (40, 33, 3001, 7, 1.0),
 ])
 def test_stages_fp32(m, n, k, N, phi):
     run_stage_case(m, n, k, N, phi, seed=m + n + k + N, dtype=np.float32)
