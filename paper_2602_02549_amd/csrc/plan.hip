@@ -89,8 +89,16 @@ __device__ __forceinline__ T block_max(T v) {
   return max(max(red[0], red[1]), max(red[2], red[3]));
 }
 
-// Pass 1: for every entry with S > 0, the smallest N in [nlo, nhi] with
-// T(N) <= eps S (nhi + 1 if none); the maximum over all entries goes to *out.
+// Pass 1: a lower bound of the smallest N in [nlo, nhi] that satisfies
+// T(N) <= eps S on every entry with S > 0 (nhi + 1 if an entry has none); the
+// maximum over the workgroups goes to *out.  Each wave keeps a running bound
+// `need` and, for its next 64 entries, looks for the first N >= need that
+// each entry satisfies.  Any N that satisfies every entry is >= every such
+// first N (by induction over the entries: it is >= each earlier bound, so it
+// is one of the candidates searched), so the maximum stays a lower bound;
+// pass 2 then searches upward from it.  Most entries pass at the running
+// bound in one step.  N advances in step across the wave, so the per-N
+// coefficients are wave-uniform (scalar) loads.
 __global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ S, int lds_,
                                                       int m, int n, int iblocks,
                                                       const double* __restrict__ rs,
@@ -98,18 +106,24 @@ __global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ 
                                                       const double* __restrict__ sr,
                                                       const double* __restrict__ sc, PlanTable pt,
                                                       int* __restrict__ out) {
-  int need = 0;
-  for_entries(m, n, iblocks, [&](int i, int j) {
-    const double Sl = (double)S[(size_t)j * lds_ + i] * pt.acc_scale;
-    bool live = Sl > 0.0;
-    const double A1 = rs[i] * sc[j] + sr[i] * cs[j];
-    const double P2 = sr[i] * sc[j];
-    const double target = pt.eps * Sl;
-    // N advances in step across the wave, so the per-N coefficients are
-    // wave-uniform (scalar) loads; each lane keeps the first N that
-    // satisfies its entry, and the wave stops once every lane has one.
+  int need = 0;   // wave-uniform running bound
+  const int64_t tasks = (int64_t)iblocks * n;
+  for (int64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
+    const int j = (int)(task / iblocks);
+    const int i = (int)(task % iblocks) * 256 + (int)threadIdx.x;
+    bool live = false;
+    double A1 = 0.0, P2 = 0.0, target = 0.0;
+    if (i < m) {
+      const double Sl = (double)S[(size_t)j * lds_ + i] * pt.acc_scale;
+      if (Sl > 0.0) {
+        A1 = rs[i] * sc[j] + sr[i] * cs[j];
+        P2 = sr[i] * sc[j];
+        target = pt.eps * Sl;
+        live = true;
+      }
+    }
     int first = 0;
-    for (int N = pt.nlo; N <= pt.nhi; ++N) {
+    for (int N = max(pt.nlo, need); N <= pt.nhi; ++N) {
       if (!__any(live)) break;
       if (live && plan_ok(pt, N, A1, P2, target)) {
         first = N;
@@ -117,8 +131,9 @@ __global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ 
       }
     }
     if (live) first = pt.nhi + 1;
-    need = max(need, first);
-  });
+    for (int off = 32; off >= 1; off >>= 1) first = max(first, __shfl_xor(first, off));
+    need = __builtin_amdgcn_readfirstlane(max(need, first));
+  }
   need = block_max(need);
   if (threadIdx.x == 0 && need > 0) atomicMax(out, need);
 }
