@@ -171,3 +171,84 @@ def pin_theorem1(A, B, st):
 def all_pins(A, B, st):
     return (pin_scaling(A, B, st) + pin_lemma0_lemma1(A, B, st) + pin_residues(st)
             + pin_accumulation(st) + pin_theorem1(A, B, st))
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2's scalar steps: Dbar = single_up(Cbar) and e = log2f(Dbar)
+# --------------------------------------------------------------------------
+
+
+def single_up_reference(M: np.ndarray) -> np.ndarray:
+    """Round-up of nonnegative integers to FP32 computed with numpy's own
+    conversion: float32(M) rounds to nearest, and one step toward +inf fixes
+    the values it rounded down.  Independent of the oracle's exact-rational
+    rounding helper."""
+    M = np.asarray(M, dtype=np.int64)
+    f = M.astype(np.float32)
+    low = f.astype(np.float64) < M.astype(np.float64)   # exact: M < 2^53
+    f[low] = np.nextafter(f[low], np.float32(np.inf))
+    return f.astype(np.int64)
+
+
+def single_up_cases(seed: int = 0) -> np.ndarray:
+    """Every M in [0, 2^12] and (2^24, 2^24 + 2^12], powers of two and their
+    neighbours up to 2^32, the values one above and one below each FP32 value
+    near 2^25..2^32, and 10^5 random M up to 2^29 plus 10^4 up to 2^32."""
+    rng = np.random.default_rng(seed)
+    parts = [np.arange(0, 2 ** 12 + 1), np.arange(2 ** 24 + 1, 2 ** 24 + 2 ** 12 + 1)]
+    pw = np.array([2 ** e for e in range(33)], dtype=np.int64)
+    parts += [pw, pw - 1, pw + 1]
+    for e in range(25, 33):
+        grid = 2 ** (e - 24)                       # FP32 spacing in [2^(e-1), 2^e)
+        base = rng.integers(2 ** (e - 1) // grid, 2 ** e // grid, 200) * grid
+        parts += [base, base + 1, base - 1]
+    parts += [rng.integers(1, 2 ** 29 + 1, 10 ** 5), rng.integers(1, 2 ** 32, 10 ** 4)]
+    M = np.concatenate(parts).astype(np.int64)
+    return M[(M >= 0) & (M <= 2 ** 32)]
+
+
+def pin_single_up(fn, M: np.ndarray) -> list:
+    """fn (the oracle's single_up_int or a planted variant) against
+    single_up_reference on every M; returns failure strings."""
+    ref = single_up_reference(M)
+    bad = []
+    for x, r in zip(M.tolist(), ref.tolist()):
+        if fn(int(x)) != r:
+            bad.append(f"single_up({x}) = {fn(int(x))}, expected {r}")
+            if len(bad) > 5:
+                break
+    return bad
+
+
+def log2f_near_midpoint_inputs(lo: int, hi: int) -> np.ndarray:
+    """Integer-valued FP32 d in [lo, hi] whose FP64 log2 lies within 2^-40
+    (relative) of an FP32 rounding midpoint: exactly the inputs the oracle's
+    vectorised log2f settles one by one."""
+    out = []
+    for a in range(lo, hi + 1, 1 << 22):
+        d = np.arange(a, min(a + (1 << 22), hi + 1), dtype=np.float64)
+        d = d[d.astype(np.float32).astype(np.float64) == d]          # FP32 values only
+        v = np.log2(d)
+        r = v.astype(np.float32)
+        up = np.nextafter(r, np.float32(np.inf)).astype(np.float64)
+        dn = np.nextafter(r, np.float32(-np.inf)).astype(np.float64)
+        rd = r.astype(np.float64)
+        tol = np.abs(v) * 2.0 ** -40
+        near = (np.abs(v - 0.5 * (rd + up)) <= tol) | (np.abs(v - 0.5 * (rd + dn)) <= tol)
+        out.append(d[near])
+    return np.concatenate(out) if out else np.zeros(0)
+
+
+def pin_log2f_many(fn, d: np.ndarray) -> list:
+    """fn (the oracle's log2f_many or a planted variant) against the
+    decimal-pinned scalar log2f, element by element."""
+    from oracle.ozaki2 import log2f
+    got = fn(np.asarray(d, dtype=np.float32))
+    bad = []
+    for x, g in zip(np.asarray(d).tolist(), got.tolist()):
+        ref = float(log2f(int(x)))
+        if float(np.float32(ref)) != g:
+            bad.append(f"log2f_many({int(x)}) = {g!r}, expected {ref!r}")
+            if len(bad) > 5:
+                break
+    return bad
