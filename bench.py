@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--N", type=int, default=0, help="fix N instead of matching the native error")
     ap.add_argument("--samples", type=int, default=48, help="sampled rows (and columns) for errors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-size", type=int, default=400)
+    ap.add_argument("--cpu-size", type=int, default=256)
+    ap.add_argument("--cpu-N", type=int, default=14)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven 512-problem batched measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -323,22 +324,48 @@ def flushed_timing(torch, dev, emulate, N: int, steps: int) -> dict:
             "steps": steps, "flush": "512 MiB fill before each call"}
 
 
-def cpu_baseline(size: int, N: int) -> dict:
-    """The CPU oracle, as it is, on a bounded sample (size^3, FP64, same
-    generator), single-threaded (BLAS limited to one thread)."""
+def host_cpu() -> dict:
+    """Logical CPUs available to this process and the CPU model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(size: int, N: int, budget_s: float = 10.0) -> dict:
+    """The CPU oracle, as it is, on the small configuration (FP64 size^3, N
+    moduli, phi = 0.5, seed 0: every step of Algorithms 1-3), repeated until
+    about budget_s seconds have passed; one thread (the oracle is sequential
+    Python, and its BLAS calls are held to one thread)."""
     from threadpoolctl import threadpool_limits
 
     from oracle.ozaki2 import os_ii
     from workload import gemm_inputs
 
     A, B = gemm_inputs(size, size, size, phi=0.5, seed=0)
+    times = []
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        os_ii(A, B, N)
-        dt = time.perf_counter() - t0
+        while sum(times) < budget_s:
+            t0 = time.perf_counter()
+            os_ii(A, B, N)
+            times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    cpu = host_cpu()
     return {"value": 2.0 * size ** 3 / dt / 1e12, "unit": "TFLOPS", "cores": 1, "kind": "oracle",
-            "sample": f"full oracle run (Algorithms 1-3) on FP64 {size}^3, N={N}, phi=0.5, seed 0: "
-                      f"{dt:.1f} s; TFLOPS = 2*{size}^3/t"}
+            "host": cpu,
+            "sample": f"full oracle run (Algorithms 1-3) on FP64 {size}^3, N={N}, phi=0.5, seed 0 "
+                      f"(the small configuration), median of {len(times)} runs: {dt:.2f} s each; "
+                      f"TFLOPS = 2*{size}^3/t; one thread of {cpu['nproc']} ({cpu['model']})"}
 
 
 def main():
@@ -493,7 +520,7 @@ def main():
     if args.extras:
         out["extras"] = extras_measurement(torch, oz)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_size, N)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_size, args.cpu_N)
     print(json.dumps(out), flush=True)
 
 

@@ -178,6 +178,7 @@ size_t ozaki2_batched_workspace_bytes(int prec, int count, const int *mnkN);
  * ozaki2_debug_stages - run Algorithms 1-3 like ozaki2_gemm / ozaki2_sgemm
  * and copy the intermediate quantities into caller buffers (device pointers;
  * any may be NULL to skip it).  For parity checks against the CPU oracle.
+ *   nout    : number of entries of out (10..16); entries past it count as NULL.
  *   out[0]  int32 [m]          mu'      (Algorithm 2)
  *   out[1]  int32 [n]          nu'
  *   out[2]  int32 [m]          row maxima of Cbar = Abar*Bbar
@@ -187,12 +188,21 @@ size_t ozaki2_batched_workspace_bytes(int prec, int count, const int *mnkN);
  *   out[6]  int8  [N][m][k]    A'_l  (row-major per modulus: k contiguous)
  *   out[7]  int8  [N][n][k]    B'_l^T (k contiguous per column of B)
  *   out[8]  int8  [N][n][m]    W_l   (column-major per modulus)
- *   out[9]  double/float [n][m] C (column-major, ldc = m)
+ *   out[9]  double/float [n][m] C (column-major, ldc = m); required
  *   out[10] float [m+n]        log2f values e (rows) then f (columns)
- * Returns like ozaki2_gemm.  Synchronises the stream.
+ *   out[11] int32 [N][n][m]    C'_l = A'_l B'_l as INT32 (Algorithm 3), from
+ *                              the residue-product kernel with the tile
+ *                              choice of the call (two's-complement wrap)
+ *   out[12] double [n][m]      C'(1) (Algorithm 3 / Lemma 2)
+ *   out[13] double [n][m]      C'(2) (0 for prec 32)
+ *   out[14] double [n][m]      Q     (Lemma 3)
+ *   out[15] double [n][m]      C''   (Lemma 4; the FP32 value for prec 32)
+ * Allocates temporary device memory for out[11..15].  Returns like
+ * ozaki2_gemm (OZAKI2_ERR_INVALID_ARG also for nout outside 10..16 or a
+ * NULL out[9]).  Synchronises the stream.
  */
 int ozaki2_debug_stages(int prec, int m, int n, int k, const void *A, int lda, const void *B,
-                        int ldb, int N, void *const *out);
+                        int ldb, int N, int nout, void *const *out);
 
 /*
  * ozaki2_debug_log2f - the library's log2f (Algorithm 2; correctly rounded
@@ -212,6 +222,30 @@ int ozaki2_debug_log2f(const float *d, float *out, int count);
 int ozaki2_profile(int enable);
 int ozaki2_profile_read(int *phase, float *ms, int cap);
 const char *ozaki2_profile_name(int phase);
+
+/*
+ * ozaki2_debug_tuning - process-wide tuning and test knobs (normal use needs
+ * none of them).  Sets knob to value and stores the old value in *previous
+ * (HOST pointer, may be NULL).  Affects calls made after it; a batch already
+ * captured keeps the choices it was captured with unless its knobs differ.
+ *   OZAKI2_KNOB_SLICE_WORKGROUPS : cap on the workgroups of each residue /
+ *                                  slice launch (0 = none, the default)
+ *   OZAKI2_KNOB_GEMM_TILE        : product tile of single-problem calls
+ *                                  (0 = automatic, 1 = 256x256, 2 = 128x128)
+ *   OZAKI2_KNOB_BATCH_SPLIT      : batched calls: -1 = autotune (default);
+ *                                  s >= 0: problems with at least s output
+ *                                  tiles of 256x256 per product use them
+ *   OZAKI2_KNOB_BATCH_GRAPH      : 1 = capture a batch into a hipGraph
+ *                                  (default), 0 = enqueue its kernels directly
+ * Returns OZAKI2_OK, or OZAKI2_ERR_INVALID_ARG for an unknown knob or value.
+ */
+enum {
+  OZAKI2_KNOB_SLICE_WORKGROUPS = 0,
+  OZAKI2_KNOB_GEMM_TILE = 1,
+  OZAKI2_KNOB_BATCH_SPLIT = 2,
+  OZAKI2_KNOB_BATCH_GRAPH = 3
+};
+int ozaki2_debug_tuning(int knob, int value, int *previous);
 
 /* Library version string. */
 const char *ozaki2_version(void);

@@ -18,7 +18,8 @@ the N-dependent part
             + (k + r_b(N) - r_b^rnd) t^2 2^alpha'_i 2^beta'_j
 
 relative to S_ij = (|A||B|)_ij: N is the smallest value in [2, 49] with
-max_ij T_ij(N) / S_ij <= eps (entries with S_ij = 0 are exact and skipped).
+max_ij T_ij(N) / S_ij <= eps (entries with (|A||B|)_ij = 0 are exact and
+skipped; one whose FP64 S_ij underflows to 0 admits no N).
 Row and column powers of two are factored out (R18) so nothing overflows.
 
 A-posteriori certification: after a run, Lemma 4 bounds the unknown |A'B'| of
@@ -141,7 +142,8 @@ def certified_ratio(A: np.ndarray, B: np.ndarray, st: dict) -> float:
     return float(best)
 
 
-def certified_moduli(A: np.ndarray, B: np.ndarray, eps: float, N_start: int, rows=None, cols=None):
+def certified_moduli(A: np.ndarray, B: np.ndarray, eps: float, N_start: int, rows=None, cols=None,
+                     table: str = "paper"):
     """Adaptive N (a-posteriori certification): starting at N_start, run
     Algorithm 1 and step N up until certified_ratio <= eps.  Returns
     (N, certified, ratio at N); N = the largest admissible N when the target
@@ -151,7 +153,7 @@ def certified_moduli(A: np.ndarray, B: np.ndarray, eps: float, N_start: int, row
     nmax = N_MAX if b == 64 else 16
     ratio = None
     for N in range(max(N_start, N_MIN), nmax + 1):
-        _, st = os_ii(A, B, N, rows=rows, cols=cols, stages=True)
+        _, st = os_ii(A, B, N, rows=rows, cols=cols, stages=True, table=table)
         ratio = certified_ratio(A, B, st)
         if ratio <= eps:
             return N, True, ratio
@@ -172,14 +174,20 @@ def planner_terms(A: np.ndarray, B: np.ndarray):
     alpha, beta = 5 - mu_p, 5 - nu_p
     As = np.ldexp(A64, -alpha[:, None].astype(np.int32))         # |A| 2^-alpha, in [0, 2)
     Bs = np.ldexp(B64, -beta[None, :].astype(np.int32))
+    # (|A||B|)_ij > 0 exactly when some h has a_ih != 0 and b_hj != 0; the
+    # FP64 S below can underflow to 0 for such an entry (a row spanning
+    # many binades), and then no N can be certified for it.
+    nz = exact_int_matmul((A64 != 0).astype(np.int64), (B64 != 0).astype(np.int64),
+                          float(max(k, 1))) > 0
     return dict(k=k, rs=As.sum(axis=1), cs=Bs.sum(axis=0),
                 sr=np.sqrt(rmax.astype(np.float64)), sc=np.sqrt(cmax.astype(np.float64)),
-                S=As @ Bs)
+                S=As @ Bs, nz=nz)
 
 
-def ratio_max(terms: dict, N: int, b: int) -> tuple:
-    """(max_ij T_ij(N)/S_ij, max_ij est2_ij/S_ij) over entries with S_ij > 0."""
-    const = constants(N, b)
+def ratio_max(terms: dict, N: int, b: int, table: str = "paper") -> tuple:
+    """(max_ij T_ij(N)/S_ij, max_ij est2_ij/S_ij) over the entries with
+    (|A||B|)_ij > 0; inf when such an entry has an FP64 S_ij of 0."""
+    const = constants(N, b, table)
     t = float(1 / mpmath.sqrt(32 * (mpmath.mpf(const.P) - 1)))
     tt_coef = float(Fraction(1, 32 * (const.P - 1)))             # t^2
     extra = float(R_const(const) / (32 * (const.P - 1)))         # (r_b - r_rnd) t^2
@@ -188,7 +196,9 @@ def ratio_max(terms: dict, N: int, b: int) -> tuple:
     base = t * (terms["rs"][:, None] * sc[None, :] + sr[:, None] * terms["cs"][None, :])
     prod = sr[:, None] * sc[None, :]
     T = base + (terms["k"] * tt_coef + extra) * prod
-    mask = (S > 0) & (prod > 0)
+    if np.any(terms["nz"] & ~((S > 0) & (prod > 0))):
+        return float("inf"), float("inf")
+    mask = terms["nz"]
     if not mask.any():
         return 0.0, 0.0
     r1 = float(np.max(T[mask] / S[mask]))
@@ -196,19 +206,19 @@ def ratio_max(terms: dict, N: int, b: int) -> tuple:
     return r1, r2
 
 
-def required_moduli_from_terms(terms: dict, eps: float, b: int = 64):
+def required_moduli_from_terms(terms: dict, eps: float, b: int = 64, table: str = "paper"):
     """Smallest N in [2, 49] (FP32: [2, 16]) whose N-dependent bound is <= eps
     relative to |A||B| on every entry (R16).  Returns (N, reachable, detail)."""
     nmax = N_MAX if b == 64 else 16
     r1 = r2 = None
     for N in range(N_MIN, nmax + 1):
-        r1, r2 = ratio_max(terms, N, b)
+        r1, r2 = ratio_max(terms, N, b, table)
         if r1 <= eps:
             return N, True, dict(ratio=r1, est2_ratio=r2)
     return nmax, False, dict(ratio=r1, est2_ratio=r2)
 
 
-def required_moduli(A: np.ndarray, B: np.ndarray, eps: float):
-    """required_moduli_from_terms(planner_terms(A, B), eps, b)."""
+def required_moduli(A: np.ndarray, B: np.ndarray, eps: float, table: str = "paper"):
+    """required_moduli_from_terms(planner_terms(A, B), eps, b, table)."""
     b = 64 if A.dtype == np.float64 else 32
-    return required_moduli_from_terms(planner_terms(A, B), eps, b)
+    return required_moduli_from_terms(planner_terms(A, B), eps, b, table)

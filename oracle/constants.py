@@ -9,7 +9,8 @@ that the working precision cannot change the rounding.
 
 Readings (where the paper is silent or garbled):
   * the N moduli are the first N entries of the fixed 49-entry list of
-    Section 3.1 (eq. p_list);
+    Section 3.1 (eq. p_list), or, with table="optimal", the per-N set of
+    largest product that Section 3.1 says can be tabulated (oracle/moduli.py);
   * s_l1 keeps the upper beta_l bits of (P/p_l)*q_l by TRUNCATION, i.e. it is
     floor(x_l / g) * g with g = 2^(floor(log2 r) + 1 + ceil(log2 rho) - 53),
     r = max_l x_l; the proof of Lemma 2 places s_l1 on this grid and uses
@@ -88,13 +89,28 @@ def pprime(P: int) -> Fraction:
     return r
 
 
+TABLES = ("paper", "optimal")
+
+
+def moduli_for(N: int, table: str = "paper") -> tuple:
+    """The N moduli: the first N of the fixed list of Section 3.1 ("paper"),
+    or the N pairwise coprime moduli <= 256 of largest product ("optimal",
+    the per-N tables Section 3.1 says can be built)."""
+    if table == "paper":
+        return MODULI[:N]
+    if table == "optimal":
+        from .moduli import optimal_moduli
+        return optimal_moduli(N)
+    raise ValueError(f"unknown moduli table {table!r}")
+
+
 @lru_cache(maxsize=None)
-def constants(N: int, b: int = 64) -> Constants:
+def constants(N: int, b: int = 64, table: str = "paper") -> Constants:
     if not (N_MIN <= N <= N_MAX):
         raise ValueError(f"N must be in [{N_MIN}, {N_MAX}], got {N}")
     if b not in (32, 64):
         raise ValueError("b must be 32 or 64")
-    p = MODULI[:N]
+    p = moduli_for(N, table)
     P = math.prod(p)
     q = tuple(pow(P // pl, -1, pl) for pl in p)
     x = tuple((P // pl) * ql for pl, ql in zip(p, q))

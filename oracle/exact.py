@@ -2,7 +2,9 @@
 
 AB is formed with exact integer arithmetic: every FP64 entry is m * 2^e with
 an integer m, so after scaling each matrix by a power of two every entry is an
-integer and the product is an exact big-integer dot product.
+integer and the product is an exact big-integer dot product.  The integer
+scaling is the measurement helper of workload/reference.py (it holds no step
+of the method), shared with the benchmark's error samples.
 """
 from __future__ import annotations
 
@@ -10,19 +12,7 @@ from fractions import Fraction
 
 import numpy as np
 
-
-def _int_scaled(X: np.ndarray):
-    """Return (object array of ints I, exponent E) with X == I * 2^E exactly."""
-    X = X.astype(np.float64)
-    f, e = np.frexp(X)                       # X = f 2^e, |f| in [0.5, 1)
-    mant = np.ldexp(f, 53).astype(np.int64)  # exact 53-bit integer significands
-    e = e.astype(np.int64) - 53
-    nz = mant != 0
-    E = int(e[nz].min()) if nz.any() else 0
-    out = np.empty(X.shape, dtype=object)
-    for idx in np.ndindex(X.shape):
-        out[idx] = int(mant[idx]) << int(e[idx] - E) if mant[idx] != 0 else 0
-    return out, E
+from workload.reference import int_scaled as _int_scaled
 
 
 def exact_product(A: np.ndarray, B: np.ndarray, rows=None, cols=None):

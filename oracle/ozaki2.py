@@ -160,12 +160,14 @@ def to_int_objects(V: np.ndarray) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 
-def scaling(A: np.ndarray, B: np.ndarray, N: int, rows=None, cols=None) -> dict:
+def scaling(A: np.ndarray, B: np.ndarray, N: int, rows=None, cols=None,
+            table: str = "paper") -> dict:
     """Algorithm 2.  With `rows`/`cols` given, mu and A' are produced only for
     those rows of A and nu and B' only for those columns of B (the row and
-    column maxima of Cbar they need are still taken over the full matrices)."""
+    column maxima of Cbar they need are still taken over the full matrices).
+    `table` selects the moduli (oracle.constants.moduli_for)."""
     b = _check_inputs(A, B)
-    const = constants(N, b)
+    const = constants(N, b, table)
     m, k = A.shape
     n = B.shape[1]
     rows = np.arange(m) if rows is None else np.asarray(rows)
@@ -281,8 +283,11 @@ def unscale(Cpp: np.ndarray, mu: np.ndarray, nu: np.ndarray, b: int) -> np.ndarr
 # --------------------------------------------------------------------------
 
 
-def os_ii(A: np.ndarray, B: np.ndarray, N: int, rows=None, cols=None, stages: bool = False):
-    """C := OS_II(A, B, p) with p the first N moduli (Algorithm 1).
+def os_ii(A: np.ndarray, B: np.ndarray, N: int, rows=None, cols=None, stages: bool = False,
+          table: str = "paper"):
+    """C := OS_II(A, B, p) with p the first N moduli of the list of Section 3.1
+    (table="paper") or the per-N moduli of largest product (table="optimal")
+    (Algorithm 1).
 
     Returns C (shape len(rows) x len(cols), FP64 or FP32); with stages=True
     returns (C, dict of every intermediate quantity).
@@ -298,7 +303,7 @@ def os_ii(A: np.ndarray, B: np.ndarray, N: int, rows=None, cols=None, stages: bo
     if nr == 0 or nc == 0 or k == 0:
         C = np.zeros((nr, nc), dtype=dt)              # BLAS convention: C = 0
         return (C, {}) if stages else C
-    st = scaling(A, B, N, rows, cols)
+    st = scaling(A, B, N, rows, cols, table)
     st.update(residue_products(st["Ap"], st["Bp"], st["const"]))
     st.update(crt_reconstruct(st["W"], st["const"]))
     C = unscale(st["Cpp"], st["mu"], st["nu"], b)

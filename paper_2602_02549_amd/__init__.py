@@ -49,13 +49,16 @@ _SIGS = {
                              ctypes.POINTER(_c_ptr), ctypes.POINTER(_c_int)], _c_int),
     "ozaki2_batched_workspace_bytes": ([_c_int, _c_int, ctypes.POINTER(_c_int)], ctypes.c_size_t),
     "ozaki2_debug_stages": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int,
-                             ctypes.POINTER(_c_ptr)], _c_int),
+                             _c_int, ctypes.POINTER(_c_ptr)], _c_int),
     "ozaki2_debug_log2f": ([_c_ptr, _c_ptr, _c_int], _c_int),
     "ozaki2_profile": ([_c_int], _c_int),
     "ozaki2_profile_read": ([ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_float), _c_int], _c_int),
     "ozaki2_profile_name": ([_c_int], ctypes.c_char_p),
+    "ozaki2_debug_tuning": ([_c_int, _c_int, ctypes.POINTER(_c_int)], _c_int),
     "ozaki2_version": ([], ctypes.c_char_p),
 }
+
+KNOB_SLICE_WORKGROUPS, KNOB_GEMM_TILE, KNOB_BATCH_SPLIT, KNOB_BATCH_GRAPH = 0, 1, 2, 3
 
 
 class Ozaki2Error(RuntimeError):
@@ -140,8 +143,8 @@ def ozaki2_batched_workspace_bytes(prec, mnkN):
 
 
 def ozaki2_debug_stages(prec, m, n, k, A, lda, B, ldb, N, outs):
-    arr = (_c_ptr * 11)(*[o or None for o in outs])
-    return _call("ozaki2_debug_stages", prec, m, n, k, A, lda, B, ldb, N, arr)
+    arr = (_c_ptr * len(outs))(*[o or None for o in outs])
+    return _call("ozaki2_debug_stages", prec, m, n, k, A, lda, B, ldb, N, len(outs), arr)
 
 
 def ozaki2_debug_log2f(d, out, count):
@@ -160,6 +163,30 @@ def ozaki2_profile_read(cap=4096):
         raise Ozaki2Error("ozaki2_profile_read", n)
     names = [lib().ozaki2_profile_name(ph[i]).decode() for i in range(n)]
     return list(zip(names, [ms[i] for i in range(n)]))
+
+
+def ozaki2_debug_tuning(knob, value):
+    """(rc, previous value)."""
+    prev = _c_int(0)
+    rc = _call("ozaki2_debug_tuning", knob, value, ctypes.byref(prev))
+    return rc, prev.value
+
+
+class tuning:
+    """Context manager: set a knob of ozaki2_debug_tuning, restore it on exit."""
+
+    def __init__(self, knob, value):
+        self.knob, self.value, self.prev = knob, value, None
+
+    def __enter__(self):
+        rc, self.prev = ozaki2_debug_tuning(self.knob, self.value)
+        if rc != OK:
+            raise Ozaki2Error("ozaki2_debug_tuning", rc)
+        return self
+
+    def __exit__(self, *exc):
+        ozaki2_debug_tuning(self.knob, self.prev)
+        return False
 
 
 def ozaki2_version():
@@ -226,13 +253,15 @@ def gemm_certified(A, B, eps: float, N_start: int = 0):
     return Ccm.t(), rc, N, ratio
 
 
-def debug_stages(A, B, N: int):
-    """Every intermediate of Algorithms 1-3 as torch tensors (see the header)."""
+def debug_stages(A, B, N: int, crt_stages: bool = True):
+    """Every intermediate of Algorithms 1-3 as torch tensors (see the header);
+    with crt_stages, also the INT32 products C'_l and C'(1), C'(2), Q, C''."""
     torch = _torch()
     m, k = A.shape
     n = B.shape[1]
     dev = A.device
     i32 = dict(dtype=torch.int32, device=dev)
+    f64 = dict(dtype=torch.float64, device=dev)
     out = dict(mu_p=torch.empty(m, **i32), nu_p=torch.empty(n, **i32), rmax=torch.empty(m, **i32),
                cmax=torch.empty(n, **i32), mu=torch.empty(m, **i32), nu=torch.empty(n, **i32),
                Al=torch.empty((N, m, k), dtype=torch.int8, device=dev),
@@ -241,6 +270,11 @@ def debug_stages(A, B, N: int):
                CT=torch.empty((n, m), dtype=A.dtype, device=dev),
                ef=torch.empty(m + n, dtype=torch.float32, device=dev))
     order = ["mu_p", "nu_p", "rmax", "cmax", "mu", "nu", "Al", "BlT", "WT", "CT", "ef"]
+    if crt_stages:
+        out.update(ClT=torch.empty((N, n, m), **i32), C1T=torch.empty((n, m), **f64),
+                   C2T=torch.empty((n, m), **f64), QT=torch.empty((n, m), **f64),
+                   CppT=torch.empty((n, m), **f64))
+        order += ["ClT", "C1T", "C2T", "QT", "CppT"]
     Acm, Bcm = col_major(A), col_major(B)
     _set_current_stream()
     prec = 64 if A.dtype == torch.float64 else 32

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -22,6 +23,8 @@ using namespace oz2;
 namespace {
 
 thread_local hipStream_t g_stream = nullptr;
+
+constexpr int kDebugOutputs = 16;   // entries of ozaki2_debug_stages' output list
 
 struct BatchEntry;
 
@@ -212,7 +215,7 @@ int get_workspace(size_t bytes, char** base, int** status, uint64_t* gen = nullp
 struct PlanLayout {
   int mp, np, kp;
   size_t rowbits, colbits, rmax, cmax, flag, res, Abar, Bbar, Abf, Bbf, pr, pc, rs, cs, sr, sc, S,
-      total;
+      mask, total;
 };
 
 PlanLayout plan_layout(int m, int n, int k) {
@@ -244,6 +247,7 @@ PlanLayout plan_layout(int m, int n, int k) {
   L.sr = take(8ull * L.mp);
   L.sc = take(8ull * L.np);
   L.S = take(4ull * L.mp * L.np);
+  L.mask = take((size_t)L.mp * L.np);
   L.total = off;
   return L;
 }
@@ -404,6 +408,37 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
     (void)hipMemcpyAsync((char*)dbg[10] + 4ull * m, ws + L.ef + 4ull * m, 4ull * n,
                          hipMemcpyDeviceToDevice, s);
   }
+  // The INT32 residue products C'_l: the residue-product kernel with the
+  // same tile choice, its accumulators stored instead of reduced mod p_l.
+  if (dbg[11]) {
+    int* D = nullptr;
+    const size_t per = (size_t)L.np * L.mp;
+    if (hipMalloc(&D, 4 * per * N) != hipSuccess) return OZAKI2_ERR_HIP;
+    launch_gemm_i8(s, 4, at<int8_t>(ws, L.A), (size_t)L.mp * L.kp, at<int8_t>(ws, L.B),
+                   (size_t)L.np * L.kp, L.mp, L.np, L.kp, N, cc, (int8_t*)D, per, L.mp, nullptr,
+                   nullptr);
+    for (int l = 0; l < N; ++l)
+      (void)hipMemcpy2DAsync((char*)dbg[11] + 4ull * l * n * m, 4ull * m, D + l * per, 4ull * L.mp,
+                             4ull * m, n, hipMemcpyDeviceToDevice, s);
+    const bool ok = hipStreamSynchronize(s) == hipSuccess;
+    (void)hipFree(D);
+    if (!ok) return OZAKI2_ERR_HIP;
+  }
+  // C'(1), C'(2), Q and C'' from the CRT kernel's debug variant (it rewrites
+  // the same C).
+  if (dbg[12] || dbg[13] || dbg[14] || dbg[15]) {
+    double* D = nullptr;
+    const size_t mn = (size_t)m * n;
+    if (hipMalloc(&D, 4 * 8 * mn) != hipSuccess) return OZAKI2_ERR_HIP;
+    launch_crt_debug(s, pr, at<int8_t>(ws, L.W), (size_t)L.np * L.mp, L.mp, at<int>(ws, L.mu),
+                     at<int>(ws, L.nu), m, n, cc, at<int>(ws, L.flag), C, ldc, D);
+    for (int q = 0; q < 4; ++q)
+      if (dbg[12 + q])
+        (void)hipMemcpyAsync(dbg[12 + q], D + q * mn, 8 * mn, hipMemcpyDeviceToDevice, s);
+    const bool ok = hipStreamSynchronize(s) == hipSuccess;
+    (void)hipFree(D);
+    if (!ok) return OZAKI2_ERR_HIP;
+  }
   return hipStreamSynchronize(s) == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
 }
 
@@ -450,10 +485,10 @@ struct BatchEntry {
   }
 };
 
-int env_int(const char* name, int dflt) {
-  const char* e = getenv(name);
-  return e ? atoi(e) : dflt;
-}
+// Batch knobs (ozaki2_debug_tuning): a forced tile split (-1: autotune) and
+// whether a batch's launch sequence is captured into a hipGraph.
+std::atomic<int> g_batch_split{-1};
+std::atomic<int> g_batch_graph{1};
 
 // Device table of CrtConsts indexed by N (entries below 2 unused).
 int get_ctab(int b, CrtConsts** out) {
@@ -661,8 +696,8 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return OZAKI2_ERR_HIP;
 
-  const int forced = env_int("OZAKI2_BATCH_SPLIT", -1);
-  const bool use_graph = env_int("OZAKI2_BATCH_GRAPH", 1) != 0;
+  const int forced = g_batch_split.load(std::memory_order_relaxed);
+  const bool use_graph = g_batch_graph.load(std::memory_order_relaxed) != 0;
   std::vector<int64_t> key;
   key.reserve(4 + 10 * (size_t)count);
   key.push_back(b);
@@ -880,8 +915,12 @@ void plan_terms(Prec pr, int m, int n, int k, const void* A, int lda, const void
     launch_slices(s, pr, 0, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc,
                   at<int8_t>(ws, L.Bbar));
   }
-  launch_gemm_i8(s, 1, at<int8_t>(ws, L.Abar), 0, at<int8_t>(ws, L.Bbar), 0, L.mp, L.np, L.kp, 1,
-                 cc, nullptr, 0, 0, rmax, cmax);
+  // and one byte per entry, Cbar_ij != 0, which holds exactly when
+  // (|A||B|)_ij > 0 (Abar, Bbar are >= 1 wherever A, B are nonzero): an
+  // entry whose lower bound of S below underflows to 0 is then known to be
+  // nonzero, and no N is accepted for it
+  launch_gemm_i8(s, 3, at<int8_t>(ws, L.Abar), 0, at<int8_t>(ws, L.Bbar), 0, L.mp, L.np, L.kp, 1,
+                 cc, at<int8_t>(ws, L.mask), 0, L.mp, rmax, cmax);
   // scaled |A|, |B| as BF16 lower bounds, with upward row / column sums
   launch_plan_slices(s, pr, true, A, lda, m, k, L.mp, L.kp, rowbits, at<uint16_t>(ws, L.Abf),
                      at<double>(ws, L.pr));
@@ -919,14 +958,15 @@ int plan_search(const PlanLayout& L, char* ws, int m, int n, int k, double eps, 
     pt.extra[N] = pc.extra[N];
   }
   const float* S = at<float>(ws, L.S);
+  const uint8_t* mask = at<uint8_t>(ws, L.mask);
   const double *rs = at<double>(ws, L.rs), *cs = at<double>(ws, L.cs);
   const double *sr = at<double>(ws, L.sr), *scv = at<double>(ws, L.sc);
   if (hipMemsetAsync(res, 0, 2 * sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
-  launch_plan_entries(s, S, L.mp, m, n, rs, cs, sr, scv, pt, res);
+  launch_plan_entries(s, S, mask, L.mp, m, n, rs, cs, sr, scv, pt, res);
   // The largest per-entry minimum is checked on every entry in the same
   // round trip (the bound is not monotone in N once the N-dependent
   // accumulation term dominates, so it may fail somewhere).
-  launch_plan_verify(s, S, L.mp, m, n, rs, cs, sr, scv, pt, 0, res, res + 1);
+  launch_plan_verify(s, S, mask, L.mp, m, n, rs, cs, sr, scv, pt, 0, res, res + 1);
   int host[2] = {0, 0};
   int hflag = 0;
   if (hipMemcpyAsync(host, res, 2 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -942,7 +982,7 @@ int plan_search(const PlanLayout& L, char* ws, int m, int n, int k, double eps, 
     // N failed on some entry: the smallest larger N that satisfies all.
     for (++N; N <= nhi; ++N) {
       if (hipMemsetAsync(res + 1, 0, sizeof(int), s) != hipSuccess) return OZAKI2_ERR_HIP;
-      launch_plan_verify(s, S, L.mp, m, n, rs, cs, sr, scv, pt, N, nullptr, res + 1);
+      launch_plan_verify(s, S, mask, L.mp, m, n, rs, cs, sr, scv, pt, N, nullptr, res + 1);
       int bad = 0;
       if (hipMemcpyAsync(&bad, res + 1, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)
@@ -1070,7 +1110,7 @@ int ozaki2_gemm_certified(int prec, int m, int n, int k, const void* A, int lda,
     unsigned long long* word = at<unsigned long long>(ws, Lp.res);
     if (hipMemsetAsync(word, 0, sizeof(*word), s) != hipSuccess) return OZAKI2_ERR_HIP;
     launch_certify(s, pr, C, ldc, at<int>(wg, Lg.mu), at<int>(wg, Lg.nu), at<float>(ws, Lp.S),
-                   Lp.mp, m, n, at<double>(ws, Lp.rs), at<double>(ws, Lp.cs),
+                   at<uint8_t>(ws, Lp.mask), Lp.mp, m, n, at<double>(ws, Lp.rs), at<double>(ws, Lp.cs),
                    at<double>(ws, Lp.sr), at<double>(ws, Lp.sc), ct, word);
     unsigned long long bits = 0;
     int hflag = 0;
@@ -1091,11 +1131,13 @@ int ozaki2_gemm_certified(int prec, int m, int n, int k, const void* A, int lda,
 }
 
 int ozaki2_debug_stages(int prec, int m, int n, int k, const void* A, int lda, const void* B,
-                        int ldb, int N, void* const* out) {
+                        int ldb, int N, int nout, void* const* out) {
   if (prec != 64 && prec != 32) return OZAKI2_ERR_INVALID_ARG;
-  if (!out || !out[9]) return OZAKI2_ERR_INVALID_ARG;
+  if (!out || nout < 10 || nout > kDebugOutputs || !out[9]) return OZAKI2_ERR_INVALID_ARG;
+  void* all[kDebugOutputs] = {};
+  for (int q = 0; q < nout; ++q) all[q] = out[q];
   return gemm_impl(prec == 64 ? Prec::F64 : Prec::F32, m, n, k, A, lda, B, ldb, out[9],
-                   m > 1 ? m : 1, N, out);
+                   m > 1 ? m : 1, N, all);
 }
 
 int ozaki2_debug_log2f(const float* d, float* out, int count) {
@@ -1133,6 +1175,33 @@ const char* ozaki2_profile_name(int phase) {
   return (phase >= 0 && phase < PH_COUNT) ? kPhaseNames[phase] : "";
 }
 
-const char* ozaki2_version(void) { return "ozaki2-gfx950 0.1"; }
+int ozaki2_debug_tuning(int knob, int value, int* previous) {
+  std::atomic<int>* k = nullptr;
+  switch (knob) {
+    case OZAKI2_KNOB_SLICE_WORKGROUPS:
+      if (value < 0) return OZAKI2_ERR_INVALID_ARG;
+      k = &g_slice_cap;
+      break;
+    case OZAKI2_KNOB_GEMM_TILE:
+      if (value < 0 || value > 2) return OZAKI2_ERR_INVALID_ARG;
+      k = &g_gemm_tile;
+      break;
+    case OZAKI2_KNOB_BATCH_SPLIT:
+      if (value < -1) return OZAKI2_ERR_INVALID_ARG;
+      k = &g_batch_split;
+      break;
+    case OZAKI2_KNOB_BATCH_GRAPH:
+      if (value != 0 && value != 1) return OZAKI2_ERR_INVALID_ARG;
+      k = &g_batch_graph;
+      break;
+    default:
+      return OZAKI2_ERR_INVALID_ARG;
+  }
+  const int old = k->exchange(value);
+  if (previous) *previous = old;
+  return OZAKI2_OK;
+}
+
+const char* ozaki2_version(void) { return "ozaki2-gfx950 0.2"; }
 
 }  // extern "C"

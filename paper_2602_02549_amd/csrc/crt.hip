@@ -23,11 +23,14 @@ namespace {
 // Thread g (g = 0 .. ceil(m/R) n - 1) takes row chunk g % ceil(m/R) of column
 // g / ceil(m/R): consecutive threads walk down a column and continue in the
 // next, so small-m problems keep every lane busy.
-template <typename T, int R>
+// With DBG, C'(1), C'(2), Q and C'' of every entry are also stored, as FP64
+// column-major m x n arrays at dbg + s * m * n for s = 0..3 (stage dumps).
+template <typename T, int R, bool DBG = false>
 __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw, int ldw,
                                 const int* __restrict__ mu, const int* __restrict__ nu, int m,
                                 int n, const CrtConsts& cc, const int* __restrict__ flag,
-                                T* __restrict__ C, int ldc, int64_t g) {
+                                T* __restrict__ C, int ldc, int64_t g,
+                                double* __restrict__ dbg = nullptr) {
   static_assert(R == 2 || R == 4 || R == 8, "rows per thread");
   typedef typename std::conditional<R == 2, uint16_t,
                                     typename std::conditional<R == 4, uint32_t, uint64_t>::type>::type
@@ -75,12 +78,24 @@ __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw
     const double q = rint(c1[e] * cc.Pinv);
     const double t = fma(-q, cc.P1, c1[e]);
     const int ex = -mu[i] - nuj;
+    double cppd;
     if (sizeof(T) == 8) {
       const double cpp = fma(-q, cc.P2, t + c2[e]);
       out[e] = bad ? (T)NAN : (T)ldexp(cpp, ex);
+      cppd = cpp;
     } else {
       const float cpp = (float)t;
       out[e] = bad ? (T)NAN : (T)ldexp((double)cpp, ex);
+      cppd = (double)cpp;
+    }
+    if constexpr (DBG) {
+      if (i0 + e < m) {
+        const size_t mn = (size_t)m * n, o = (size_t)j * m + i0 + e;
+        dbg[o] = c1[e];
+        dbg[mn + o] = c2[e];
+        dbg[2 * mn + o] = q;
+        dbg[3 * mn + o] = cppd;
+      }
     }
   }
   T* cp = C + (size_t)j * ldc + i0;
@@ -113,6 +128,17 @@ __global__ __launch_bounds__(256) void k_crt(const int8_t* __restrict__ W, size_
                                              const int* __restrict__ flag, T* __restrict__ C, int ldc) {
   crt_body<T, R>(W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc,
                  (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_crt_debug(const int8_t* __restrict__ W, size_t sw, int ldw,
+                                                   const int* __restrict__ mu,
+                                                   const int* __restrict__ nu, int m, int n,
+                                                   CrtConsts cc, const int* __restrict__ flag,
+                                                   T* __restrict__ C, int ldc,
+                                                   double* __restrict__ dbg) {
+  crt_body<T, kCrtRows, true>(W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc,
+                              (int64_t)blockIdx.x * 256 + threadIdx.x, dbg);
 }
 
 template <typename T>
@@ -180,6 +206,18 @@ void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, con
     launch_crt_t<double>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
   else
     launch_crt_t<float>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
+}
+
+void launch_crt_debug(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,
+                      const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
+                      int ldc, double* dbg) {
+  const dim3 grid((unsigned)crt_blocks(m, n)), block(256);
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL(k_crt_debug<double>, grid, block, 0, s, W, sw, ldw, mu, nu, m, n, cc, flag,
+                       (double*)C, ldc, dbg);
+  else
+    hipLaunchKernelGGL(k_crt_debug<float>, grid, block, 0, s, W, sw, ldw, mu, nu, m, n, cc, flag,
+                       (float*)C, ldc, dbg);
 }
 
 void launch_fill_zero(hipStream_t s, Prec pr, void* C, int ldc, int m, int n) {

@@ -2,7 +2,10 @@
 //   epi 0: the N residue products C'_l = A'_l B'_l of Algorithm 3 with the
 //          reduction W_l = mod(C'_l, p_l) fused into the epilogue;
 //   epi 1: the scaling product Cbar = Abar Bbar of Algorithm 2, of which only
-//          the row and column maxima are kept (atomicMax, order-free).
+//          the row and column maxima are kept (atomicMax, order-free);
+//   epi 3: epi 1 plus one byte per entry, Cbar_ij != 0 (the planner's
+//          indicator of (|A||B|)_ij > 0);
+//   epi 4: the raw INT32 accumulators C'_l (stage dumps only).
 //
 // Operands are K-major INT8 slices (k contiguous), zero padded, so the kernel
 // needs no bounds checks:  D[x][y] = sum_h X[x][h] Y[y][h], with X the A side
@@ -28,8 +31,8 @@
 //
 // Accumulator layout of the 32x32x32 MFMA (lane l, register r):
 //   row (X side) = 8*(r/4) + 4*(l/32) + r%4,   column (Y side) = l%32.
+#include <atomic>
 #include <cstdint>
-#include <cstdlib>
 #include <type_traits>
 
 #include "ozaki2_internal.h"
@@ -208,8 +211,43 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   };
 
   const int xb = x0 + wx * WX, yb = y0 + wy * WY;
-  // Epilogue (EPI 0: mod p_z into W_z; EPI 1: maxima; EPI 2: store).
+  // Per 32 x 32 block, lane l holds rows {0-3, 8-11, 16-19, 24-27} + 4 (l/32)
+  // of column l%32, packed as 4 dwords R0..R3 (one byte per row).  Swapping
+  // R0<->R2 and R1<->R3 between lanes l and l+32 (v_permlane32_swap) leaves
+  // rows 0-15 in lane l and rows 16-31 in lane l+32, each stored as one
+  // 16-byte write into the column-major byte matrix Wz (row length ldw).
+  auto store_block = [&](int8_t* Wz, int tx, int ty, uint32_t R0, uint32_t R1, uint32_t R2,
+                         uint32_t R3) {
+    const auto s02 = __builtin_amdgcn_permlane32_swap(R0, R2, false, false);
+    const auto s13 = __builtin_amdgcn_permlane32_swap(R1, R3, false, false);
+    const int x = xb + tx * 32 + 16 * (lane >> 5);
+    const int y = yb + ty * 32 + (lane & 31);
+    uint4 v;
+    v.x = s02[0];
+    v.y = s02[1];
+    v.z = s13[0];
+    v.w = s13[1];
+    *reinterpret_cast<uint4*>(Wz + (size_t)y * ldw + x) = v;
+  };
+  // Epilogue (EPI 0: mod p_z into W_z; EPI 1: maxima; EPI 2: FP32 store;
+  // EPI 3: maxima and nonzero bytes; EPI 4: INT32 store).
   auto finish = [&]() {
+    if constexpr (EPI == 4) {
+      // INT32 accumulators of slice z stored column-major: D_z[y][x]
+      int* Dz = reinterpret_cast<int*>(W) + (size_t)z * sw;
+#pragma unroll
+      for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+        for (int ty = 0; ty < TY; ++ty)
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const int x = xb + tx * 32 + 8 * r4 + 4 * (lane >> 5);
+            const int y = yb + ty * 32 + (lane & 31);
+            *reinterpret_cast<int4*>(Dz + (size_t)y * ldw + x) =
+                make_int4(acc[tx][ty][4 * r4 + 0], acc[tx][ty][4 * r4 + 1],
+                          acc[tx][ty][4 * r4 + 2], acc[tx][ty][4 * r4 + 3]);
+          }
+    }
     if constexpr (EPI == 2) {
       // FP32 accumulators stored column-major: S[y][x], 4 consecutive x per lane
       float* S = reinterpret_cast<float*>(W);
@@ -228,22 +266,6 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
     } else if constexpr (EPI == 0) {
       const int p = cc.p[z];
       int8_t* Wz = W + (size_t)z * sw;
-      // Per 32 x 32 block, lane l holds rows {0-3, 8-11, 16-19, 24-27} + 4 (l/32)
-      // of column l%32, packed as 4 dwords R0..R3.  Swapping R0<->R2 and R1<->R3
-      // between lanes l and l+32 (v_permlane32_swap) leaves rows 0-15 in lane l
-      // and rows 16-31 in lane l+32, each stored as one 16-byte write.
-      auto store_block = [&](int tx, int ty, uint32_t R0, uint32_t R1, uint32_t R2, uint32_t R3) {
-        const auto s02 = __builtin_amdgcn_permlane32_swap(R0, R2, false, false);
-        const auto s13 = __builtin_amdgcn_permlane32_swap(R1, R3, false, false);
-        const int x = xb + tx * 32 + 16 * (lane >> 5);
-        const int y = yb + ty * 32 + (lane & 31);
-        uint4 v;
-        v.x = s02[0];
-        v.y = s02[1];
-        v.z = s13[0];
-        v.w = s13[1];
-        *reinterpret_cast<uint4*>(Wz + (size_t)y * ldw + x) = v;
-      };
       // The modulus is uniform: one branch for the whole tile.
       if (p == 256) {
 #pragma unroll
@@ -255,7 +277,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
             for (int r4 = 0; r4 < 4; ++r4)
               R[r4] = pack_bytes(acc[tx][ty][4 * r4 + 0], acc[tx][ty][4 * r4 + 1],
                                  acc[tx][ty][4 * r4 + 2], acc[tx][ty][4 * r4 + 3]);
-            store_block(tx, ty, R[0], R[1], R[2], R[3]);
+            store_block(Wz, tx, ty, R[0], R[1], R[2], R[3]);
           }
       } else {
         const double pd = (double)p, pinv = cc.pinv[z];
@@ -270,10 +292,23 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
                                  mod_odd(acc[tx][ty][4 * r4 + 1], pd, pinv),
                                  mod_odd(acc[tx][ty][4 * r4 + 2], pd, pinv),
                                  mod_odd(acc[tx][ty][4 * r4 + 3], pd, pinv));
-            store_block(tx, ty, R[0], R[1], R[2], R[3]);
+            store_block(Wz, tx, ty, R[0], R[1], R[2], R[3]);
           }
       }
-    } else if constexpr (EPI == 1) {
+    } else if constexpr (EPI == 1 || EPI == 3) {
+      if constexpr (EPI == 3) {
+#pragma unroll
+        for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+          for (int ty = 0; ty < TY; ++ty) {
+            uint32_t R[4];
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4)
+              R[r4] = pack_bytes(acc[tx][ty][4 * r4 + 0] != 0, acc[tx][ty][4 * r4 + 1] != 0,
+                                 acc[tx][ty][4 * r4 + 2] != 0, acc[tx][ty][4 * r4 + 3] != 0);
+            store_block(W, tx, ty, R[0], R[1], R[2], R[3]);
+          }
+      }
       // max over x for each y
 #pragma unroll
       for (int ty = 0; ty < TY; ++ty) {
@@ -397,23 +432,29 @@ void launch_cfg(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t
                 size_t sw, int ldw, int* xmax, int* ymax) {
   const int tiles_x = nx_pad / B, tiles_y = ny_pad / B;
   const dim3 grid((unsigned)(tiles_x * tiles_y * nz)), block(tile_threads<B>());
-  if (epi == 0)
-    hipLaunchKernelGGL((k_gemm_i8<B, 0>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
-                       k_pad, cc, W, sw, ldw, xmax, ymax);
-  else
-    hipLaunchKernelGGL((k_gemm_i8<B, 1>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
-                       k_pad, cc, W, sw, ldw, xmax, ymax);
+  switch (epi) {
+    case 0:
+      hipLaunchKernelGGL((k_gemm_i8<B, 0>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
+                         k_pad, cc, W, sw, ldw, xmax, ymax);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_gemm_i8<B, 1>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
+                         k_pad, cc, W, sw, ldw, xmax, ymax);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_gemm_i8<B, 3>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
+                         k_pad, cc, W, sw, ldw, xmax, ymax);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gemm_i8<B, 4>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
+                         k_pad, cc, W, sw, ldw, xmax, ymax);
+      break;
+  }
 }
 
-// Tile configuration: 0 = automatic; 1 = 256x256, 2 = 128x128 (environment
-// variable OZAKI2_GEMM_CFG, read once; a tuning aid).
-int forced_cfg() {
-  static int v = [] {
-    const char* e = getenv("OZAKI2_GEMM_CFG");
-    return e ? atoi(e) : 0;
-  }();
-  return v;
-}
+// Tile configuration: 0 = automatic; 1 = 256x256, 2 = 128x128 (g_gemm_tile,
+// a tuning knob set through ozaki2_debug_tuning).
+int forced_cfg() { return g_gemm_tile.load(std::memory_order_relaxed); }
 
 // 256x256 tiles (one workgroup per CU, 128 KB of LDS) when there are more
 // than 128 of them, that is when the 128x128 tiles (two workgroups per CU,
@@ -430,6 +471,8 @@ bool use_256(int nx_pad, int ny_pad, int nz) {
 }
 
 }  // namespace
+
+std::atomic<int> g_gemm_tile{0};
 
 void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const BlockRef* map,
                        int blocks, const CrtConsts* ctab) {

@@ -1,6 +1,8 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 
@@ -158,6 +160,12 @@ void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int 
                    int* mu_p, int* nu_p, int* mu, int* nu, float* ef);
 void launch_log2f(hipStream_t s, const float* d, float* out, int count);
 
+// Tuning and test knobs (ozaki2_debug_tuning): a cap on the workgroups of a
+// slice launch (0: none; residue.hip) and the forced tile of the single-problem
+// products (0: automatic, 1: 256x256, 2: 128x128; gemm_i8.hip).
+extern std::atomic<int> g_slice_cap;
+extern std::atomic<int> g_gemm_tile;
+
 // residue.hip: per-device launch figures of the slice kernels (resident workgroups);
 // called once per device before its first launch, outside stream capture.
 void init_slice_launch(int dev);
@@ -182,6 +190,8 @@ void launch_plan_slices(hipStream_t s, Prec pr, bool trans, const void* src, int
 //   X_z = X + z*sx, Y_z = Y + z*sy (X: A side, x = i; Y: B side, y = j).
 //   epi 0: W_z[y][x] = mod(D, p_z) as int8 into W + z*sw, row length ldw.
 //   epi 1: xmax[x] = max_y D, ymax[y] = max_x D (atomicMax; D >= 0).
+//   epi 3: epi 1, and W[y][x] = (D != 0) as one byte (row length ldw).
+//   epi 4: D_z[y][x] as INT32 into (int*)W + z*sw, row length ldw (elements).
 void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                     int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
                     size_t sw, int ldw, int* xmax, int* ymax);
@@ -195,18 +205,20 @@ void launch_gemm_bf16_store(hipStream_t s, const uint16_t* X, const uint16_t* Y,
 void launch_plan_vectors(hipStream_t s, const double* pr, int m_pad, const double* pc, int n_pad,
                          int tiles, const int* rmax, const int* cmax, int m, int n, double* rs,
                          double* cs, double* sr, double* sc);
-void launch_plan_entries(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
-                         const double* cs, const double* sr, const double* sc,
+// S: lower bound of (|A||B|)_ij (scaled), nz: one byte per entry, nonzero
+// exactly when (|A||B|)_ij > 0; both column-major with row length lds_.
+void launch_plan_entries(hipStream_t s, const float* S, const uint8_t* nz, int lds_, int m, int n,
+                         const double* rs, const double* cs, const double* sr, const double* sc,
                          const PlanTable& pt, int* out);
 // N from Nsrc (device) when it is not null; see k_plan_verify.
-void launch_plan_verify(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
-                        const double* cs, const double* sr, const double* sc, const PlanTable& pt,
-                        int N, const int* Nsrc, int* bad);
+void launch_plan_verify(hipStream_t s, const float* S, const uint8_t* nz, int lds_, int m, int n,
+                        const double* rs, const double* cs, const double* sr, const double* sc,
+                        const PlanTable& pt, int N, const int* Nsrc, int* bad);
 // Maximum over entries of the a-posteriori est1 / S (bit pattern into *out,
 // which the caller zeroes); C is the output of the run whose shifts are mu, nu.
 void launch_certify(hipStream_t s, Prec pr, const void* C, int ldc, const int* mu, const int* nu,
-                    const float* S, int lds_, int m, int n, const double* rs, const double* cs,
-                    const double* sr, const double* sc, const CertTable& ct,
+                    const float* S, const uint8_t* nz, int lds_, int m, int n, const double* rs,
+                    const double* cs, const double* sr, const double* sc, const CertTable& ct,
                     unsigned long long* out);
 
 // Grouped launches (one per phase for a whole batch of `count` problems);
@@ -228,6 +240,10 @@ void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const BlockRef*
 void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,
                 const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
                 int ldc);
+// launch_crt plus C'(1), C'(2), Q, C'' as FP64 [4][n][m] into dbg (stage dumps).
+void launch_crt_debug(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,
+                      const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
+                      int ldc, double* dbg);
 void launch_fill_zero(hipStream_t s, Prec pr, void* C, int ldc, int m, int n);
 // Folds the per-call non-finite flag into the sticky status word.
 void launch_or_status(hipStream_t s, const int* flag, int* status);

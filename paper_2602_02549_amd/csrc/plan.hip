@@ -8,7 +8,10 @@
 // sqrt(max_h Cbar_ih) (2^(e'_i/2)), sc_j likewise, t(N) = 1/sqrt(2^5 (P-1)) and
 // extra(N) t^-2 is r_b(N) minus its N-independent output-rounding part.
 // rs, cs, sr, sc are rounded up and S_ij is replaced by a lower bound, so every
-// decision errs towards a larger N.
+// decision errs towards a larger N.  Entries with S_ij = 0 are exact zeros and
+// are skipped, unless the byte nz_ij (Cbar_ij != 0, which holds exactly when
+// (|A||B|)_ij > 0) says the lower bound merely underflowed: such an entry
+// accepts no N (and certifies no eps).
 #include <cstdint>
 
 #include "ozaki2_internal.h"
@@ -99,7 +102,8 @@ __device__ __forceinline__ T block_max(T v) {
 // pass 2 then searches upward from it.  Most entries pass at the running
 // bound in one step.  N advances in step across the wave, so the per-N
 // coefficients are wave-uniform (scalar) loads.
-__global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ S, int lds_,
+__global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ S,
+                                                      const uint8_t* __restrict__ nz, int lds_,
                                                       int m, int n, int iblocks,
                                                       const double* __restrict__ rs,
                                                       const double* __restrict__ cs,
@@ -120,6 +124,9 @@ __global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ 
         P2 = sr[i] * sc[j];
         target = pt.eps * Sl;
         live = true;
+      } else if (nz[(size_t)j * lds_ + i]) {
+        live = true;          // nonzero (|A||B|)_ij with no positive lower bound:
+        target = -1.0;        // T >= 0 never meets it, so no N is accepted
       }
     }
     int first = 0;
@@ -141,7 +148,8 @@ __global__ __launch_bounds__(256) void k_plan_entries(const float* __restrict__ 
 // Pass 2: does N satisfy every entry?  Any failure sets *bad.  With Nsrc,
 // N is read from there (pass 1's result, at least nlo), and nothing is
 // checked if it exceeds nhi.
-__global__ __launch_bounds__(256) void k_plan_verify(const float* __restrict__ S, int lds_, int m,
+__global__ __launch_bounds__(256) void k_plan_verify(const float* __restrict__ S,
+                                                     const uint8_t* __restrict__ nz, int lds_, int m,
                                                      int n, int iblocks,
                                                      const double* __restrict__ rs,
                                                      const double* __restrict__ cs,
@@ -158,6 +166,8 @@ __global__ __launch_bounds__(256) void k_plan_verify(const float* __restrict__ S
       const double A1 = rs[i] * sc[j] + sr[i] * cs[j];
       const double P2 = sr[i] * sc[j];
       if (!plan_ok(pt, N, A1, P2, pt.eps * Sl)) fail = 1;
+    } else if (nz[(size_t)j * lds_ + i]) {
+      fail = 1;
     }
   });
   fail = block_max(fail);
@@ -179,7 +189,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_certify(const T* __restrict__ C, int ldc,
                                                  const int* __restrict__ mu,
                                                  const int* __restrict__ nu,
-                                                 const float* __restrict__ S, int lds_, int m,
+                                                 const float* __restrict__ S,
+                                                 const uint8_t* __restrict__ nz, int lds_, int m,
                                                  int n, int iblocks, const double* __restrict__ rs,
                                                  const double* __restrict__ cs,
                                                  const double* __restrict__ sr,
@@ -196,6 +207,8 @@ __global__ __launch_bounds__(256) void k_certify(const T* __restrict__ C, int ld
       const double est =
           (ct.t * A1 + (ct.k * ct.tt + ct.extra + ct.rel * (cpp + ct.rconst) * kTUp) * P2) * kTUp;
       ratio = fmax(ratio, est / Sl * kTUp);
+    } else if (nz[(size_t)j * lds_ + i]) {
+      ratio = INFINITY;     // nonzero (|A||B|)_ij with no positive lower bound
     }
   });
   ratio = block_max(ratio);
@@ -211,17 +224,17 @@ unsigned entry_grid(int iblocks, int n) {
 }  // namespace
 
 void launch_certify(hipStream_t s, Prec pr, const void* C, int ldc, const int* mu, const int* nu,
-                    const float* S, int lds_, int m, int n, const double* rs, const double* cs,
-                    const double* sr, const double* sc, const CertTable& ct,
+                    const float* S, const uint8_t* nz, int lds_, int m, int n, const double* rs,
+                    const double* cs, const double* sr, const double* sc, const CertTable& ct,
                     unsigned long long* out) {
   const int iblocks = (m + 255) / 256;
   const dim3 grid(entry_grid(iblocks, n)), block(256);
   if (pr == Prec::F64)
-    hipLaunchKernelGGL(k_certify<double>, grid, block, 0, s, (const double*)C, ldc, mu, nu, S,
+    hipLaunchKernelGGL(k_certify<double>, grid, block, 0, s, (const double*)C, ldc, mu, nu, S, nz,
                        lds_, m, n, iblocks, rs, cs, sr, sc, ct, out);
   else
-    hipLaunchKernelGGL(k_certify<float>, grid, block, 0, s, (const float*)C, ldc, mu, nu, S, lds_,
-                       m, n, iblocks, rs, cs, sr, sc, ct, out);
+    hipLaunchKernelGGL(k_certify<float>, grid, block, 0, s, (const float*)C, ldc, mu, nu, S, nz,
+                       lds_, m, n, iblocks, rs, cs, sr, sc, ct, out);
 }
 
 void launch_plan_vectors(hipStream_t s, const double* pr, int m_pad, const double* pc, int n_pad,
@@ -231,19 +244,19 @@ void launch_plan_vectors(hipStream_t s, const double* pr, int m_pad, const doubl
                      n_pad, tiles, rmax, cmax, m, n, rs, cs, sr, sc);
 }
 
-void launch_plan_entries(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
-                         const double* cs, const double* sr, const double* sc,
+void launch_plan_entries(hipStream_t s, const float* S, const uint8_t* nz, int lds_, int m, int n,
+                         const double* rs, const double* cs, const double* sr, const double* sc,
                          const PlanTable& pt, int* out) {
   const int iblocks = (m + 255) / 256;
-  hipLaunchKernelGGL(k_plan_entries, dim3(entry_grid(iblocks, n)), dim3(256), 0, s, S,
+  hipLaunchKernelGGL(k_plan_entries, dim3(entry_grid(iblocks, n)), dim3(256), 0, s, S, nz,
                      lds_, m, n, iblocks, rs, cs, sr, sc, pt, out);
 }
 
-void launch_plan_verify(hipStream_t s, const float* S, int lds_, int m, int n, const double* rs,
-                        const double* cs, const double* sr, const double* sc, const PlanTable& pt,
-                        int N, const int* Nsrc, int* bad) {
+void launch_plan_verify(hipStream_t s, const float* S, const uint8_t* nz, int lds_, int m, int n,
+                        const double* rs, const double* cs, const double* sr, const double* sc,
+                        const PlanTable& pt, int N, const int* Nsrc, int* bad) {
   const int iblocks = (m + 255) / 256;
-  hipLaunchKernelGGL(k_plan_verify, dim3(entry_grid(iblocks, n)), dim3(256), 0, s, S,
+  hipLaunchKernelGGL(k_plan_verify, dim3(entry_grid(iblocks, n)), dim3(256), 0, s, S, nz,
                      lds_, m, n, iblocks, rs, cs, sr, sc, pt, N, Nsrc, bad);
 }
 

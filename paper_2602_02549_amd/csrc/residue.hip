@@ -543,9 +543,9 @@ void fill_occ() {
 }
 
 // Workgroups for `tiles` tiles: all resident slots of the device, or one per
-// tile if the device's figures are unknown.  The environment variable
-// OZAKI2_SLICE_WORKGROUPS (a test aid, read at every launch) caps the count,
-// so that each workgroup walks many tiles.
+// tile if the device's figures are unknown.  A positive g_slice_cap (a test
+// knob set through ozaki2_debug_tuning) caps the count, so that each
+// workgroup walks many tiles.
 int slice_grid(bool f32, bool trans, int variant, int tiles) {
   int grid = tiles;
   int dev = 0;
@@ -554,10 +554,8 @@ int slice_grid(bool f32, bool trans, int variant, int tiles) {
     const int occ = g_occ[f32 ? 1 : 0][trans ? 1 : 0][variant].load(std::memory_order_relaxed);
     if (cus > 0 && occ > 0) grid = (int)std::min<int64_t>(tiles, (int64_t)cus * occ);
   }
-  if (const char* e = getenv("OZAKI2_SLICE_WORKGROUPS")) {
-    const int cap = atoi(e);
-    if (cap > 0) grid = std::min(grid, cap);
-  }
+  const int cap = g_slice_cap.load(std::memory_order_relaxed);
+  if (cap > 0) grid = std::min(grid, cap);
   return grid;
 }
 
@@ -641,6 +639,8 @@ void group_slices_t(hipStream_t s, int mode, int path, const ProbDesc* P, const 
 }
 
 }  // namespace
+
+std::atomic<int> g_slice_cap{0};
 
 void init_slice_launch(int dev) {
   if (dev < 0 || dev >= kMaxDevices) return;

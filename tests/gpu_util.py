@@ -54,6 +54,13 @@ def compare_stages(got: dict, st: dict, C_ref: np.ndarray, N: int) -> list:
         eq(f"A'_{l}", got["Al"][l], st["Al"][l])
         eq(f"B'_{l}", got["BlT"][l], st["Bl"][l].T)
         eq(f"W_{l}", got["WT"][l], st["W"][l].T)
+        if "ClT" in got:      # the INT32 residue products, two's complement
+            eq(f"C'_{l}", got["ClT"][l].astype(np.int64), st["Cl"][l].T)
+    if "C1T" in got:          # Algorithm 3's FP64 intermediates (Lemmas 2-4)
+        eq("C'(1)", got["C1T"].T, st["C1"])
+        eq("C'(2)", got["C2T"].T, st["C2"])
+        eq("Q", got["QT"].T, st["Q"])
+        eq("C''", got["CppT"].T, st["Cpp"])
     eq("C", got["CT"].T, C_ref)
     return bad
 

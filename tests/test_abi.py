@@ -91,6 +91,10 @@ def test_debug_and_log2f_argument_errors():
     assert oz.ozaki2_debug_log2f(None, None, 0) == oz.OK
     assert oz.ozaki2_debug_log2f(None, None, 5) == oz.ERR_INVALID_ARG
     assert oz.ozaki2_debug_stages(64, 4, 4, 4, FAKE, 4, FAKE, 4, 10, [None] * 11) == oz.ERR_INVALID_ARG
+    outs = [None] * 9 + [FAKE]
+    assert oz.ozaki2_debug_stages(64, 4, 4, 4, FAKE, 4, FAKE, 4, 10, outs[:9]) == oz.ERR_INVALID_ARG
+    assert oz.ozaki2_debug_stages(64, 4, 4, 4, FAKE, 4, FAKE, 4, 10, outs + [None] * 7) == oz.ERR_INVALID_ARG
+    assert oz.ozaki2_debug_stages(64, 4, 4, 4, FAKE, 4, FAKE, 4, 50, outs + [None] * 6) == oz.ERR_N_RANGE
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
@@ -134,3 +138,18 @@ def test_certified_argument_errors_and_workspace_query():
     assert q(64, 300, 200, 500, 14) > oz.ozaki2_workspace_bytes(64, 300, 200, 500, 14)
     assert q(64, 300, 200, 500, 20) > q(64, 300, 200, 500, 14)
     assert q(64, 300, 200, 500, 50) == 0 and q(32, 300, 200, 500, 17) == 0 and q(64, 0, 4, 4, 14) == 0
+
+
+def test_tuning_knobs():
+    # Set, read back through `previous`, restore; bad knobs and values rejected.
+    t = oz.ozaki2_debug_tuning
+    rc, prev = t(oz.KNOB_SLICE_WORKGROUPS, 5)
+    assert rc == oz.OK and prev == 0
+    assert t(oz.KNOB_SLICE_WORKGROUPS, 0) == (oz.OK, 5)
+    assert t(oz.KNOB_GEMM_TILE, 3)[0] == oz.ERR_INVALID_ARG
+    assert t(oz.KNOB_BATCH_SPLIT, -2)[0] == oz.ERR_INVALID_ARG
+    assert t(oz.KNOB_BATCH_GRAPH, 2)[0] == oz.ERR_INVALID_ARG
+    assert t(99, 0)[0] == oz.ERR_INVALID_ARG
+    with oz.tuning(oz.KNOB_BATCH_SPLIT, 4):
+        assert t(oz.KNOB_BATCH_SPLIT, 4) == (oz.OK, 4)
+    assert t(oz.KNOB_BATCH_SPLIT, -1) == (oz.OK, -1)

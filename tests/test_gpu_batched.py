@@ -89,18 +89,18 @@ def test_batched_one_residue_path(N, dtype):
                 assert np.array_equal(got, os_ii(A, B, Nq)), f"problem {q} vs oracle"
 
 
-@pytest.mark.parametrize("split", ["0", "1000000", "4"])
-def test_batched_tile_splits_and_eager(split, monkeypatch):
+@pytest.mark.parametrize("split", [0, 1000000, 4])
+def test_batched_tile_splits_and_eager(split):
     # Every tile split (all 256x256, all 128x128, mixed) and the eager
     # (uncaptured) launch sequence give the same bits.
     announce(f"batched split={split}")
     cases = SMALL[:6] + SMALL[9:]
     As, Bs = make_batch(cases, np.float64, seed=300)
     Ns = [c[3] for c in cases]
-    monkeypatch.setenv("OZAKI2_BATCH_SPLIT", split)
-    _, _, C1, _ = run_batched(As, Bs, Ns)
-    monkeypatch.setenv("OZAKI2_BATCH_GRAPH", "0")
-    _, _, C2, _ = run_batched(As, Bs, Ns)
+    with oz.tuning(oz.KNOB_BATCH_SPLIT, split):
+        _, _, C1, _ = run_batched(As, Bs, Ns)
+        with oz.tuning(oz.KNOB_BATCH_GRAPH, 0):
+            _, _, C2, _ = run_batched(As, Bs, Ns)
     for q, (A, B, N) in enumerate(zip(As, Bs, Ns)):
         ref = single(A, B, N)
         assert np.array_equal(host(C1[q]).T, ref), f"graph, problem {q}"

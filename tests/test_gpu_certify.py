@@ -112,3 +112,18 @@ def test_certified_caller_owned_workspace():
         torch.cuda.synchronize()
     finally:
         oz.ozaki2_set_workspace(None, 0)
+
+
+def test_certified_tiny_nonzero_entry_is_not_skipped():
+    # Entry (0, 1) of |A||B| is 2^-160 > 0, but its lower bound underflows to
+    # 0.  It must not be skipped: the certificate is infinite at every N and
+    # the call ends UNREACHABLE at N = 49, with C the plain result at 49.
+    announce("certified: nonzero entry whose lower bound of S underflows")
+    A, B = gemm_inputs(60, 70, 90, phi=0.5, seed=41)
+    A[0, :] = 0.0
+    A[0, 0], A[0, 2] = 1.0, 2.0 ** -80
+    B[:, 1] = 0.0
+    B[1, 1], B[2, 1] = 1.0, 2.0 ** -80
+    C, rc, N_used, ratio = oz.gemm_certified(dev(A), dev(B), 1e-3, 40)
+    assert rc == oz.ERR_UNREACHABLE and N_used == 49 and ratio == float("inf")
+    assert np.array_equal(host(C), os_ii(A, B, 49))

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Integer stages (mu', nu', Cbar maxima, mu, nu, A'_l, B'_l, W_l) must be
-bit-exact; log2f must equal the correctly rounded value on every input;
+Integer stages (mu', nu', Cbar maxima, mu, nu, A'_l, B'_l, the INT32 products
+C'_l, W_l) must be bit-exact, and so must the FP64 intermediates C'(1), C'(2),
+Q and C'' of Algorithm 3; log2f must equal the correctly rounded value on every input;
 outputs must be within 2^-50 (FP64) / 2^-22 (FP32) of the oracle per entry.
 The library follows the oracle's operation order in the CRT (explicit fma,
 fixed l order), so the outputs are in fact required to be bit-identical too.
@@ -43,6 +44,7 @@ def test_stages_config_256():
     got = {kk: host(v) for kk, v in oz.debug_stages(dev(A), dev(B), 14).items()}
     C_ref, st = os_ii(A, B, 14, stages=True)
     assert compare_stages(got, st, C_ref, 14) == []
+    assert "ClT" in got and "CppT" in got
     from oracle.constants import constants
     from oracle.exact import exact_int_product
     const = constants(14, 64)
@@ -56,7 +58,7 @@ def test_stages_config_256():
     assert oz.ozaki2_sync_status() == oz.OK
 
 
-def test_int32_wrap_at_k_max(monkeypatch):
+def test_int32_wrap_at_k_max():
     # k = 2^17 with every residue modulo 256 equal to -128 (N = 14): the
     # p = 256 residue product sums k terms of 2^14 to 2^31, which the INT8
     # matrix cores must wrap to -2^31 (W = 0), not saturate (W = -1).  Every
@@ -71,6 +73,7 @@ def test_int32_wrap_at_k_max(monkeypatch):
     C_ref, st = os_ii(A, B, N, stages=True)
     l = list(st["const"].p).index(256)
     assert np.all(st["Cl"][l] == -2 ** 31)
+    assert np.all(got["ClT"][l] == -2 ** 31)      # the wrap, seen on the matrix cores
     assert np.all(got["WT"][l] == 0)
     bad = compare_stages(got, st, C_ref, N)
     assert bad == [], bad
@@ -87,16 +90,16 @@ def test_int32_wrap_at_k_max(monkeypatch):
     assert np.array_equal(ref[np.ix_(rows, cols)], want)
     dA, dB = dev(np.ascontiguousarray(A.T)), dev(np.ascontiguousarray(B.T))
     del A, B
-    for split in ("0", "1000000"):
+    for split in (0, 1000000):
         announce(f"int32 wrap batched split={split}")
-        monkeypatch.setenv("OZAKI2_BATCH_SPLIT", split)
-        Cc = torch.full((n, m), float("nan"), dtype=torch.float64, device="cuda:0")
-        oz.gemm_batched_cm([dA], [dB], [Cc], [(m, n, k)], [N])
+        with oz.tuning(oz.KNOB_BATCH_SPLIT, split):
+            Cc = torch.full((n, m), float("nan"), dtype=torch.float64, device="cuda:0")
+            oz.gemm_batched_cm([dA], [dB], [Cc], [(m, n, k)], [N])
         assert oz.ozaki2_sync_status() == oz.OK
         assert np.array_equal(host(Cc).T, ref), f"split {split}"
 
 
-def test_single_call_256_tiles_ragged(monkeypatch):
+def test_single_call_256_tiles_ragged():
     # 768 x 1000, k = 130, N = 16: padding n to 256 costs nothing over 128,
     # and the 16 residue products have 3 x 4 x 16 = 192 tiles of 256 x 256,
     # so the single call takes the 256 x 256 kernel for them (the scaling
@@ -110,12 +113,22 @@ def test_single_call_256_tiles_ragged(monkeypatch):
     assert oz.ozaki2_sync_status() == oz.OK
     rows, cols = np.array([0, 255, 256, 511, 767]), np.array([0, 255, 256, 767, 768, 999])
     assert np.array_equal(C[np.ix_(rows, cols)], os_ii(A, B, N, rows=rows, cols=cols))
-    monkeypatch.setenv("OZAKI2_BATCH_SPLIT", "1000000")
     dA, dB = dev(np.ascontiguousarray(A.T)), dev(np.ascontiguousarray(B.T))
     Cc = torch.full((n, m), float("nan"), dtype=torch.float64, device="cuda:0")
-    oz.gemm_batched_cm([dA], [dB], [Cc], [(m, n, k)], [N])
+    with oz.tuning(oz.KNOB_BATCH_SPLIT, 1000000):
+        oz.gemm_batched_cm([dA], [dB], [Cc], [(m, n, k)], [N])
     assert oz.ozaki2_sync_status() == oz.OK
     assert np.array_equal(host(Cc).T, C)
+
+
+def test_stages_256_tiles():
+    # 768 x 1000 x 130, N = 16: the residue products run on the 256 x 256
+    # kernel (192 tiles of 256 x 256 over the 16 products, and padding n to
+    # 256 costs nothing over 128).  Every stage bit-exact, the INT32 products
+    # C'_l and the full W_l of that kernel included.
+    m, n, k, N = 768, 1000, 130, 16
+    assert (m // 256) * ((n + 255) // 256) * N > 128
+    run_stage_case(m, n, k, N, 1.0, seed=31, dtype=np.float64)
 
 
 @pytest.mark.parametrize("m,n,k,N,phi", [
@@ -160,13 +173,17 @@ def test_stages_fp32(m, n, k, N, phi):
 
 
 @pytest.mark.parametrize("cap", ["1", "5"])
-def test_slices_few_workgroups(cap, monkeypatch):
+def test_slices_few_workgroups(cap):
     # The slice kernels walk their tiles in a grid-stride loop, prefetching the
     # next tile.  Capped at `cap` workgroups, every workgroup walks many tiles
     # (with 5, unevenly many).  Every stage stays bit-exact on each residue
     # path (2 and 3 limbs, one, three and four exact steps, FP32), and the
     # grouped kernels of a batch give the oracle's result.
-    monkeypatch.setenv("OZAKI2_SLICE_WORKGROUPS", cap)
+    with oz.tuning(oz.KNOB_SLICE_WORKGROUPS, int(cap)):
+        _slices_few_workgroups(cap)
+
+
+def _slices_few_workgroups(cap):
     for m, n, k, N, phi, dt in [(300, 200, 500, 14, 0.5, np.float64), (257, 129, 130, 16, 1.0, np.float64),
                                 (100, 90, 300, 7, 2.0, np.float64), (90, 70, 150, 28, 3.0, np.float64),
                                 (60, 50, 100, 36, 4.0, np.float64), (70, 65, 200, 49, 4.0, np.float64),
@@ -329,7 +346,7 @@ def test_full_size_sampled(dtype, N, size):
     assert oz.ozaki2_sync_status() == oz.OK
 
 
-@pytest.mark.parametrize("phi", [0.0, 2.0, 4.0])
+@pytest.mark.parametrize("phi", [0.0, 1.0, 2.0, 4.0])
 def test_wide_exponent_4096_sampled(phi):
     # The wide-exponent workload at 4096^3 with N from the bound at 1e-15
     # (49 where it is unreachable): sampled rows x columns against the oracle.

@@ -85,3 +85,50 @@ def test_required_moduli_4096(phi):
     hi = required_moduli_from_terms(terms, 1e-15 * (1 - slack(4096)))
     print(f"[planner] phi={phi}: oracle {lo[:2]} .. {hi[:2]}, GPU rc={rc} N={Ng}", flush=True)
     check_between(rc, Ng, lo, hi, 49)
+
+
+def _tiny_product_inputs(e):
+    """60 x 70 x 90 inputs in which entry (0, 1) of |A||B| is the single
+    product 2^e * 2^e: row 0 of A is [1, 0, 2^e, 0, ...] and column 1 of B
+    is [0, 1, 2^e, 0, ...]; everything else is a regular draw."""
+    A, B = gemm_inputs(60, 70, 90, phi=0.5, seed=41)
+    A[0, :] = 0.0
+    A[0, 0], A[0, 2] = 1.0, 2.0 ** e
+    B[:, 1] = 0.0
+    B[1, 1], B[2, 1] = 1.0, 2.0 ** e
+    return A, B
+
+
+def test_required_moduli_tiny_nonzero_entry():
+    # (|A||B|)_01 = 2^-160: positive, but its BF16 / FP32 lower bound
+    # underflows to 0.  The entry must still count (the planner's scaling
+    # product marks it nonzero): no N is accepted for it, so the GPU answer
+    # is UNREACHABLE, at or above the oracle's N (whose FP64 S holds 2^-160).
+    announce("planner: nonzero entry whose lower bound of S underflows")
+    A, B = _tiny_product_inputs(-80)
+    rc, Ng = oz.required_moduli(dev(A), dev(B), 1e-3)
+    lo = required_moduli_from_terms(planner_terms(A, B), 1e-3 * (1 + 1e-9))
+    assert rc == oz.ERR_UNREACHABLE and Ng == 49
+    assert effective(lo[1], lo[0], 49) <= effective(rc, Ng, 49)
+    # 2^-1200 underflows in FP64 too: the oracle agrees that no N works.
+    A, B = _tiny_product_inputs(-600)
+    rc, Ng = oz.required_moduli(dev(A), dev(B), 1e-3)
+    lo = required_moduli_from_terms(planner_terms(A, B), 1e-3)
+    assert not lo[1]
+    assert rc == oz.ERR_UNREACHABLE and Ng == 49
+
+
+def test_required_moduli_exact_zero_entry_is_skipped():
+    # A row and a column with disjoint supports give an exactly zero entry,
+    # which must not make the target unreachable.
+    announce("planner: exactly zero entry")
+    A, B = gemm_inputs(60, 70, 90, phi=0.5, seed=42)
+    A[0, 45:] = 0.0
+    B[:45, 1] = 0.0
+    rc, Ng = oz.required_moduli(dev(A), dev(B), 1e-12)
+    terms = planner_terms(A, B)
+    assert not terms["nz"][0, 1]
+    lo = required_moduli_from_terms(terms, 1e-12 * (1 + 1e-9))
+    hi = required_moduli_from_terms(terms, 1e-12 * (1 - slack(90)))
+    check_between(rc, Ng, lo, hi, 49)
+    assert rc == oz.OK

@@ -14,8 +14,8 @@ from workload import gemm_inputs, wrap_inputs
 def _const_mut(monkeypatch, fn):
     real = oz.constants
 
-    def patched(N, b=64):
-        return fn(real(N, b))
+    def patched(N, b=64, table="paper"):
+        return fn(real(N, b, table))
     monkeypatch.setattr(oz, "constants", patched)
 
 

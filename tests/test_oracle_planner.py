@@ -45,3 +45,29 @@ def test_unreachable_target():
 def test_wider_exponent_range_needs_more_moduli():
     Ns = [required_moduli(*gemm_inputs(12, 12, 80, phi=phi, seed=3), 1e-15)[0] for phi in (0.0, 4.0)]
     assert Ns[0] <= Ns[1]
+
+
+def test_entry_whose_S_underflows_admits_no_N():
+    # (|A||B|)_ij > 0 with every product term tiny: row [1, 0, 2^-600] of A and
+    # column [0, 1, 2^-600] of B give (|A||B|)_01 = 2^-1200, which FP64
+    # cannot hold.  That entry is nonzero, so it must not be skipped: no N
+    # can meet a relative target for it, and the planner must say so.
+    A = np.array([[1.0, 0.0, 2.0 ** -600], [0.5, 0.25, 0.125]])
+    B = np.array([[1.0, 0.0], [0.0, 1.0], [0.5, 2.0 ** -600]])
+    S_exact = 2.0 ** -600 * 2.0 ** -600
+    assert S_exact == 0.0                      # underflows in FP64 ...
+    terms = planner_terms(A, B)
+    assert terms["nz"][0, 1] and terms["S"][0, 1] == 0.0   # ... but the entry is nonzero
+    N, ok, det = required_moduli(A, B, 1e-3)
+    assert not ok and N == 49 and det["ratio"] == float("inf")
+
+
+def test_exact_zero_entries_are_skipped():
+    # An entry whose row and column have disjoint supports is exactly zero and
+    # does not constrain N.
+    A = np.array([[1.0, 0.0], [0.5, 0.25]])
+    B = np.array([[0.0, 1.0], [1.0, 0.5]])
+    terms = planner_terms(A, B)
+    assert not terms["nz"][0, 0] and terms["nz"][0, 1]
+    N, ok, _ = required_moduli(A, B, 1e-12)
+    assert ok

@@ -1,8 +1,10 @@
-"""Exact reference values of AB at sampled entries, for error reporting.
+"""Exact reference values of AB, for error measurement.
 
-Not part of the method: every FP64 entry is an integer times a power of two,
-so after scaling each matrix by a power of two the sampled dot products are
-exact big-integer sums.
+Not part of the method (no step of Ozaki-II is here): every FP64 entry is an
+integer times a power of two, so after scaling each matrix by one power of
+two its entries are integers and AB is an exact big-integer product.  The
+benchmark's error samples and the oracle's exact products (oracle/exact.py)
+both use int_scaled, so the exact-product code exists once.
 """
 from __future__ import annotations
 
@@ -11,7 +13,8 @@ from fractions import Fraction
 import numpy as np
 
 
-def _as_ints(X: np.ndarray):
+def int_scaled(X: np.ndarray):
+    """(object array of Python ints I, exponent E) with X == I * 2^E exactly."""
     X = X.astype(np.float64)
     f, e = np.frexp(X)
     mant = np.ldexp(f, 53).astype(np.int64)
@@ -29,8 +32,8 @@ class ExactSamples:
 
     def __init__(self, A: np.ndarray, B: np.ndarray, rows, cols):
         Ar, Bc = A[np.asarray(rows)], B[:, np.asarray(cols)]
-        IA, EA = _as_ints(Ar)
-        IB, EB = _as_ints(Bc)
+        IA, EA = int_scaled(Ar)
+        IB, EB = int_scaled(Bc)
         P = IA.dot(IB)
         scale = Fraction(2) ** (EA + EB)
         self.AB = np.empty(P.shape, dtype=object)
