@@ -145,6 +145,27 @@ size_t ozaki2_workspace_bytes(int prec, int m, int n, int k, int N);
  * calls that use it are in flight. */
 int ozaki2_set_workspace(void *dptr, size_t bytes);
 
+/*
+ * ozaki2_gemm_noalloc - for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): ozaki2_gemm (prec 64) or ozaki2_sgemm (prec 32) with the same
+ * arguments, results and asynchrony, but its workspace is a fixed device
+ * array of OZAKI2_NOALLOC_SCRATCH_BYTES per device, owned by the library and
+ * held from the device's first call until the process ends.  The call
+ * allocates nothing: no hipMalloc, no hipFree, no allocating library call,
+ * and it ignores any workspace installed with ozaki2_set_workspace.
+ *   prec : 64 (A, B, C are double*) or 32 (float*).
+ * Returns OZAKI2_ERR_WORKSPACE, before anything is enqueued, when the call
+ * needs more than that array holds (ozaki2_workspace_bytes(prec, m, n, k, N)
+ * + 256 > OZAKI2_NOALLOC_SCRATCH_BYTES; e.g. FP64 2048^3 fits up to N = 21).
+ * Every call on one device shares that device's array, so calls that
+ * overlap on one device (other streams, other host threads) race on it.
+ * A non-finite input is reported by ozaki2_sync_status as for ozaki2_gemm.
+ */
+#define OZAKI2_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int ozaki2_gemm_noalloc(int prec, int m, int n, int k, const void *A, int lda, const void *B,
+                        int ldb, void *C, int ldc, int N);
+
 /* Wait for the stream, then return OZAKI2_OK or the first data-dependent
  * status recorded since the previous ozaki2_sync_status (and clear it). */
 int ozaki2_sync_status(void);

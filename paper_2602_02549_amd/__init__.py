@@ -44,6 +44,8 @@ _SIGS = {
     "ozaki2_workspace_bytes": ([_c_int, _c_int, _c_int, _c_int, _c_int], _c_size),
     "ozaki2_set_workspace": ([_c_ptr, _c_size], _c_int),
     "ozaki2_sync_status": ([], _c_int),
+    "ozaki2_gemm_noalloc": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int,
+                             _c_int], _c_int),
     "ozaki2_gemm_batched": ([_c_int, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_ptr),
                              ctypes.POINTER(_c_int), ctypes.POINTER(_c_ptr), ctypes.POINTER(_c_int),
                              ctypes.POINTER(_c_ptr), ctypes.POINTER(_c_int)], _c_int),
@@ -127,6 +129,10 @@ def ozaki2_set_workspace(ptr, nbytes):
 
 def ozaki2_sync_status():
     return _call("ozaki2_sync_status")
+
+
+def ozaki2_gemm_noalloc(prec, m, n, k, A, lda, B, ldb, C, ldc, N):
+    return _call("ozaki2_gemm_noalloc", prec, m, n, k, A, lda, B, ldb, C, ldc, N)
 
 
 def ozaki2_gemm_batched(prec, mnkN, A, lda, B, ldb, C, ldc):

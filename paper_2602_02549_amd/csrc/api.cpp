@@ -377,7 +377,8 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
   char* ws;
   int* status;
   if ((rc = get_workspace(L.total, &ws, &status))) return rc;
-  rc = run_pipeline(pr, m, n, k, A, lda, B, ldb, C, ldc, cc, L, ws, status, s, dbg != nullptr);
+  if (!dbg) return run_pipeline(pr, m, n, k, A, lda, B, ldb, C, ldc, cc, L, ws, status, s, false);
+  rc = run_pipeline(pr, m, n, k, A, lda, B, ldb, C, ldc, cc, L, ws, status, s, true);
   if (rc || !dbg) return rc;
   // debug dumps (see ozaki2_debug_stages)
   auto cp = [&](void* dst, size_t off, size_t bytes) {
@@ -441,6 +442,39 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
   }
   return hipStreamSynchronize(s) == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
 }
+
+}  // namespace
+
+namespace oz2 {
+
+// Algorithm 1 for one problem with the workspace `ws` (capacity `cap`
+// bytes) and status word `status` that the caller provides; allocates
+// nothing.  The size check comes before any HIP call.
+int gemm_on_buffer(Prec pr, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+                   void* C, int ldc, int N, size_t cap, BufferSource get) {
+  const int b = pr == Prec::F64 ? 64 : 32;
+  int rc = check_args(m, n, k, A, lda, B, ldb, C, ldc, true);
+  if (rc) return rc;
+  if ((rc = check_N(N, b))) return rc;
+  if (m == 0 || n == 0) return OZAKI2_OK;
+  const Layout L = layout(m, n, k > 0 ? k : 1, N, single_row_pad(m, n, N));
+  if (L.total > cap) return OZAKI2_ERR_WORKSPACE;
+  hipStream_t s = g_stream;
+  if (k == 0) {
+    launch_fill_zero(s, pr, C, ldc, m, n);
+    return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
+  }
+  CrtConsts cc;
+  if ((rc = get_consts(N, b, &cc))) return rc;
+  char* ws = nullptr;
+  int* status = nullptr;
+  if ((rc = get(&ws, &status))) return rc;
+  return run_pipeline(pr, m, n, k, A, lda, B, ldb, C, ldc, cc, L, ws, status, s, false);
+}
+
+}  // namespace oz2
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // batched execution: every phase of Algorithm 1 is one grouped launch over all
@@ -860,11 +894,16 @@ int ozaki2_sync_status(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     status = g_dev[dev].status;
   }
-  if (!status) return OZAKI2_OK;
-  int h = 0;
-  if (hipMemcpy(&h, status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return OZAKI2_ERR_HIP;
-  if (hipMemset(status, 0, sizeof(int)) != hipSuccess) return OZAKI2_ERR_HIP;
-  return h ? OZAKI2_ERR_NONFINITE : OZAKI2_OK;
+  // The workspace path's word and the allocation-free entry point's word.
+  int any = 0;
+  for (int* w : {status, noalloc_status(dev)}) {
+    if (!w) continue;
+    int h = 0;
+    if (hipMemcpy(&h, w, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return OZAKI2_ERR_HIP;
+    if (h && hipMemset(w, 0, sizeof(int)) != hipSuccess) return OZAKI2_ERR_HIP;
+    any |= h;
+  }
+  return any ? OZAKI2_ERR_NONFINITE : OZAKI2_OK;
 }
 
 int ozaki2_gemm_batched(int prec, int count, const int* mnkN, const void* const* A, const int* lda,

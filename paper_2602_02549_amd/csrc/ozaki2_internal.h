@@ -248,4 +248,15 @@ void launch_fill_zero(hipStream_t s, Prec pr, void* C, int ldc, int m, int n);
 // Folds the per-call non-finite flag into the sticky status word.
 void launch_or_status(hipStream_t s, const int* flag, int* status);
 
+// api.cpp: Algorithm 1 for one problem on a workspace of `cap` bytes that
+// `get` supplies, with its sticky status word; checks the arguments and the
+// size (OZAKI2_ERR_WORKSPACE if the layout needs more than cap) before any
+// HIP call and allocates nothing.
+typedef int (*BufferSource)(char** ws, int** status);
+int gemm_on_buffer(Prec pr, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+                   void* C, int ldc, int N, size_t cap, BufferSource get);
+// noalloc.hip: the status word of the allocation-free entry point on device
+// `dev`, or nullptr while that entry point has not been set up there.
+int* noalloc_status(int dev);
+
 }  // namespace oz2

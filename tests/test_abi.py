@@ -87,6 +87,27 @@ def test_batched_rejects_bad_problem_before_running():
     assert oz.ozaki2_gemm_batched(16, [], [], [], [], [], [], []) == oz.ERR_INVALID_ARG
 
 
+def test_noalloc_rejections_before_running():
+    # The allocation-free entry point checks its arguments and the fixed
+    # scratch size on the host; nothing here reaches a device.
+    f = oz.ozaki2_gemm_noalloc
+    assert f(16, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 10) == oz.ERR_INVALID_ARG
+    assert f(64, 4, 4, 4, FAKE, 3, FAKE, 4, FAKE, 4, 10) == oz.ERR_INVALID_ARG
+    assert f(64, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 50) == oz.ERR_N_RANGE
+    assert f(32, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 17) == oz.ERR_N_RANGE
+    assert f(64, 4, 4, 2 ** 17 + 1, FAKE, 4, FAKE, 2 ** 17 + 1, FAKE, 4, 10) == oz.ERR_K_RANGE
+    assert f(64, 0, 4, 4, None, 1, FAKE, 4, None, 1, 10) == oz.OK
+    cap = 256 << 20
+    # 2048^3 FP64 fits up to N = 21 and not at N = 22; 4096^3 not at N = 14
+    # (FP64) or N = 7 (FP32)
+    assert oz.ozaki2_workspace_bytes(64, 2048, 2048, 2048, 21) + 256 <= cap
+    assert oz.ozaki2_workspace_bytes(64, 2048, 2048, 2048, 22) + 256 > cap
+    assert f(64, 2048, 2048, 2048, FAKE, 2048, FAKE, 2048, FAKE, 2048, 22) == oz.ERR_WORKSPACE
+    assert oz.ozaki2_workspace_bytes(32, 4096, 4096, 4096, 7) + 256 > cap
+    assert f(64, 4096, 4096, 4096, FAKE, 4096, FAKE, 4096, FAKE, 4096, 14) == oz.ERR_WORKSPACE
+    assert f(32, 4096, 4096, 4096, FAKE, 4096, FAKE, 4096, FAKE, 4096, 7) == oz.ERR_WORKSPACE
+
+
 def test_debug_and_log2f_argument_errors():
     assert oz.ozaki2_debug_log2f(None, None, 0) == oz.OK
     assert oz.ozaki2_debug_log2f(None, None, 5) == oz.ERR_INVALID_ARG
