@@ -38,6 +38,16 @@ MODULI = (
 )
 N_MIN, N_MAX = 2, 49          # Algorithm 2/3 preconditions: 2 <= N <= 49
 K_MAX = 2 ** 17               # Section 3: k <= 2^17
+# Reading R22 (k beyond the paper's 2^17): every use of k <= 2^17 in
+# Sections 3-4 is one of (i) Cbar = Abar Bbar <= 2^12 k exact in INT32,
+# (ii) log2 Cbar <= 29 in the proofs of Lemmas 0 and 1, (iii) each residue
+# product exact in INT32.  For k < 2^19, (i) still holds (2^12 k < 2^31),
+# (ii) holds with 31 in place of 29 (the exhaustive claim of Lemma 0's proof
+# can only fail for Cbar < 2^16, and Lemma 1's constant 147 u_32 becomes
+# 157 u_32, still far inside its slack), and (iii) is kept by accumulating
+# each residue product in chunks of 2^17 of k, each exact in INT32, whose
+# residues mod p_l are added mod p_l.
+K_MAX_EXT = 2 ** 19 - 1
 
 U32 = Fraction(1, 2 ** 24)    # unit roundoff of FP32 (Section 1.2)
 U64 = Fraction(1, 2 ** 53)    # unit roundoff of FP64

@@ -27,13 +27,17 @@ Readings where the paper is silent (R numbers shared with the library's document
   R13 the inverse scaling is one multiplication by 2^(-mu_i - nu_j); for
       b = 32 the FP32 C'' is scaled exactly and rounded once to FP32.
   R14 non-finite input is outside the domain: the oracle raises.
+  R22 k may reach 2^19 - 1 (the paper assumes k <= 2^17): Cbar <= 2^12 k
+      stays below 2^31, and beyond 2^17 each residue product is formed in
+      chunks of 2^17 of k whose residues are added mod p_l (see
+      oracle/constants.py, K_MAX_EXT).
   b=32 requires N <= 16 so that the FP32 value single(C'') cannot overflow
       (|A'B'| < P/2 and P/2 < 2^128 only up to N = 16).
 
 Exactness arguments used for speed (each one asserted at run time):
   * Abar Bbar, and A'_l B'_l, are computed with FP64 BLAS: all terms and
     partial sums are integers below 2^53 (entries <= 64 resp. <= 128 in
-    magnitude, k <= 2^17), so every blocking order gives the exact result
+    magnitude, k < 2^19), so every blocking order gives the exact result
     (eq. 2^29 of Section 3.2 and the bound in Section 3.3).
   * A' = trunc(ldexp(A, mu)) in FP64 is exact: ldexp only rounds when the
     result is below 2^-1022, where trunc gives 0 either way.
@@ -47,7 +51,7 @@ from fractions import Fraction
 
 import numpy as np
 
-from .constants import K_MAX, constants
+from .constants import K_MAX, K_MAX_EXT, constants
 from .fp import fma64, ldexp64, mul64, add64, round_f32
 
 # --------------------------------------------------------------------------
@@ -60,8 +64,8 @@ def _check_inputs(A: np.ndarray, B: np.ndarray) -> int:
         raise ValueError("shapes must be (m,k) and (k,n)")
     if A.dtype != B.dtype or A.dtype not in (np.float64, np.float32):
         raise ValueError("A and B must both be float64 or both float32")
-    if A.shape[1] > K_MAX:
-        raise ValueError("k must be <= 2^17 (Section 3)")
+    if A.shape[1] > K_MAX_EXT:
+        raise ValueError("k must be below 2^19 (Section 3's k <= 2^17, widened by reading R22)")
     if not (np.all(np.isfinite(A)) and np.all(np.isfinite(B))):
         raise ValueError("non-finite input is outside the domain of the method (R14)")
     return 64 if A.dtype == np.float64 else 32
@@ -180,7 +184,8 @@ def scaling(A: np.ndarray, B: np.ndarray, N: int, rows=None, cols=None,
     Abar = ceil_scaled(absA, mu_p[:, None])                           # Abar
     Bbar = ceil_scaled(absB, nu_p[None, :])                           # Bbar
 
-    # Cbar = Abar Bbar on "INT8 matrix engines"; exact integers <= 2^12 k <= 2^29.
+    # Cbar = Abar Bbar on "INT8 matrix engines"; exact integers <= 2^12 k
+    # (<= 2^29 for k <= 2^17; below 2^31 for k < 2^19, reading R22).
     bound = 64.0 * 64.0 * max(k, 1)
     full = len(rows) == m and len(cols) == n
     if full:
@@ -192,7 +197,7 @@ def scaling(A: np.ndarray, B: np.ndarray, N: int, rows=None, cols=None,
         Cbar = None
         rmax = exact_int_matmul(Abar[rows], Bbar, bound).max(axis=1)
         cmax = exact_int_matmul(Abar, Bbar[:, cols], bound).max(axis=0)
-    assert rmax.size == 0 or rmax.max() <= 2 ** 29
+    assert rmax.size == 0 or rmax.max() <= 2 ** 12 * k < 2 ** 31
 
     mu = np.array([shift(mu_p[i], rmax[t], const) for t, i in enumerate(rows)], dtype=np.int64)
     nu = np.array([shift(nu_p[j], cmax[t], const) for t, j in enumerate(cols)], dtype=np.int64)
@@ -211,17 +216,33 @@ def scaling(A: np.ndarray, B: np.ndarray, N: int, rows=None, cols=None,
 
 
 def residue_products(Ap: np.ndarray, Bp: np.ndarray, const) -> dict:
-    """Algorithm 3, residue steps: A'_l, B'_l, C'_l (INT32) and W_l."""
+    """Algorithm 3, residue steps: A'_l, B'_l, C'_l (INT32) and W_l.
+
+    For k <= 2^17, C'_l is the INT32 product (two's complement; it wraps only
+    for p = 256, where the wrap keeps it congruent mod 256) and
+    W_l = mod(C'_l, p_l).  For larger k (reading R22) the product is formed
+    in chunks of 2^17 of k, each such INT32 product, and
+    W_l = mod(sum of the chunks' mod(., p_l), p_l); the stage C'_l then
+    holds the exact product A'_l B'_l (int64)."""
     k = Ap.shape[1]
     Al, Bl, Cl, W = [], [], [], []
     for p in const.p:
         a = mod_sym(Ap, p)
         bm = mod_sym(Bp, p)
-        c = wrap_int32(exact_int_matmul(a, bm, 128.0 * 128.0 * max(k, 1)))
+        if k <= K_MAX:
+            c = wrap_int32(exact_int_matmul(a, bm, 128.0 * 128.0 * max(k, 1)))
+            w = mod_sym(c, p)
+        else:
+            c = exact_int_matmul(a, bm, 128.0 * 128.0 * k)
+            w = np.zeros(c.shape, dtype=np.int64)
+            for h0 in range(0, k, K_MAX):
+                part = wrap_int32(exact_int_matmul(a[:, h0:h0 + K_MAX], bm[h0:h0 + K_MAX],
+                                                   128.0 * 128.0 * K_MAX))
+                w = mod_sym(w + mod_sym(part, p), p)
         Al.append(a)
         Bl.append(bm)
         Cl.append(c)
-        W.append(mod_sym(c, p))
+        W.append(w)
     return dict(Al=Al, Bl=Bl, Cl=Cl, W=W)
 
 

@@ -21,7 +21,7 @@ def _abs_int(X):
 
 def pin_scaling(A, B, st):
     """Section 3.2 facts: 2^mu' max|a| in [32, 64); Abar, Bbar in [0, 64] and
-    Abar >= 2^mu'|A| (a ceiling); Cbar row/col maxima <= 2^29; A' equals
+    Abar >= 2^mu'|A| (a ceiling); Cbar row/col maxima <= 2^12 k (< 2^31); A' equals
     trunc(2^mu a) computed with exact rationals."""
     bad = []
     A64, B64 = np.abs(A.astype(np.float64)), np.abs(B.astype(np.float64))
@@ -38,8 +38,9 @@ def pin_scaling(A, B, st):
     scaled = np.ldexp(A64, st["mu_p"][:, None].astype(np.int32))
     if np.any(Ab < scaled) or np.any(Ab >= scaled + 1):
         bad.append("Abar is not the ceiling of 2^mu'|A|")
-    if st["rmax"].max(initial=0) > 2 ** 29 or st["cmax"].max(initial=0) > 2 ** 29:
-        bad.append("Cbar maximum exceeds 2^29")
+    lim = 2 ** 12 * A.shape[1]                     # eq. (2^29): 2^12 k, <= 2^29 for k <= 2^17
+    if st["rmax"].max(initial=0) > lim or st["cmax"].max(initial=0) > lim or lim >= 2 ** 31:
+        bad.append("Cbar maximum exceeds 2^12 k, or 2^12 k reaches 2^31")
     for t, i in enumerate(rows):
         for h in range(A.shape[1]):
             ref = int(Fraction(float(A[i, h])) * Fraction(2) ** int(st["mu"][t]))
@@ -252,3 +253,42 @@ def pin_log2f_many(fn, d: np.ndarray) -> list:
             if len(bad) > 5:
                 break
     return bad
+
+
+# --------------------------------------------------------------------------
+# k beyond 2^17 (reading R22): inputs that push a residue product past INT32
+# --------------------------------------------------------------------------
+
+
+def fold_inputs(m: int, n: int, k: int, N: int, p: int = 255, seed: int = 0):
+    """Constant rows of A and columns of B whose scaled integers are all
+    congruent to (p - 1)/2 modulo the odd modulus p, so that every term of
+    the residue product modulo p is ((p - 1)/2)^2 and the product reaches
+    k ((p - 1)/2)^2: beyond 2^31 for k >= 2^18 at p = 255.  Built with the
+    oracle's own scaling: with every entry 2^-5 * 47.5 = 1.484375 (Abar = 48,
+    far from a ceiling step) the shift mu is found, then the entry is moved
+    by less than p units of 2^-mu to the nearest integer of that class, which
+    leaves mu', Abar and hence mu unchanged.  Random signs per row / column
+    keep the sign pattern from cancelling.  Needs 2^mu < 2^53 (small N)."""
+    from oracle.constants import constants
+    from oracle.ozaki2 import scaling
+
+    rng = np.random.default_rng(seed)
+    base = 1.484375
+    probeA, probeB = np.full((1, k), base), np.full((k, 1), base)
+    st = scaling(probeA, probeB, N)
+    assert p in constants(N).p
+    want = (p - 1) // 2
+
+    def moved(shift):
+        X = int(Fraction(base) * Fraction(2) ** int(shift))
+        X += (want - X) % p
+        assert X < 2 ** 53
+        return float(Fraction(X) / Fraction(2) ** int(shift))
+
+    a, b = moved(st["mu"][0]), moved(st["nu"][0])
+    sa = rng.choice([-1.0, 1.0], (m, 1))
+    sb = rng.choice([-1.0, 1.0], (1, n))
+    A = np.full((m, k), a) * sa
+    B = np.full((k, n), b) * sb
+    return A, B

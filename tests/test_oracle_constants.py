@@ -142,3 +142,31 @@ def test_log2f_correctly_rounded_against_decimal():
         v = Fraction(Decimal(d).ln() / Decimal(2).ln())
         ulp = Fraction(2) ** (math.floor(math.log2(float(got))) - 23)
         assert abs(v - got) <= ulp / 2
+
+
+@pytest.mark.parametrize("table", ["paper", "optimal"])
+def test_exhaustive_claim_beyond_2_29(table):
+    # Reading R22 (k < 2^19): Cbar can reach 2^31 - 1, so the claim in the
+    # proof of Lemma 0 is needed for e' = log2 cbar up to 31.  Above
+    # cbar = 2^16 it holds for any P': floor(y) <= y with
+    # y = P' - 0.5(1+u)e', and y <= P' - 0.5 e' - 2^-21 once 0.5 u e' >= 2^-21,
+    # i.e. e' >= 16.  Checked on every N at 2^16 samples in (2^29, 2^31) and
+    # the ends of the range, in exact arithmetic near decision boundaries.
+    import mpmath
+    u = 2.0 ** -24
+    for N in ALL_N:
+        pp = float(constants(N, 64, table).Pprime)
+        rng = np.random.default_rng(2000 + N)
+        cb = np.concatenate([rng.integers(2 ** 29 + 1, 2 ** 31, 2 ** 16),
+                             np.array([2 ** 16, 2 ** 29 + 1, 2 ** 31 - 1])])
+        e = np.log2(cb.astype(np.float64))
+        assert np.all(0.5 * u * e >= 2.0 ** -21)
+        y = pp - 0.5 * (1 + u) * e
+        lhs, rhs = np.floor(y), pp - 0.5 * e - 2.0 ** -21
+        near = (np.abs(y - np.rint(y)) < 1e-9) | (np.abs(lhs - rhs) < 1e-9)
+        assert np.all((lhs <= rhs) | near)
+        with mpmath.workprec(200):
+            for v in cb[near]:
+                ev = mpmath.log(int(v), 2)
+                lv = mpmath.floor(mpmath.mpf(pp) - mpmath.mpf(0.5) * (1 + mpmath.mpf(u)) * ev)
+                assert lv <= mpmath.mpf(pp) - ev / 2 - mpmath.mpf(2) ** -21

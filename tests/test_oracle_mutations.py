@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle.ozaki2 as oz
-from pins import all_pins, pin_residues
+from pins import all_pins, fold_inputs, pin_residues
 from workload import gemm_inputs, wrap_inputs
 
 
@@ -113,5 +113,25 @@ def test_saturating_accumulator_is_caught(monkeypatch):
     # modulo 256; the residue pin must see it.
     m_saturate_int32(monkeypatch)
     A, B = wrap_inputs(4, 3, 2 ** 17, seed=1)
+    _, st = oz.os_ii(A, B, 14, stages=True)
+    assert pin_residues(st) != []
+
+
+def test_unchunked_int32_accumulation_is_caught(monkeypatch):
+    # Reading R22: beyond 2^17 of k each residue product is formed in chunks
+    # that stay exact in INT32.  A version that accumulates all of k in one
+    # INT32 value wraps on the fold-stressing inputs (k = 2^18, all residues
+    # mod 255 equal to +-127); the residue pin must see it.
+    real = oz.residue_products
+
+    def unchunked(Ap, Bp, const):
+        out = real(Ap, Bp, const)
+        W = []
+        for l, p in enumerate(const.p):
+            c = oz.wrap_int32(oz.exact_int_matmul(out["Al"][l], out["Bl"][l], 128.0 * 128.0 * Ap.shape[1]))
+            W.append(oz.mod_sym(c, p))
+        return dict(out, W=W)
+    monkeypatch.setattr(oz, "residue_products", unchunked)
+    A, B = fold_inputs(2, 3, 2 ** 18, 14)
     _, st = oz.os_ii(A, B, 14, stages=True)
     assert pin_residues(st) != []

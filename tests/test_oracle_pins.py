@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle.ozaki2 import os_ii
-from pins import (all_pins, pin_accumulation, pin_lemma0_lemma1, pin_residues,
+from pins import (all_pins, fold_inputs, pin_accumulation, pin_lemma0_lemma1, pin_residues,
                   pin_scaling, pin_theorem1)
 from workload import gemm_inputs, wrap_inputs
 
@@ -120,3 +120,37 @@ def test_domain_errors():
     with pytest.raises(ValueError):
         os_ii(A, B, 17)
     assert os_ii(np.zeros((3, 0)), np.zeros((0, 2)), 10).shape == (3, 2)
+
+
+@pytest.mark.parametrize("k", [2 ** 17 + 1, 2 ** 18])
+def test_k_beyond_2_17_pins(k):
+    # Reading R22: k up to 2^19 - 1.  Random inputs: every lemma and
+    # Theorem 1 hold, and Cbar stays below 2^12 k < 2^31.
+    A, B = gemm_inputs(3, 2, k, phi=1.0, seed=k % 1000)
+    _, st = os_ii(A, B, 14, stages=True)
+    assert all_pins(A, B, st) == []
+
+
+def test_k_beyond_2_17_residue_product_past_int32():
+    # Every term of the p = 255 residue product is 127^2, so at k = 2^18 the
+    # product is 2^18 127^2 > 2^31: one INT32 accumulation over all of k
+    # would wrap (and 2^32 = 1 mod 255, so W would be off by one).  The
+    # chunked accumulation of reading R22 keeps W = A'B' mod p exactly.
+    k = 2 ** 18
+    A, B = fold_inputs(2, 3, k, 14)
+    _, st = os_ii(A, B, 14, stages=True)
+    l = list(st["const"].p).index(255)
+    assert np.all(np.abs(st["Al"][l]) == 127) and np.all(np.abs(st["Bl"][l]) == 127)
+    assert np.all(np.abs(st["Cl"][l]) == k * 127 * 127) and k * 127 * 127 >= 2 ** 31
+    assert all_pins(A, B, st) == []
+
+
+def test_largest_k():
+    # k = 2^19 - 1, the largest k accepted: Cbar <= 2^12 k < 2^31.
+    k = 2 ** 19 - 1
+    A, B = gemm_inputs(2, 2, k, phi=0.5, seed=3)
+    _, st = os_ii(A, B, 12, stages=True)
+    assert st["rmax"].max() < 2 ** 31
+    assert pin_residues(st) == [] and pin_lemma0_lemma1(A, B, st) == []
+    with pytest.raises(ValueError):
+        os_ii(np.ones((1, 2 ** 19)), np.ones((2 ** 19, 1)), 12)

@@ -31,6 +31,18 @@ def gemm_inputs(m: int, n: int, k: int, phi: float = 0.5, seed: int = 0,
     return A.astype(dtype), B.astype(dtype)
 
 
+def complex_gemm_inputs(m: int, n: int, k: int, phi: float = 0.5, seed: int = 0,
+                        dtype=np.complex128):
+    """Complex A (m x k) and B (k x n): the real recipe applied to each part.
+    Draw order: A's real part, A's imaginary part, B's real part, B's
+    imaginary part (each uniform array, then normal array).  complex64
+    inputs are the complex128 draws with each part rounded to nearest."""
+    rng = np.random.default_rng(seed)
+    Ar, Ai = draw_matrix(rng, (m, k), phi), draw_matrix(rng, (m, k), phi)
+    Br, Bi = draw_matrix(rng, (k, n), phi), draw_matrix(rng, (k, n), phi)
+    return (Ar + 1j * Ai).astype(dtype), (Br + 1j * Bi).astype(dtype)
+
+
 def batched_shapes(count: int = 512, lo: int = 64, hi: int = 2048, seed: int = 0):
     """(m, n, k) per problem, each log-uniform in [lo, hi], drawn in the order
     m, n, k per problem before any matrix.  Returns (rng, shapes) so that the
