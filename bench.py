@@ -89,6 +89,9 @@ def extras_measurement(torch, oz) -> dict:
         t0 = time.perf_counter()
         rc, N = oz.ozaki2_required_moduli(64, n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, 1e-15)
         plan_ms = (time.perf_counter() - t0) * 1e3
+        with oz.moduli_table(oz.MODULI_OPTIMAL):
+            rc_opt, N_opt = oz.ozaki2_required_moduli(64, n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n,
+                                                      1e-15)
         t0 = time.perf_counter()
         oz.ozaki2_required_moduli(64, n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, 1e-15)
         plan_ms = min(plan_ms, (time.perf_counter() - t0) * 1e3)
@@ -106,11 +109,13 @@ def extras_measurement(torch, oz) -> dict:
         nat_err = ex.rel_error(Cn[torch.as_tensor(rows, device=dev)][:, torch.as_tensor(cols, device=dev)].cpu().numpy())
         out["phi_sweep_4096"].append({
             "phi": phi, "N": N, "reachable": rc == oz.OK, "plan_ms": round(plan_ms, 3),
+            "N_optimal_table": N_opt, "reachable_optimal_table": rc_opt == oz.OK,
             "ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2),
             "rel_err_sampled": err, "native_ms": round(nat_ms, 4), "native_rel_err_sampled": nat_err})
         del dA, dB, Acm, Bcm, Ccm, Cn
         torch.cuda.empty_cache()
     out["certified_4096"] = certified_measurement(torch, oz, rng)
+    out["complex_4096"] = complex_measurement(torch, oz, rng)
     # FP32 16384^3
     n = 16384
     A, B = gemm_inputs(n, n, n, phi=0.5, seed=0, dtype=np.float32)
@@ -140,6 +145,55 @@ def extras_measurement(torch, oz) -> dict:
                          "native_tflops": round(2.0 * n ** 3 / (nat_ms * 1e-3) / 1e12, 2),
                          "native_rel_err_sampled": nat_err, "emulated": res, "matched_N": matched}
     return out
+
+
+def complex_measurement(torch, oz, rng) -> dict:
+    """Complex FP64 4096^3 (ZGEMM emulation through the real embedding)
+    against native complex128 matmul: time, effective TFLOPS (8 m n k / t,
+    the real flops of a complex product) and sampled error relative to
+    (|Ar|+|Ai|)(|Br|+|Bi|) -- the real embedding's |A||B| -- for N = 14..17,
+    and the smallest N matching the native error."""
+    from workload import complex_gemm_inputs
+    from workload.reference import ExactSamples
+
+    dev = torch.device("cuda:0")
+    n = 4096
+    A, B = complex_gemm_inputs(n, n, n, phi=0.5, seed=0)
+    rows = np.sort(rng.choice(n, 8, replace=False))
+    cols = np.sort(rng.choice(n, 8, replace=False))
+    # exact samples of the real embedding: rows of Re and of Im
+    Ahat_rows = np.block([[A.real[rows], -A.imag[rows]], [A.imag[rows], A.real[rows]]])
+    Bhat = np.vstack([B.real, B.imag])
+    ex = ExactSamples(Ahat_rows, Bhat, np.arange(2 * len(rows)), cols)
+    dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    del A, B, Bhat
+    Acm, Bcm = oz.col_major(dA), oz.col_major(dB)
+    Ccm = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    ri, ci = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
+
+    def sampled(Ct):
+        sub = Ct[ri][:, ci].cpu().numpy()
+        return ex.rel_error(np.vstack([sub.real, sub.imag]))
+
+    flops = 8.0 * n ** 3
+    nat_ms = _time_ms(torch, lambda: torch.matmul(dA, dB), 3)
+    nat_err = sampled(torch.matmul(dA, dB))
+    res = {}
+    for N in (14, 15, 16, 17):
+        def emu():
+            r = oz.ozaki2_zgemm(n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, Ccm.data_ptr(), n, N)
+            if r != oz.OK:
+                raise oz.Ozaki2Error("ozaki2_zgemm", r)
+
+        ms = _time_ms(torch, emu, 3)
+        res[str(N)] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                       "rel_err_sampled": sampled(Ccm.t())}
+    matched = next((int(k) for k, v in res.items() if v["rel_err_sampled"] <= nat_err), None)
+    del dA, dB, Acm, Bcm, Ccm
+    torch.cuda.empty_cache()
+    return {"workload": "complex FP64 4096^3, each part (U-0.5)exp(0.5 Z), seed 0",
+            "native_ms": round(nat_ms, 3), "native_tflops": round(flops / (nat_ms * 1e-3) / 1e12, 2),
+            "native_rel_err_sampled": nat_err, "emulated": res, "matched_N": matched}
 
 
 def certified_measurement(torch, oz, rng) -> list:
@@ -503,6 +557,14 @@ def main():
         "phases_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
     }
     out["int8_fraction_whole_call"] = round((N + 1) * flops / (ms * 1e-3) / 1e12 / PEAK_INT8_TOPS, 4)
+    # The per-N moduli of largest product (Section 3.1) at the matched N and
+    # one below it, outside the timed region.
+    opt = {}
+    with oz.moduli_table(oz.MODULI_OPTIMAL):
+        for cand in (N - 1, N):
+            emulate(cand)
+            opt[str(cand)] = sampled_error(Ccm.t())
+    out["optimal_table_rel_err_sampled"] = opt
     out["memory_phases"] = memory_phases(torch, dev, phase_ms, m, n, k, N, 8)
     out["mall_flushed"] = flushed_timing(torch, dev, emulate, N, max(args.steps, 10))
     # The N that Theorem 1's bound demands for 1e-15 (reading R16), planned
@@ -512,7 +574,10 @@ def main():
         t_plan = time.perf_counter()
         rc_b, N_b = oz.ozaki2_required_moduli(64, m, n, k, Acm.data_ptr(), m, Bcm.data_ptr(), k, 1e-15)
         times.append((time.perf_counter() - t_plan) * 1e3)
-    out["bound_N_1e-15"] = {"N": N_b, "reachable": rc_b == oz.OK, "plan_ms": round(min(times), 3)}
+    with oz.moduli_table(oz.MODULI_OPTIMAL):
+        rc_o, N_o = oz.ozaki2_required_moduli(64, m, n, k, Acm.data_ptr(), m, Bcm.data_ptr(), k, 1e-15)
+    out["bound_N_1e-15"] = {"N": N_b, "reachable": rc_b == oz.OK, "plan_ms": round(min(times), 3),
+                            "N_optimal_table": N_o, "reachable_optimal_table": rc_o == oz.OK}
     del Acm, Bcm, Ccm, dA, dB
     torch.cuda.empty_cache()
     if not args.no_batched:

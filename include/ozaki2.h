@@ -50,7 +50,8 @@ typedef enum {
                                   ldb < max(1,k); ldc < max(1,m); NULL pointer for a matrix
                                   with a nonzero extent                                      */
   OZAKI2_ERR_N_RANGE = -2,     /* N outside [2, 49] (FP64) or [2, 16] (FP32)                  */
-  OZAKI2_ERR_K_RANGE = -3,     /* k > 2^17 (the analysis of Sections 3-4 assumes k <= 2^17)   */
+  OZAKI2_ERR_K_RANGE = -3,     /* k >= 2^19 (Sections 3-4 assume k <= 2^17; up to 2^19 - 1
+                                  the library keeps every step exact, see ozaki2_gemm)        */
   OZAKI2_ERR_WORKSPACE = -4,   /* caller-installed workspace smaller than required            */
   OZAKI2_ERR_UNREACHABLE = -5, /* required_moduli: no admissible N meets eps                  */
   OZAKI2_ERR_NONFINITE = -6,   /* an input entry was Inf or NaN (reported by sync_status)     */
@@ -63,6 +64,11 @@ typedef enum {
  *   m, n, k : sizes; A is m x k, B is k x n, C is m x n (column-major).
  *   N       : number of moduli, 2 <= N <= 49 (Algorithms 1-3 preconditions).
  * Accuracy: |AB - C| obeys Theorem 1 (eq. thm:err-1) entrywise.
+ * k: 0 <= k < 2^19.  The paper assumes k <= 2^17; above it, Cbar = Abar Bbar
+ * (at most 2^12 k) still fits INT32 exactly, and each residue product is
+ * reduced mod p_l after every 2^17 of k, so W_l = mod(A'_l B'_l, p_l) stays
+ * exact and Lemmas 0-4 and Theorem 1 hold as stated (Lemma 1's proof with
+ * log2 Cbar < 31 in place of 29).
  * k == 0 writes C = 0; m == 0 or n == 0 does nothing.
  * If an input entry is non-finite every entry of C is set to NaN and
  * ozaki2_sync_status later returns OZAKI2_ERR_NONFINITE.
@@ -80,6 +86,34 @@ int ozaki2_gemm(int m, int n, int k, const double *A, int lda, const double *B, 
  */
 int ozaki2_sgemm(int m, int n, int k, const float *A, int lda, const float *B, int ldb,
                  float *C, int ldc, int N);
+
+/*
+ * ozaki2_zgemm - complex FP64 C := A*B (ZGEMM emulation); ozaki2_cgemm the
+ * complex FP32 form (b = 32, N <= 16).  Sections 1.1 and 7 name complex
+ * emulation and leave its analysis to future work; here the real method of
+ * Algorithm 1 runs unchanged on the real embedding
+ *     [[Ar, -Ai], [Ai, Ar]] (2m x 2k)  times  [[Br], [Bi]] (2k x n),
+ * whose product holds Re(AB) in its first m rows and Im(AB) in the rest, so
+ * Lemmas 0-4 and Theorem 1 bound the error of each real and imaginary part
+ * as for a real product with inner dimension 2k (four real residue products
+ * of the complex sizes per modulus).  Each row of the embedding gets its own
+ * shift: the real and imaginary parts of a row of C are scaled separately.
+ *   A, B, C : DEVICE pointers to interleaved (re, im) pairs (C99 complex /
+ *             std::complex layout), column-major; lda, ldb, ldc count complex
+ *             elements (lda >= max(1,m), ldb >= max(1,k), ldc >= max(1,m),
+ *             ldc < 2^30).
+ *   k       : 0 <= k < 2^18 (the real limit applies to 2k).
+ *   N       : as ozaki2_gemm / ozaki2_sgemm.
+ * Workspace: ozaki2_complex_workspace_bytes (library-managed or installed).
+ * Returns and reports like ozaki2_gemm.
+ */
+int ozaki2_zgemm(int m, int n, int k, const double *A, int lda, const double *B, int ldb,
+                 double *C, int ldc, int N);
+int ozaki2_cgemm(int m, int n, int k, const float *A, int lda, const float *B, int ldb, float *C,
+                 int ldc, int N);
+/* Bytes of device workspace ozaki2_zgemm (prec 64) / ozaki2_cgemm (prec 32)
+ * needs; 0 for arguments they would reject and for m, n or k == 0. */
+size_t ozaki2_complex_workspace_bytes(int prec, int m, int n, int k, int N);
 
 /*
  * ozaki2_required_moduli - smallest N for which the N-dependent part of the
@@ -135,6 +169,30 @@ size_t ozaki2_certified_workspace_bytes(int prec, int m, int n, int k, int N);
 /* Work queue: every later call on this host thread enqueues on `stream`
  * (a hipStream_t; NULL = the null stream). */
 int ozaki2_set_stream(void *stream);
+
+/*
+ * ozaki2_set_moduli_table - the moduli every later call on this host thread
+ * uses (Section 3.1, Determination of Constants):
+ *   OZAKI2_MODULI_PAPER   (default) the first N entries of the fixed list of
+ *                         49 pairwise coprime moduli <= 256 (eq. p_list);
+ *   OZAKI2_MODULI_OPTIMAL for each N, the N pairwise coprime integers in
+ *                         [2, 256] of largest product P (Section 3.1 notes
+ *                         that this set depends on N -- 255 leaves it from
+ *                         N = 7 on -- and can be tabulated per N), in
+ *                         descending order.
+ * Every constant of Section 3.1 (P, q_l, s_l1, s_l2, P1, P2, P_inv, P') and
+ * of the Theorem 1 bounds follows the table.  Returns OZAKI2_OK or
+ * OZAKI2_ERR_INVALID_ARG for an unknown table.
+ * ozaki2_moduli writes the N moduli of `table` to p_out (HOST array of N
+ * ints); OZAKI2_ERR_N_RANGE for N outside [2, 49].
+ * ozaki2_debug_constants writes, for parity checks against the CPU oracle,
+ * the FP64 values P1, P2, P_inv, P', c, s_1..s_N(1), s_1..s_N(2) of (prec,
+ * table, N) to out (HOST array of 5 + 2N doubles).
+ */
+enum { OZAKI2_MODULI_PAPER = 0, OZAKI2_MODULI_OPTIMAL = 1 };
+int ozaki2_set_moduli_table(int table);
+int ozaki2_moduli(int table, int N, int *p_out);
+int ozaki2_debug_constants(int prec, int table, int N, double *out);
 
 /* Bytes of device workspace a call with these sizes needs (prec 64 or 32);
  * 0 for arguments the call itself would reject. */
@@ -213,7 +271,9 @@ size_t ozaki2_batched_workspace_bytes(int prec, int count, const int *mnkN);
  *   out[10] float [m+n]        log2f values e (rows) then f (columns)
  *   out[11] int32 [N][n][m]    C'_l = A'_l B'_l as INT32 (Algorithm 3), from
  *                              the residue-product kernel with the tile
- *                              choice of the call (two's-complement wrap)
+ *                              choice of the call (two's-complement wrap);
+ *                              for k > 2^17 the accumulator as it ends after
+ *                              its reductions mod p_l, congruent to C'_l
  *   out[12] double [n][m]      C'(1) (Algorithm 3 / Lemma 2)
  *   out[13] double [n][m]      C'(2) (0 for prec 32)
  *   out[14] double [n][m]      Q     (Lemma 3)

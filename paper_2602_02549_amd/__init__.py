@@ -40,7 +40,13 @@ _SIGS = {
     "ozaki2_gemm_certified": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int,
                                _c_double, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)], _c_int),
     "ozaki2_certified_workspace_bytes": ([_c_int, _c_int, _c_int, _c_int, _c_int], _c_size),
+    "ozaki2_zgemm": ([_c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int], _c_int),
+    "ozaki2_cgemm": ([_c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int], _c_int),
+    "ozaki2_complex_workspace_bytes": ([_c_int, _c_int, _c_int, _c_int, _c_int], _c_size),
     "ozaki2_set_stream": ([_c_ptr], _c_int),
+    "ozaki2_set_moduli_table": ([_c_int], _c_int),
+    "ozaki2_moduli": ([_c_int, _c_int, ctypes.POINTER(_c_int)], _c_int),
+    "ozaki2_debug_constants": ([_c_int, _c_int, _c_int, ctypes.POINTER(_c_double)], _c_int),
     "ozaki2_workspace_bytes": ([_c_int, _c_int, _c_int, _c_int, _c_int], _c_size),
     "ozaki2_set_workspace": ([_c_ptr, _c_size], _c_int),
     "ozaki2_sync_status": ([], _c_int),
@@ -115,8 +121,62 @@ def ozaki2_certified_workspace_bytes(prec, m, n, k, N):
     return _call("ozaki2_certified_workspace_bytes", prec, m, n, k, N)
 
 
+def ozaki2_zgemm(m, n, k, A, lda, B, ldb, C, ldc, N):
+    return _call("ozaki2_zgemm", m, n, k, A, lda, B, ldb, C, ldc, N)
+
+
+def ozaki2_cgemm(m, n, k, A, lda, B, ldb, C, ldc, N):
+    return _call("ozaki2_cgemm", m, n, k, A, lda, B, ldb, C, ldc, N)
+
+
+def ozaki2_complex_workspace_bytes(prec, m, n, k, N):
+    return _call("ozaki2_complex_workspace_bytes", prec, m, n, k, N)
+
+
 def ozaki2_set_stream(stream):
     return _call("ozaki2_set_stream", stream)
+
+
+MODULI_PAPER, MODULI_OPTIMAL = 0, 1
+
+
+def ozaki2_set_moduli_table(table):
+    return _call("ozaki2_set_moduli_table", table)
+
+
+def ozaki2_moduli(table, N):
+    """(rc, list of the N moduli)."""
+    out = (_c_int * max(N, 1))()
+    rc = _call("ozaki2_moduli", table, N, out)
+    return rc, list(out)[:N] if rc == OK else []
+
+
+def ozaki2_debug_constants(prec, table, N):
+    """(rc, dict with P1, P2, Pinv, Pprime, c, s1, s2)."""
+    out = (_c_double * (5 + 2 * max(N, 0)))()
+    rc = _call("ozaki2_debug_constants", prec, table, N, out)
+    if rc != OK:
+        return rc, None
+    v = list(out)
+    return rc, {"P1": v[0], "P2": v[1], "Pinv": v[2], "Pprime": v[3], "c": v[4],
+                "s1": v[5:5 + N], "s2": v[5 + N:5 + 2 * N]}
+
+
+class moduli_table:
+    """Context manager: calls on this thread use `table` inside the block."""
+
+    def __init__(self, table):
+        self.table = table
+
+    def __enter__(self):
+        rc = ozaki2_set_moduli_table(self.table)
+        if rc != OK:
+            raise Ozaki2Error("ozaki2_set_moduli_table", rc)
+        return self
+
+    def __exit__(self, *exc):
+        ozaki2_set_moduli_table(MODULI_PAPER)
+        return False
 
 
 def ozaki2_workspace_bytes(prec, m, n, k, N):
@@ -230,6 +290,23 @@ def gemm(A, B, N: int, out=None):
     rc = f(m, n, k, Acm.data_ptr(), max(m, 1), Bcm.data_ptr(), max(k, 1), Ccm.data_ptr(), max(m, 1), N)
     if rc != OK:
         raise Ozaki2Error("ozaki2_gemm", rc)
+    return Ccm.t()
+
+
+def zgemm(A, B, N: int):
+    """C = A @ B for complex CUDA tensors (complex128: ozaki2_zgemm,
+    complex64: ozaki2_cgemm).  Returns C (m x n), a transposed view of a
+    column-major buffer."""
+    torch = _torch()
+    m, k = A.shape
+    n = B.shape[1]
+    Acm, Bcm = col_major(A), col_major(B)
+    Ccm = torch.empty((n, m), dtype=A.dtype, device=A.device)
+    _set_current_stream()
+    f = ozaki2_zgemm if A.dtype == torch.complex128 else ozaki2_cgemm
+    rc = f(m, n, k, Acm.data_ptr(), max(m, 1), Bcm.data_ptr(), max(k, 1), Ccm.data_ptr(), max(m, 1), N)
+    if rc != OK:
+        raise Ozaki2Error("ozaki2_zgemm", rc)
     return Ccm.t()
 
 

@@ -23,6 +23,7 @@ using namespace oz2;
 namespace {
 
 thread_local hipStream_t g_stream = nullptr;
+thread_local int g_table = kTablePaper;   // moduli table of this host thread's calls
 
 constexpr int kDebugOutputs = 16;   // entries of ozaki2_debug_stages' output list
 
@@ -35,7 +36,7 @@ struct DeviceState {
   size_t user_bytes = 0;
   uint64_t ws_gen = 1;         // bumped whenever the workspace address may change
   int* status = nullptr;       // sticky data-dependent status word
-  CrtConsts* ctab[2] = {nullptr, nullptr};  // device tables of CrtConsts by N (b = 64, 32)
+  CrtConsts* ctab[2][2] = {};  // device tables of CrtConsts by N: [moduli table][b = 64, 32]
   hipStream_t capture = nullptr;            // library stream used only for graph capture
   std::vector<std::shared_ptr<BatchEntry>> batches;  // captured batches, oldest first
 };
@@ -43,9 +44,9 @@ std::mutex g_mu;
 // Never destroyed: its entries own device resources, and HIP must not be
 // called from static destructors at process exit.
 std::map<int, DeviceState>& g_dev = *new std::map<int, DeviceState>;
-std::map<int, CrtConsts> g_consts;  // key: N * 100 + b
-PlanCoef g_plan[2];                 // planner coefficients for b = 64, 32
-bool g_plan_ok[2] = {false, false};
+std::map<int, CrtConsts> g_consts;  // key: (table * 100 + N) * 100 + b
+PlanCoef g_plan[2][2];              // planner coefficients: [moduli table][b = 64, 32]
+bool g_plan_ok[2][2] = {};
 
 // ---------------------------------------------------------------------------
 // profiling (HIP events around each phase on the library stream)
@@ -165,13 +166,15 @@ int check_N(int N, int b) {
   return OZAKI2_OK;
 }
 
+// Constants of the calling thread's moduli table.
 int get_consts(int N, int b, CrtConsts* out) {
+  const int table = g_table;
   std::lock_guard<std::mutex> lk(g_mu);
-  int key = N * 100 + b;
+  int key = (table * 100 + N) * 100 + b;
   auto it = g_consts.find(key);
   if (it == g_consts.end()) {
     CrtConsts cc;
-    if (!build_consts(N, b, &cc)) return OZAKI2_ERR_INIT;
+    if (!build_consts(N, b, table, &cc)) return OZAKI2_ERR_INIT;
     it = g_consts.emplace(key, cc).first;
   }
   *out = it->second;
@@ -253,13 +256,14 @@ PlanLayout plan_layout(int m, int n, int k) {
 }
 
 int get_plan_coef(int b, PlanCoef* out) {
+  const int table = g_table;
   std::lock_guard<std::mutex> lk(g_mu);
   const int i = b == 64 ? 0 : 1;
-  if (!g_plan_ok[i]) {
-    if (!build_plan_coef(b, &g_plan[i])) return OZAKI2_ERR_INIT;
-    g_plan_ok[i] = true;
+  if (!g_plan_ok[table][i]) {
+    if (!build_plan_coef(b, table, &g_plan[table][i])) return OZAKI2_ERR_INIT;
+    g_plan_ok[table][i] = true;
   }
-  *out = g_plan[i];
+  *out = g_plan[table][i];
   return OZAKI2_OK;
 }
 
@@ -443,6 +447,69 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
   return hipStreamSynchronize(s) == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
 }
 
+// Complex C = AB (reading R23): the real Algorithm 1 on the embedding
+// Ahat = [[Ar, -Ai], [Ai, Ar]] (2m x 2k), Bhat = [[Br], [Bi]] (2k x n),
+// whose product holds Re AB in rows 1..m and Im AB in rows m+1..2m.  The
+// workspace holds Ahat, Bhat and the 2m x n real result, then the real
+// layout of the 2m x n x 2k problem.
+struct ZLayout {
+  size_t Ah, Bh, Ch, real, total;
+  Layout L;
+};
+
+ZLayout zlayout(int m, int n, int k, int N, size_t s) {
+  ZLayout Z;
+  Z.Ah = 0;
+  Z.Bh = rup(Z.Ah + s * 4 * (size_t)m * k, 256);
+  Z.Ch = rup(Z.Bh + s * 2 * (size_t)k * n, 256);
+  Z.real = rup(Z.Ch + s * 2 * (size_t)m * n, 256);
+  Z.L = layout(2 * m, n, 2 * k, N, single_row_pad(2 * m, n, N));
+  Z.total = Z.real + Z.L.total;
+  return Z;
+}
+
+// Argument checks of the complex calls (leading dimensions in complex
+// elements); the embedded problem must be a valid real one.
+int check_complex_args(int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+                       const void* C, int ldc) {
+  if (m < 0 || n < 0 || k < 0 || m > kMaxDim / 2 || n > kMaxDim) return OZAKI2_ERR_INVALID_ARG;
+  if (lda < (m > 1 ? m : 1) || ldb < (k > 1 ? k : 1) || ldc < (m > 1 ? m : 1))
+    return OZAKI2_ERR_INVALID_ARG;
+  if (ldc > INT32_MAX / 2) return OZAKI2_ERR_INVALID_ARG;
+  if ((size_t)m * k > 0 && !A) return OZAKI2_ERR_INVALID_ARG;
+  if ((size_t)k * n > 0 && !B) return OZAKI2_ERR_INVALID_ARG;
+  if ((size_t)m * n > 0 && !C) return OZAKI2_ERR_INVALID_ARG;
+  if (k > kMaxK / 2) return OZAKI2_ERR_K_RANGE;
+  return OZAKI2_OK;
+}
+
+int zgemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+               void* C, int ldc, int N) {
+  const int b = pr == Prec::F64 ? 64 : 32;
+  int rc = check_complex_args(m, n, k, A, lda, B, ldb, C, ldc);
+  if (rc) return rc;
+  if ((rc = check_N(N, b))) return rc;
+  if (m == 0 || n == 0) return OZAKI2_OK;
+  hipStream_t s = g_stream;
+  if (k == 0) {  // C = 0: the interleaved pairs as a 2m x n real matrix
+    launch_fill_zero(s, pr, C, 2 * ldc, 2 * m, n);
+    return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
+  }
+  CrtConsts cc;
+  if ((rc = get_consts(N, b, &cc))) return rc;
+  const size_t es = pr == Prec::F64 ? 8 : 4;
+  const ZLayout Z = zlayout(m, n, k, N, es);
+  char* ws;
+  int* status;
+  if ((rc = get_workspace(Z.total, &ws, &status))) return rc;
+  launch_embed_complex(s, pr, A, lda, B, ldb, m, n, k, ws + Z.Ah, ws + Z.Bh);
+  rc = run_pipeline(pr, 2 * m, n, 2 * k, ws + Z.Ah, 2 * m, ws + Z.Bh, 2 * k, ws + Z.Ch, 2 * m, cc,
+                    Z.L, ws + Z.real, status, s, false);
+  if (rc) return rc;
+  launch_interleave_complex(s, pr, ws + Z.Ch, m, n, C, ldc);
+  return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
+}
+
 }  // namespace
 
 namespace oz2 {
@@ -531,7 +598,7 @@ int get_ctab(int b, CrtConsts** out) {
   const int nmax = b == 64 ? kMaxModuli : 16;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    CrtConsts* t = g_dev[dev].ctab[b == 64 ? 0 : 1];
+    CrtConsts* t = g_dev[dev].ctab[g_table][b == 64 ? 0 : 1];
     if (t) {
       *out = t;
       return OZAKI2_OK;
@@ -549,7 +616,7 @@ int get_ctab(int b, CrtConsts** out) {
       hipSuccess)
     return OZAKI2_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_mu);
-  CrtConsts*& slot = g_dev[dev].ctab[b == 64 ? 0 : 1];
+  CrtConsts*& slot = g_dev[dev].ctab[g_table][b == 64 ? 0 : 1];
   if (slot) {
     (void)hipFree(t);   // another thread got there first
   } else {
@@ -735,6 +802,7 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
   std::vector<int64_t> key;
   key.reserve(4 + 10 * (size_t)count);
   key.push_back(b);
+  key.push_back(g_table);
   key.push_back((int64_t)(intptr_t)ws);
   key.push_back((int64_t)gen);
   key.push_back(forced);
@@ -863,8 +931,60 @@ int ozaki2_sgemm(int m, int n, int k, const float* A, int lda, const float* B, i
   return gemm_impl(Prec::F32, m, n, k, A, lda, B, ldb, C, ldc, N, nullptr);
 }
 
+int ozaki2_zgemm(int m, int n, int k, const double* A, int lda, const double* B, int ldb,
+                 double* C, int ldc, int N) {
+  return zgemm_impl(Prec::F64, m, n, k, A, lda, B, ldb, C, ldc, N);
+}
+
+int ozaki2_cgemm(int m, int n, int k, const float* A, int lda, const float* B, int ldb, float* C,
+                 int ldc, int N) {
+  return zgemm_impl(Prec::F32, m, n, k, A, lda, B, ldb, C, ldc, N);
+}
+
+size_t ozaki2_complex_workspace_bytes(int prec, int m, int n, int k, int N) {
+  if ((prec != 64 && prec != 32) || m < 0 || n < 0 || k < 0) return 0;
+  if (m > kMaxDim / 2 || n > kMaxDim || k > kMaxK / 2 || check_N(N, prec) != OZAKI2_OK) return 0;
+  if (m == 0 || n == 0 || k == 0) return 0;
+  return zlayout(m, n, k, N, prec == 64 ? 8 : 4).total;
+}
+
 int ozaki2_set_stream(void* stream) {
   g_stream = (hipStream_t)stream;
+  return OZAKI2_OK;
+}
+
+int ozaki2_set_moduli_table(int table) {
+  if (table != OZAKI2_MODULI_PAPER && table != OZAKI2_MODULI_OPTIMAL) return OZAKI2_ERR_INVALID_ARG;
+  g_table = table == OZAKI2_MODULI_PAPER ? kTablePaper : kTableOptimal;
+  return OZAKI2_OK;
+}
+
+int ozaki2_moduli(int table, int N, int* p_out) {
+  if ((table != OZAKI2_MODULI_PAPER && table != OZAKI2_MODULI_OPTIMAL) || !p_out)
+    return OZAKI2_ERR_INVALID_ARG;
+  if (N < 2 || N > kMaxModuli) return OZAKI2_ERR_N_RANGE;
+  return moduli_of(table == OZAKI2_MODULI_PAPER ? kTablePaper : kTableOptimal, N, p_out)
+             ? OZAKI2_OK
+             : OZAKI2_ERR_INIT;
+}
+
+int ozaki2_debug_constants(int prec, int table, int N, double* out) {
+  if ((prec != 64 && prec != 32) || !out) return OZAKI2_ERR_INVALID_ARG;
+  if (table != OZAKI2_MODULI_PAPER && table != OZAKI2_MODULI_OPTIMAL) return OZAKI2_ERR_INVALID_ARG;
+  int rc = check_N(N, prec);
+  if (rc) return rc;
+  CrtConsts cc;
+  if (!build_consts(N, prec, table == OZAKI2_MODULI_PAPER ? kTablePaper : kTableOptimal, &cc))
+    return OZAKI2_ERR_INIT;
+  out[0] = cc.P1;
+  out[1] = cc.P2;
+  out[2] = cc.Pinv;
+  out[3] = cc.Pprime;
+  out[4] = cc.c;
+  for (int l = 0; l < N; ++l) {
+    out[5 + l] = cc.s1[l];
+    out[5 + N + l] = cc.s2[l];
+  }
   return OZAKI2_OK;
 }
 

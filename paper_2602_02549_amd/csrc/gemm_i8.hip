@@ -46,6 +46,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
 
 constexpr int kXcds = 8;
+constexpr int kFoldGroups = (1 << 17) / 128;   // 128-k groups per 2^17 of k
 
 // mod(x, p) of an INT32 product as an INT8 value (Section 1.2), odd p: the
 // FP64 quotient x * (1/p) is within 2^-25 of x/p, which is never within
@@ -352,9 +353,30 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
     }
     if constexpr (TX * TY > TX + TY) __builtin_amdgcn_sched_group_barrier(0x008, TX * TY - (TX + TY), 0);
   };
+  // Beyond 2^17 of k (residue products, EPI 0 and its INT32 dump EPI 4) the
+  // accumulators are reduced mod p_z (odd p) after every 2^17 of k: a chunk
+  // adds at most 127^2 2^17 < 2^31 - 127 in magnitude to a reduced value, so
+  // every partial sum stays exact in INT32 and the result is congruent to
+  // C'_l mod p_z.  For p = 256 the two's-complement wrap is already exact
+  // mod 256.  The inner loop is the same for every chunk.
+  constexpr bool kFold = EPI == 0 || EPI == 4;
+  const int chunk = kFold ? kFoldGroups : NG;
+  auto fold = [&]() {
+    const int p = cc.p[z];
+    if (p == 256) return;
+    const double pd = (double)p, pinv = cc.pinv[z];
+#pragma unroll
+    for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+      for (int ty = 0; ty < TY; ++ty)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[tx][ty][r] = mod_odd(acc[tx][ty][r], pd, pinv);
+  };
   issue_x(lds, z, 0);
   issue_y(lds, z, 0);
-  for (int gi = 0; gi < NG; ++gi) {
+  for (int g0 = 0; g0 < NG; g0 += chunk) {
+  const int g1 = min(NG, g0 + chunk);
+  for (int gi = g0; gi < g1; ++gi) {
     int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
     int8_t* const next = lds + ((gi + 1) & 1) * GROUP_BYTES;
     wait_vmcnt<0>();
@@ -382,6 +404,10 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
     interleave();
     __builtin_amdgcn_sched_barrier(0);
     mfmas(a1, b1);
+  }
+  if constexpr (kFold) {
+    if (g1 < NG) fold();
+  }
   }
   finish();
 }

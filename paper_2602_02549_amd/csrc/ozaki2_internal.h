@@ -9,7 +9,9 @@
 namespace oz2 {
 
 constexpr int kMaxModuli = 49;   // Section 3.1: p_l <= 256 pairwise coprime => N <= 49
-constexpr int kMaxK = 1 << 17;   // Section 3: k <= 2^17
+// k < 2^19: Section 3 assumes k <= 2^17; beyond it Cbar <= 2^12 k stays below
+// 2^31 and the residue products are reduced mod p_l every 2^17 of k.
+constexpr int kMaxK = (1 << 19) - 1;
 constexpr int kRowPad = 256;     // m and n are padded to this multiple in the workspace
 constexpr int kMaxDim = 0x7FFFFF00; // largest m, n whose padding to kRowPad fits in int
 constexpr int kKPad = 128;       // k is padded to this multiple (bytes of INT8 per row)
@@ -21,6 +23,7 @@ constexpr int kCrtRows = 4;      // CRT: consecutive rows per thread (256 thread
 struct CrtConsts {
   int N;
   int b;            // 64 or 32
+  int table;        // moduli: kTablePaper or kTableOptimal
   int nsteps;       // exact-reduction steps for |A'| < 2^(6 + floor(P'))
   int nlimbs;       // 2 or 3: residues from limbs of A' (0: use nsteps)
   float Pprime;     // P' = single_down(log2(P-1)/2 - 0.5)
@@ -33,9 +36,15 @@ struct CrtConsts {
   double s2[kMaxModuli];    // s_l2 (0 for b = 32)
 };
 
+// Moduli tables (Section 3.1): the first N of the paper's fixed list, or the
+// N pairwise coprime integers <= 256 of largest product (descending).
+constexpr int kTablePaper = 0;
+constexpr int kTableOptimal = 1;
+bool moduli_of(int table, int N, int* p);
+
 // Host-side tables (tables.cpp).  Returns false if a constant could not be
 // established (e.g. P' too close to the FP32 grid for the host's precision).
-bool build_consts(int N, int b, CrtConsts* out);
+bool build_consts(int N, int b, int table, CrtConsts* out);
 // N-dependent coefficients of the planner bound for every N in [2, 49]:
 //   t(N) = 1/sqrt(32 (P-1)), tt(N) = t^2, extra(N) = (r_b(N) - r_rnd) t^2,
 //   rnd(N) = r_rnd t^2 (the N-independent output rounding part).
@@ -47,7 +56,7 @@ struct PlanCoef {
   double rconst[kMaxModuli + 1];  // R_const of Lemma 4
   double rel[kMaxModuli + 1];     // R_rel t^2 / (1 - R_rel)
 };
-bool build_plan_coef(int b, PlanCoef* out);
+bool build_plan_coef(int b, int table, PlanCoef* out);
 
 // The a-posteriori est1 of Theorem 1 at one N, in the planner's factored form
 // (passed by value to the certification kernel).
@@ -247,6 +256,16 @@ void launch_crt_debug(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ld
 void launch_fill_zero(hipStream_t s, Prec pr, void* C, int ldc, int m, int n);
 // Folds the per-call non-finite flag into the sticky status word.
 void launch_or_status(hipStream_t s, const int* flag, int* status);
+
+// complex.hip: the real embedding of a complex product (interleaved (re, im)
+// column-major inputs; leading dimensions in complex elements) into
+// Ahat = [[Ar, -Ai], [Ai, Ar]] (2m x 2k, ld 2m) and Bhat = [[Br], [Bi]]
+// (2k x n, ld 2k), and the 2m x n real result (ld 2m) back into the
+// interleaved complex C.
+void launch_embed_complex(hipStream_t s, Prec pr, const void* A, int lda, const void* B, int ldb,
+                          int m, int n, int k, void* Ah, void* Bh);
+void launch_interleave_complex(hipStream_t s, Prec pr, const void* Ch, int m, int n, void* C,
+                               int ldc);
 
 // api.cpp: Algorithm 1 for one problem on a workspace of `cap` bytes that
 // `get` supplies, with its sticky status word; checks the arguments and the

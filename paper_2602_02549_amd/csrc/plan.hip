@@ -19,8 +19,8 @@
 namespace oz2 {
 namespace {
 
-// Upward factors: FP64 sums of at most 2^17 nonnegative terms are within
-// 2^-36 (relative) of the exact sum; one correctly rounded sqrt within 2^-53.
+// Upward factors: FP64 sums of fewer than 2^19 nonnegative terms are within
+// 2^-34 (relative) of the exact sum; one correctly rounded sqrt within 2^-53.
 constexpr double kSumUp = 1.0 + 0x1p-30;
 constexpr double kSqrtUp = 1.0 + 0x1p-50;
 constexpr double kTUp = 1.0 + 0x1p-40;   // a few roundings in T itself

@@ -5,11 +5,14 @@
 // built with a small fixed-width unsigned big integer and correct rounding
 // to FP64; P' and the constant c use 64-bit-mantissa long double arithmetic
 // followed by an explicit round-down to FP32 and a margin check.
+#include <algorithm>
 #include <cfloat>
 #include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <functional>
+#include <vector>
 
 #include "ozaki2_internal.h"
 
@@ -17,7 +20,7 @@ namespace oz2 {
 namespace {
 
 // Section 3.1, eq. (p_list): the moduli, descending, pairwise coprime.
-constexpr int kModuli[kMaxModuli] = {
+constexpr int kPaperModuli[kMaxModuli] = {
     256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199, 197, 193, 191,
     181, 179, 173, 167, 163, 157, 151, 149, 139, 137, 131, 127, 113, 109, 107, 103, 101,
     97,  89,  83,  79,  73,  71,  67,  61,  59,  53,  47,  43,  41,  37,  29};
@@ -136,6 +139,102 @@ int modinv(int a, int p) {  // inverse of a modulo p (gcd(a, p) = 1), in [1, p-1
   return t < 0 ? t + p : t;
 }
 
+// ---------------------------------------------------------------------------
+// Moduli of largest product for each N (Section 3.1: the set that maximises
+// P depends on N, 255 leaving it beyond a small N, so a table per N can be
+// built).  Sought: N pairwise coprime integers in [2, 256] of largest
+// product.  Every v <= 256 is s * q with s 13-smooth and q = 1 or a prime
+// >= 17 (two primes >= 17 already exceed 256).  Coprimality therefore means:
+// the 13-smooth parts use disjoint sets of the primes 2..13, and each prime
+// >= 17 occurs at most once.  A dynamic program over "groups" -- one per
+// prime q >= 17 (choose at most one multiple q s <= 256) and one per
+// 13-smooth v (take it or not) -- keeps, per (set of small primes used,
+// count chosen), the largest product; that is exact, because the groups'
+// choices interact only through the small-prime set.  Among sets of equal
+// product the one whose descending sequence is lexicographically larger is
+// kept (that order is preserved when the same moduli are added to both, so
+// the per-state choice is the global one).
+struct ModSet {
+  Big prod;                 // 0: state not reached
+  std::vector<int> desc;    // the moduli, descending
+};
+
+bool better(const Big& p, const std::vector<int>& d, const ModSet& cur) {
+  const int c = Big::cmp(p, cur.prod);
+  if (c != 0) return c > 0;
+  return std::lexicographical_compare(cur.desc.begin(), cur.desc.end(), d.begin(), d.end());
+}
+
+constexpr int kSmallPrimes[6] = {2, 3, 5, 7, 11, 13};
+
+// Bit mask of the primes 2..13 dividing v, and the cofactor left over.
+int small_mask(int v, int* rest) {
+  int mask = 0;
+  for (int i = 0; i < 6; ++i)
+    if (v % kSmallPrimes[i] == 0) {
+      mask |= 1 << i;
+      while (v % kSmallPrimes[i] == 0) v /= kSmallPrimes[i];
+    }
+  *rest = v;
+  return mask;
+}
+
+struct OptimalTable {
+  bool ok = false;
+  int p[kMaxModuli + 1][kMaxModuli];   // p[N][0..N-1], descending
+  OptimalTable() {
+    // groups of alternatives: each a list of (value, small-prime mask)
+    std::vector<std::vector<std::pair<int, int>>> groups;
+    std::vector<std::pair<int, int>> by_prime[257];
+    for (int v = 2; v <= 256; ++v) {
+      int rest;
+      const int mask = small_mask(v, &rest);
+      if (rest == 1)
+        groups.push_back({{v, mask}});          // 13-smooth: its own group
+      else
+        by_prime[rest].push_back({v, mask});    // rest is a prime >= 17
+    }
+    for (int q = 17; q <= 256; ++q)
+      if (!by_prime[q].empty()) groups.push_back(by_prime[q]);
+    // dp[mask][count]
+    std::vector<ModSet> dp(64 * (kMaxModuli + 1));
+    auto st = [&](int mask, int cnt) -> ModSet& { return dp[mask * (kMaxModuli + 1) + cnt]; };
+    st(0, 0).prod = Big(1);
+    for (const auto& g : groups) {
+      std::vector<ModSet> next = dp;            // "choose none of the group"
+      for (int mask = 0; mask < 64; ++mask)
+        for (int cnt = 0; cnt < kMaxModuli; ++cnt) {
+          const ModSet& cur = st(mask, cnt);
+          if (cur.prod.bitlen() == 0) continue;
+          for (const auto& opt : g) {
+            if (mask & opt.second) continue;
+            Big prod = cur.prod;
+            prod.mul_small((uint64_t)opt.first);
+            std::vector<int> d = cur.desc;
+            d.insert(std::upper_bound(d.begin(), d.end(), opt.first, std::greater<int>()),
+                     opt.first);
+            ModSet& dst = next[(mask | opt.second) * (kMaxModuli + 1) + cnt + 1];
+            if (better(prod, d, dst)) {
+              dst.prod = prod;
+              dst.desc = std::move(d);
+            }
+          }
+        }
+      dp.swap(next);
+    }
+    for (int N = 2; N <= kMaxModuli; ++N) {
+      ModSet best;
+      for (int mask = 0; mask < 64; ++mask) {
+        const ModSet& c = st(mask, N);
+        if (c.prod.bitlen() != 0 && better(c.prod, c.desc, best)) best = c;
+      }
+      if ((int)best.desc.size() != N) return;
+      for (int l = 0; l < N; ++l) p[N][l] = best.desc[l];
+    }
+    ok = true;
+  }
+};
+
 // Round a long double down to an FP32 value (normal range); also returns the
 // distance to the two neighbouring grid points in *margin.
 float single_down(long double v, long double* margin) {
@@ -185,12 +284,28 @@ double recip_rn(const Big& P, double guess) {
 
 }  // namespace
 
-bool build_consts(int N, int b, CrtConsts* out) {
+bool moduli_of(int table, int N, int* p) {
+  if (N < 2 || N > kMaxModuli) return false;
+  if (table == kTablePaper) {
+    for (int l = 0; l < N; ++l) p[l] = kPaperModuli[l];
+    return true;
+  }
+  if (table != kTableOptimal) return false;
+  static const OptimalTable opt;   // built once, on first use
+  if (!opt.ok) return false;
+  for (int l = 0; l < N; ++l) p[l] = opt.p[N][l];
+  return true;
+}
+
+bool build_consts(int N, int b, int table, CrtConsts* out) {
   if (N < 2 || N > kMaxModuli || (b != 64 && b != 32)) return false;
+  int kModuli[kMaxModuli];
+  if (!moduli_of(table, N, kModuli)) return false;
   CrtConsts cc;
   std::memset(&cc, 0, sizeof(cc));
   cc.N = N;
   cc.b = b;
+  cc.table = table;
   Big P(1);
   int rho = 0;
   for (int l = 0; l < N; ++l) {
@@ -276,10 +391,12 @@ bool build_consts(int N, int b, CrtConsts* out) {
   return true;
 }
 
-bool build_plan_coef(int b, PlanCoef* out) {
+bool build_plan_coef(int b, int table, PlanCoef* out) {
   std::memset(out, 0, sizeof(*out));
   const long double u64 = std::ldexp((long double)1, -53), u32 = std::ldexp((long double)1, -24);
   for (int N = 2; N <= kMaxModuli; ++N) {
+    int kModuli[kMaxModuli];
+    if (!moduli_of(table, N, kModuli)) return false;
     Big P(1);
     int rho = 0;
     for (int l = 0; l < N; ++l) {

@@ -45,7 +45,8 @@ def test_version_and_workspace_query():
     assert oz.ozaki2_workspace_bytes(64, 10, 10, 10, 1) == 0
     assert oz.ozaki2_workspace_bytes(32, 10, 10, 10, 17) == 0     # FP32 allows N <= 16
     assert oz.ozaki2_workspace_bytes(32, 10, 10, 10, 16) > 0
-    assert oz.ozaki2_workspace_bytes(64, 10, 10, (1 << 17) + 1, 14) == 0
+    assert oz.ozaki2_workspace_bytes(64, 10, 10, 1 << 19, 14) == 0
+    assert oz.ozaki2_workspace_bytes(64, 10, 10, (1 << 19) - 1, 14) > 0
     assert oz.ozaki2_workspace_bytes(16, 10, 10, 10, 5) == 0
     # m and n stay at or below 2^31 - 256, so that their padding fits in int
     assert oz.ozaki2_workspace_bytes(64, 2 ** 31 - 255, 10, 10, 14) == 0
@@ -67,7 +68,7 @@ FAKE = 0x1000  # never dereferenced: every case below fails validation first
     ((4, 2 ** 31 - 255, 4, FAKE, 4, FAKE, 4, FAKE, 4, 10), oz.ERR_INVALID_ARG),  # n > 2^31 - 256
     ((4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1), oz.ERR_N_RANGE),
     ((4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 50), oz.ERR_N_RANGE),
-    ((4, 4, 2 ** 17 + 1, FAKE, 4, FAKE, 2 ** 17 + 1, FAKE, 4, 10), oz.ERR_K_RANGE),
+    ((4, 4, 2 ** 19, FAKE, 4, FAKE, 2 ** 19, FAKE, 4, 10), oz.ERR_K_RANGE),      # k >= 2^19
     ((0, 4, 4, None, 1, FAKE, 4, None, 1, 10), oz.OK),                   # m = 0: no-op
     ((4, 0, 4, FAKE, 4, None, 4, None, 4, 10), oz.OK),                   # n = 0: no-op
 ])
@@ -95,7 +96,7 @@ def test_noalloc_rejections_before_running():
     assert f(64, 4, 4, 4, FAKE, 3, FAKE, 4, FAKE, 4, 10) == oz.ERR_INVALID_ARG
     assert f(64, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 50) == oz.ERR_N_RANGE
     assert f(32, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 17) == oz.ERR_N_RANGE
-    assert f(64, 4, 4, 2 ** 17 + 1, FAKE, 4, FAKE, 2 ** 17 + 1, FAKE, 4, 10) == oz.ERR_K_RANGE
+    assert f(64, 4, 4, 2 ** 19, FAKE, 4, FAKE, 2 ** 19, FAKE, 4, 10) == oz.ERR_K_RANGE
     assert f(64, 0, 4, 4, None, 1, FAKE, 4, None, 1, 10) == oz.OK
     cap = 256 << 20
     # 2048^3 FP64 fits up to N = 21 and not at N = 22; 4096^3 not at N = 14
@@ -106,6 +107,26 @@ def test_noalloc_rejections_before_running():
     assert oz.ozaki2_workspace_bytes(32, 4096, 4096, 4096, 7) + 256 > cap
     assert f(64, 4096, 4096, 4096, FAKE, 4096, FAKE, 4096, FAKE, 4096, 14) == oz.ERR_WORKSPACE
     assert f(32, 4096, 4096, 4096, FAKE, 4096, FAKE, 4096, FAKE, 4096, 7) == oz.ERR_WORKSPACE
+
+
+def test_complex_argument_errors_and_workspace():
+    # Host-side checks of ozaki2_zgemm / ozaki2_cgemm (nothing reaches a device).
+    z, c, q = oz.ozaki2_zgemm, oz.ozaki2_cgemm, oz.ozaki2_complex_workspace_bytes
+    assert z(4, 4, 4, FAKE, 3, FAKE, 4, FAKE, 4, 10) == oz.ERR_INVALID_ARG     # lda < m
+    assert z(4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 2 ** 30, 10) == oz.ERR_INVALID_ARG  # ldc >= 2^30
+    assert z(4, 4, 4, None, 4, FAKE, 4, FAKE, 4, 10) == oz.ERR_INVALID_ARG
+    assert z(4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 50) == oz.ERR_N_RANGE
+    assert c(4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 17) == oz.ERR_N_RANGE
+    assert z(4, 4, 2 ** 18, FAKE, 4, FAKE, 2 ** 18, FAKE, 4, 10) == oz.ERR_K_RANGE  # 2k >= 2^19
+    assert z(0, 4, 4, None, 1, FAKE, 4, None, 1, 10) == oz.OK
+    # the embedded real problem is 2m x n x 2k; the workspace holds it, the
+    # embedded operands and the 2m x n real result
+    real = oz.ozaki2_workspace_bytes(64, 600, 200, 500, 14)
+    got = q(64, 300, 200, 250, 14)
+    assert got >= real + 8 * (4 * 300 * 250 + 2 * 250 * 200 + 2 * 300 * 200)
+    assert q(32, 300, 200, 250, 14) < got
+    assert q(64, 300, 200, 2 ** 18, 14) == 0 and q(64, 300, 200, 2 ** 18 - 1, 14) > 0
+    assert q(32, 300, 200, 250, 17) == 0 and q(64, 0, 4, 4, 14) == 0
 
 
 def test_debug_and_log2f_argument_errors():
@@ -137,7 +158,8 @@ def test_batched_workspace_query():
     assert q(64, [300, 200, 500, 14, 5, 4, 0, 10]) == one
     assert q(64, [300, 200, 500, 50]) == 0          # N out of range
     assert q(32, [300, 200, 500, 17]) == 0          # FP32 allows N <= 16
-    assert q(64, [300, 200, (1 << 17) + 1, 14]) == 0
+    assert q(64, [300, 200, 1 << 19, 14]) == 0
+    assert q(64, [300, 200, (1 << 17) + 1, 14]) > 0
     assert q(16, [300, 200, 500, 14]) == 0
     # at least the moduli slices and W of every active problem
     assert two >= 20 * (128 * 384 + 128 * 384 + 128 * 128) + 14 * (384 * 512 + 256 * 512 + 256 * 384)
@@ -153,7 +175,7 @@ def test_certified_argument_errors_and_workspace_query():
     assert c(64, 4, 4, 4, FAKE, 4, FAKE, 4, None, 4, 1e-14, 0)[0] == oz.ERR_INVALID_ARG   # NULL C
     assert c(64, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1e-14, 1)[0] == oz.ERR_N_RANGE
     assert c(32, 4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1e-6, 17)[0] == oz.ERR_N_RANGE
-    assert c(64, 4, 4, 2 ** 17 + 1, FAKE, 4, FAKE, 2 ** 17 + 1, FAKE, 4, 1e-14, 0)[0] == oz.ERR_K_RANGE
+    assert c(64, 4, 4, 2 ** 19, FAKE, 4, FAKE, 2 ** 19, FAKE, 4, 1e-14, 0)[0] == oz.ERR_K_RANGE
     assert c(64, 0, 4, 4, None, 1, FAKE, 4, None, 1, 1e-14, 0) == (oz.OK, 2, 0.0)   # m = 0: no-op
     q = oz.ozaki2_certified_workspace_bytes
     assert q(64, 300, 200, 500, 14) > oz.ozaki2_workspace_bytes(64, 300, 200, 500, 14)

@@ -99,6 +99,42 @@ def test_int32_wrap_at_k_max():
         assert np.array_equal(host(Cc).T, ref), f"split {split}"
 
 
+@pytest.mark.parametrize("k", [2 ** 17 + 1, 3 * 2 ** 17])
+def test_k_beyond_2_17(k):
+    # k above the paper's 2^17 (up to 2^19 - 1): Cbar maxima above 2^29,
+    # residue products reduced mod p_l every 2^17 of k.  Every stage
+    # bit-exact (C'_l congruent mod p_l), through the single call and a batch.
+    m, n, N = 16, 12, 14
+    announce(f"k beyond 2^17: m={m} n={n} k={k} N={N}")
+    A, B = gemm_inputs(m, n, k, phi=1.0, seed=k % 997)
+    run_stage_case(m, n, k, N, 1.0, seed=k % 997, dtype=np.float64)
+    ref = host(oz.gemm(dev(A), dev(B), N))
+    cases = [(A, B, N), gemm_inputs(30, 20, 100, phi=1.0, seed=5) + (13,)]
+    Cb = oz.gemm_batched([dev(a) for a, _, _ in cases], [dev(b) for _, b, _ in cases],
+                         [c[2] for c in cases])
+    assert np.array_equal(host(Cb[0]), ref)
+    assert np.array_equal(host(Cb[1]), os_ii(cases[1][0], cases[1][1], 13))
+    assert oz.ozaki2_sync_status() == oz.OK
+
+
+def test_k_beyond_2_17_residue_product_past_int32():
+    # Every term of the p = 255 residue product is 127^2 (fold-stressing
+    # inputs), so at k = 2^18 the product 2^18 127^2 exceeds 2^31: without
+    # the reduction every 2^17 of k the INT32 accumulator would wrap and W
+    # would be off by one modulo 255.  Every stage bit-exact against the
+    # oracle, the accumulator within INT32 and congruent to the product.
+    from pins import fold_inputs
+    m, n, k, N = 16, 8, 2 ** 18, 14
+    announce(f"fold-stressing inputs m={m} n={n} k={k} N={N}")
+    A, B = fold_inputs(m, n, k, N)
+    got = {kk: host(v) for kk, v in oz.debug_stages(dev(A), dev(B), N).items()}
+    C_ref, st = os_ii(A, B, N, stages=True)
+    l = list(st["const"].p).index(255)
+    assert np.all(np.abs(st["Cl"][l]) == k * 127 * 127)
+    assert compare_stages(got, st, C_ref, N) == []
+    assert oz.ozaki2_sync_status() == oz.OK
+
+
 def test_single_call_256_tiles_ragged():
     # 768 x 1000, k = 130, N = 16: padding n to 256 costs nothing over 128,
     # and the 16 residue products have 3 x 4 x 16 = 192 tiles of 256 x 256,

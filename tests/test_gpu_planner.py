@@ -40,6 +40,7 @@ def check_between(rc, Ng, lo, hi, nmax):
     (257, 129, 1000, 1.0, 1e-12),
     (64, 700, 256, 2.0, 1e-9),
     (40, 30, 50, 0.0, 1e-15),
+    (16, 12, 3 * 2 ** 17, 1.0, 1e-13),     # k beyond 2^17
 ])
 def test_required_moduli_fp64(m, n, k, phi, eps):
     announce(f"planner fp64 m={m} n={n} k={k} phi={phi} eps={eps}")
