@@ -40,12 +40,15 @@ def parse():
     ap.add_argument("--N", type=int, default=0, help="fix N instead of matching the native error")
     ap.add_argument("--samples", type=int, default=48, help="sampled rows (and columns) for errors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-size", type=int, default=256)
+    ap.add_argument("--cpu-size", type=int, default=2048)
     ap.add_argument("--cpu-N", type=int, default=14)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven 512-problem batched measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device copy of MIB MiB first (HBM counter calibration)")
+    ap.add_argument("--vendor-int8", action="store_true",
+                    help="also time the vendor INT8 GEMM (torch._int_mm, hipBLASLt) at size^3: "
+                         "context for the INT8 roofline of the residue products")
     ap.add_argument("--extras", action="store_true",
                     help="also measure the 4096^3 phi sweep (N from the bound at 1e-15), the "
                          "certified call at 1e-14 on the same inputs, and the FP32 16384^3 "
@@ -325,6 +328,24 @@ def batched_measurement(torch, oz, steps: int) -> dict:
             "speedup_vs_native": round(res["native"]["ms"] / res["emulated"]["ms"], 3)}
 
 
+def vendor_int8(torch, dev, size: int, reps: int = 5) -> dict:
+    """torch._int_mm (INT8 x INT8 -> INT32, hipBLASLt on ROCm) on random
+    size^3 operands in [-128, 127], timed with events: the vendor library's
+    rate for the same contraction the residue products run."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    a = torch.randint(-128, 128, (size, size), dtype=torch.int8, device=dev, generator=g)
+    b = torch.randint(-128, 128, (size, size), dtype=torch.int8, device=dev, generator=g)
+    try:
+        ms = _time_ms(torch, lambda: torch._int_mm(a, b), reps)
+    except RuntimeError as exc:      # not available in this build
+        return {"error": str(exc)[:200]}
+    ops = 2.0 * size ** 3
+    return {"op": "torch._int_mm (hipBLASLt INT8 GEMM)", "size": size, "ms": round(ms, 4),
+            "tops": round(ops / (ms * 1e-3) / 1e12, 1),
+            "frac_int8_peak": round(ops / (ms * 1e-3) / 1e12 / PEAK_INT8_TOPS, 4)}
+
+
 def hbm_reference(torch, dev, mib: int = 1024, reps: int = 5) -> dict:
     """Device copy (read + write) and fill (write) of `mib` MiB timed with
     events: the practical HBM rates the memory-bound phases are set against."""
@@ -396,30 +417,42 @@ def host_cpu() -> dict:
     return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model}
 
 
-def cpu_baseline(size: int, N: int, budget_s: float = 10.0) -> dict:
-    """The CPU oracle, as it is, on the small configuration (FP64 size^3, N
-    moduli, phi = 0.5, seed 0: every step of Algorithms 1-3), repeated until
-    about budget_s seconds have passed; one thread (the oracle is sequential
-    Python, and its BLAS calls are held to one thread)."""
+def cpu_baseline(size: int, N: int, budget_s: float = 15.0) -> dict:
+    """The CPU oracle, as it is, on every host core: its C++ twin
+    (oracle/os_ii_twin.cpp, plain loops with OpenMP, every step of
+    Algorithms 1-3) on FP64 size^3, N moduli, phi = 0.5, seed 0 -- a bounded
+    sample of the 8192^3 workload -- repeated until about budget_s seconds
+    have passed (at least once).  Also the Python oracle, one thread, on the
+    small 256^3 configuration (the reference implementation itself)."""
     from threadpoolctl import threadpool_limits
 
+    from oracle import twin
     from oracle.ozaki2 import os_ii
     from workload import gemm_inputs
 
     A, B = gemm_inputs(size, size, size, phi=0.5, seed=0)
     times = []
-    with threadpool_limits(limits=1):
-        while sum(times) < budget_s:
-            t0 = time.perf_counter()
-            os_ii(A, B, N)
-            times.append(time.perf_counter() - t0)
+    while not times or sum(times) < budget_s:
+        t0 = time.perf_counter()
+        twin.os_ii_twin(A, B, N)
+        times.append(time.perf_counter() - t0)
     dt = float(np.median(times))
+    threads = twin.threads()
+    A, B = gemm_inputs(256, 256, 256, phi=0.5, seed=0)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        os_ii(A, B, N)
+        dt_py = time.perf_counter() - t0
     cpu = host_cpu()
-    return {"value": 2.0 * size ** 3 / dt / 1e12, "unit": "TFLOPS", "cores": 1, "kind": "oracle",
+    return {"value": 2.0 * size ** 3 / dt / 1e12, "unit": "TFLOPS", "cores": threads, "kind": "oracle",
             "host": cpu,
-            "sample": f"full oracle run (Algorithms 1-3) on FP64 {size}^3, N={N}, phi=0.5, seed 0 "
-                      f"(the small configuration), median of {len(times)} runs: {dt:.2f} s each; "
-                      f"TFLOPS = 2*{size}^3/t; one thread of {cpu['nproc']} ({cpu['model']})"}
+            "sample": f"C++ twin of the oracle (every step of Algorithms 1-3) on FP64 {size}^3, "
+                      f"N={N}, phi=0.5, seed 0 -- a size-reduced sample of the 8192^3 workload -- "
+                      f"median of {len(times)} runs: {dt:.2f} s each; TFLOPS = 2*{size}^3/t; "
+                      f"{threads} OpenMP threads on {cpu['nproc']} logical CPUs ({cpu['model']})",
+            "python_oracle_256": {"seconds": round(dt_py, 2), "threads": 1,
+                                  "tflops": 2.0 * 256 ** 3 / dt_py / 1e12,
+                                  "sample": f"Python oracle, FP64 256^3, N={N}, one thread"}}
 
 
 def main():
@@ -580,6 +613,8 @@ def main():
                             "N_optimal_table": N_o, "reachable_optimal_table": rc_o == oz.OK}
     del Acm, Bcm, Ccm, dA, dB
     torch.cuda.empty_cache()
+    if args.vendor_int8:
+        out["vendor_int8"] = vendor_int8(torch, dev, m)
     if not args.no_batched:
         out["batched"] = batched_measurement(torch, oz, max(1, min(args.steps, 10)))
     if args.extras:
