@@ -239,8 +239,10 @@ int ozaki2_sync_status(void);
  * Each problem obeys the rules of ozaki2_gemm / ozaki2_sgemm; any invalid
  * problem makes the whole call fail before anything is enqueued.
  * The first call with a given batch (sizes, N, pointers, leading dimensions
- * and workspace) builds a device problem table, times tile choices on the
- * batch's own operands, captures the launch sequence into a hipGraph and
+ * and workspace) builds a device problem table, runs the batch once, times
+ * the residue products under each tile split and form (one workgroup per
+ * tile or persistent workgroups) on the residues that run produced,
+ * captures the launch sequence with the fastest into a hipGraph and
  * synchronises the stream; later calls with the same batch replay the graph
  * asynchronously and allocate nothing.  Up to eight batches stay cached per
  * device.  The workspace needed is ozaki2_batched_workspace_bytes.
@@ -318,13 +320,17 @@ const char *ozaki2_profile_name(int phase);
  *                                  tiles of 256x256 per product use them
  *   OZAKI2_KNOB_BATCH_GRAPH      : 1 = capture a batch into a hipGraph
  *                                  (default), 0 = enqueue its kernels directly
+ *   OZAKI2_KNOB_BATCH_PERSIST    : batched residue products: -1 = autotune
+ *                                  (default), 0 = one workgroup per tile,
+ *                                  1 = persistent workgroups
  * Returns OZAKI2_OK, or OZAKI2_ERR_INVALID_ARG for an unknown knob or value.
  */
 enum {
   OZAKI2_KNOB_SLICE_WORKGROUPS = 0,
   OZAKI2_KNOB_GEMM_TILE = 1,
   OZAKI2_KNOB_BATCH_SPLIT = 2,
-  OZAKI2_KNOB_BATCH_GRAPH = 3
+  OZAKI2_KNOB_BATCH_GRAPH = 3,
+  OZAKI2_KNOB_BATCH_PERSIST = 4
 };
 int ozaki2_debug_tuning(int knob, int value, int *previous);
 

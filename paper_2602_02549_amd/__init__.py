@@ -66,7 +66,7 @@ _SIGS = {
     "ozaki2_version": ([], ctypes.c_char_p),
 }
 
-KNOB_SLICE_WORKGROUPS, KNOB_GEMM_TILE, KNOB_BATCH_SPLIT, KNOB_BATCH_GRAPH = 0, 1, 2, 3
+KNOB_SLICE_WORKGROUPS, KNOB_GEMM_TILE, KNOB_BATCH_SPLIT, KNOB_BATCH_GRAPH, KNOB_BATCH_PERSIST = 0, 1, 2, 3, 4
 
 
 class Ozaki2Error(RuntimeError):

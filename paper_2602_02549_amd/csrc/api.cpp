@@ -568,6 +568,9 @@ struct BatchEntry {
   int blocks[BS_COUNT] = {};             // grid size per slot
   size_t map_off[BS_COUNT] = {};         // byte offset of each slot's block map
   int split = 0;                         // problems with >= split 256x256 tiles use them
+  bool persist = false;                  // residue products: persistent kernels
+  bool fold = false;                     // some k_pad > 2^17 (reduction mod p inside k)
+  int pgrid[2] = {0, 0};                 // resident workgroups of the persistent kernels (256, 128)
   int res_path = -1;                     // residue path code for the grouped slice kernels
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -586,10 +589,13 @@ struct BatchEntry {
   }
 };
 
-// Batch knobs (ozaki2_debug_tuning): a forced tile split (-1: autotune) and
-// whether a batch's launch sequence is captured into a hipGraph.
+// Batch knobs (ozaki2_debug_tuning): a forced tile split (-1: autotune),
+// whether a batch's launch sequence is captured into a hipGraph, and a forced
+// form of the residue products (-1: autotune, 0: one workgroup per tile,
+// 1: persistent).
 std::atomic<int> g_batch_split{-1};
 std::atomic<int> g_batch_graph{1};
+std::atomic<int> g_batch_persist{-1};
 
 // Device table of CrtConsts indexed by N (entries below 2 unused).
 int get_ctab(int b, CrtConsts** out) {
@@ -663,11 +669,21 @@ void build_table(const std::vector<ProbDesc>& D, int split, std::vector<char>* o
   }
   out->assign(off, 0);
   memcpy(out->data(), D.data(), sizeof(ProbDesc) * cnt);
+  // The residue-product maps list the problems by decreasing k, so that the
+  // persistent kernels, which deal entries out in a fixed stride, start with
+  // the longest tiles and end with the shortest (each problem's entries stay
+  // a multiple of 8 long, so every entry keeps its XCD).
+  std::vector<int> by_k(cnt);
+  for (int p = 0; p < cnt; ++p) by_k[p] = p;
+  std::stable_sort(by_k.begin(), by_k.end(), [&](int a, int b) { return D[a].kp > D[b].kp; });
   for (int sl = 0; sl < BS_COUNT; ++sl) {
     BlockRef* map = reinterpret_cast<BlockRef*>(out->data() + map_off[sl]);
+    const bool sorted = sl == BS_GR_BIG || sl == BS_GR_SMALL;
     size_t q = 0;
-    for (int p = 0; p < cnt; ++p)
+    for (int t = 0; t < cnt; ++t) {
+      const int p = sorted ? by_k[t] : t;
       for (int l = 0; l < c[(size_t)p * BS_COUNT + sl]; ++l) map[q++] = BlockRef{p, l};
+    }
   }
 }
 
@@ -676,6 +692,21 @@ bool table_fits(const int blocks[BS_COUNT]) {
   for (int sl = 0; sl < BS_COUNT; ++sl)
     if (blocks[sl] < 0) return false;
   return true;
+}
+
+// The residue products of a batch, in the entry's form.
+void enqueue_residue_products(const BatchEntry& e, const CrtConsts* ctab, hipStream_t s) {
+  const ProbDesc* D = reinterpret_cast<const ProbDesc*>(e.table);
+  auto M = [&](int sl) { return reinterpret_cast<const BlockRef*>(e.table + e.map_off[sl]); };
+  if (e.persist) {
+    launch_group_gemm_persist(s, 256, e.fold, e.pgrid[0], D, M(BS_GR_BIG), e.blocks[BS_GR_BIG],
+                              ctab);
+    launch_group_gemm_persist(s, 128, e.fold, e.pgrid[1], D, M(BS_GR_SMALL),
+                              e.blocks[BS_GR_SMALL], ctab);
+  } else {
+    launch_group_gemm(s, 0, 256, D, M(BS_GR_BIG), e.blocks[BS_GR_BIG], ctab);
+    launch_group_gemm(s, 0, 128, D, M(BS_GR_SMALL), e.blocks[BS_GR_SMALL], ctab);
+  }
 }
 
 // Enqueue the grouped launch sequence on `s` (table already on the device).
@@ -697,8 +728,7 @@ void enqueue_batch(Prec pr, const BatchEntry& e, const CrtConsts* ctab, int* sta
   launch_group_scale(s, pr, GP_SHIFTS, D, M(BS_SHIFTS), B(BS_SHIFTS), ctab);
   launch_group_slices(s, pr, 1, true, e.res_path, D, M(BS_SL_A), B(BS_SL_A), ctab);
   launch_group_slices(s, pr, 1, false, e.res_path, D, M(BS_SL_B), B(BS_SL_B), ctab);
-  launch_group_gemm(s, 0, 256, D, M(BS_GR_BIG), B(BS_GR_BIG), ctab);
-  launch_group_gemm(s, 0, 128, D, M(BS_GR_SMALL), B(BS_GR_SMALL), ctab);
+  enqueue_residue_products(e, ctab, s);
   launch_group_crt(s, pr, D, M(BS_CRT), B(BS_CRT), e.active, ctab, status);
 }
 
@@ -719,12 +749,20 @@ int upload_table(BatchEntry* e, const std::vector<char>& host, hipStream_t s) {
 }
 
 // Autotuner: times the residue products (the dominant phase) under each
-// candidate tile split, on this batch's operands, and returns the fastest.
-int tune_split(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* ctab,
-               hipStream_t s, int* best) {
-  const int cand[4] = {1 << 30, 16, 4, 0};
+// candidate tile split and form (one workgroup per tile, or persistent) and
+// keeps the fastest.  The caller has run the whole batch once, so the
+// operand slices in the workspace are this batch's own residues; the split
+// does not move them (the padding of every problem is fixed).  A forced
+// split or form (forced_split >= 0, forced_persist >= 0) is not tuned.
+int tune_batch(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* ctab,
+               hipStream_t s, int forced_split, int forced_persist) {
+  std::vector<int> splits = forced_split >= 0 ? std::vector<int>{forced_split}
+                                              : std::vector<int>{1 << 30, 16, 4, 0};
+  std::vector<int> forms = forced_persist >= 0 ? std::vector<int>{forced_persist}
+                                               : std::vector<int>{1, 0};
   float best_ms = 0.f;
-  *best = cand[0];
+  bool have = false;
+  int best_split = splits[0], best_form = forms[0];
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return OZAKI2_ERR_HIP;
   if (hipEventCreate(&b) != hipSuccess) {
@@ -733,30 +771,34 @@ int tune_split(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* c
   }
   int rc = OZAKI2_OK;
   std::vector<char> host;
-  for (int c = 0; c < 4 && rc == OZAKI2_OK; ++c) {
-    build_table(D, cand[c], &host, e->blocks, e->map_off);
+  for (size_t c = 0; c < splits.size() && rc == OZAKI2_OK; ++c) {
+    build_table(D, splits[c], &host, e->blocks, e->map_off);
     if (!table_fits(e->blocks)) continue;
     if ((rc = upload_table(e, host, s))) break;
-    const ProbDesc* Dd = reinterpret_cast<const ProbDesc*>(e->table);
-    auto M = [&](int sl) { return reinterpret_cast<const BlockRef*>(e->table + e->map_off[sl]); };
-    float ms = 0.f;
-    for (int rep = 0; rep < 3; ++rep) {
-      if (rep == 1) (void)hipEventRecord(a, s);
-      launch_group_gemm(s, 0, 256, Dd, M(BS_GR_BIG), e->blocks[BS_GR_BIG], ctab);
-      launch_group_gemm(s, 0, 128, Dd, M(BS_GR_SMALL), e->blocks[BS_GR_SMALL], ctab);
-    }
-    (void)hipEventRecord(b, s);
-    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
-      rc = OZAKI2_ERR_HIP;
-      break;
-    }
-    if (c == 0 || ms < best_ms) {
-      best_ms = ms;
-      *best = cand[c];
+    for (int form : forms) {
+      e->persist = form == 1;
+      float ms = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {
+        if (rep == 1) (void)hipEventRecord(a, s);
+        enqueue_residue_products(*e, ctab, s);
+      }
+      (void)hipEventRecord(b, s);
+      if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        rc = OZAKI2_ERR_HIP;
+        break;
+      }
+      if (!have || ms < best_ms) {
+        have = true;
+        best_ms = ms;
+        best_split = splits[c];
+        best_form = form;
+      }
     }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
+  e->split = best_split;
+  e->persist = best_form == 1;
   return rc;
 }
 
@@ -798,6 +840,7 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
   if (hipGetDevice(&dev) != hipSuccess) return OZAKI2_ERR_HIP;
 
   const int forced = g_batch_split.load(std::memory_order_relaxed);
+  const int forced_persist = g_batch_persist.load(std::memory_order_relaxed);
   const bool use_graph = g_batch_graph.load(std::memory_order_relaxed) != 0;
   std::vector<int64_t> key;
   key.reserve(4 + 10 * (size_t)count);
@@ -806,6 +849,7 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
   key.push_back((int64_t)(intptr_t)ws);
   key.push_back((int64_t)gen);
   key.push_back(forced);
+  key.push_back(forced_persist);
   key.push_back(use_graph ? 1 : 0);
   for (int p = 0; p < count; ++p) {
     for (int q = 0; q < 4; ++q) key.push_back(mnkN[4 * p + q]);
@@ -866,10 +910,20 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
       for (const CrtConsts& c : cs) ptrs.push_back(&c);
       e->res_path = group_residue_path(ptrs.data(), (int)ptrs.size());
     }
+    for (const ProbDesc& d : D) e->fold = e->fold || d.kp > (1 << 17);
+    e->pgrid[0] = persist_grid(256);
+    e->pgrid[1] = persist_grid(128);
     std::vector<char> host;
     e->split = forced >= 0 ? forced : 1 << 30;
-    if (forced < 0 && e->active > 0) {
-      if ((rc = tune_split(D, e.get(), ctab, s, &e->split))) return rc;
+    e->persist = forced_persist != 0;
+    if ((forced < 0 || forced_persist < 0) && e->active > 0) {
+      // One eager pass of the whole batch first, so that the tuner times the
+      // residue products on this batch's own residues.
+      build_table(D, e->split, &host, e->blocks, e->map_off);
+      if (!table_fits(e->blocks)) return OZAKI2_ERR_INVALID_ARG;
+      if ((rc = upload_table(e.get(), host, s))) return rc;
+      enqueue_batch(pr, *e, ctab, status, s, C, ldc, mnkN);
+      if ((rc = tune_batch(D, e.get(), ctab, s, forced, forced_persist))) return rc;
     }
     build_table(D, e->split, &host, e->blocks, e->map_off);
     if (!table_fits(e->blocks)) return OZAKI2_ERR_INVALID_ARG;
@@ -1352,6 +1406,10 @@ int ozaki2_debug_tuning(int knob, int value, int* previous) {
     case OZAKI2_KNOB_BATCH_GRAPH:
       if (value != 0 && value != 1) return OZAKI2_ERR_INVALID_ARG;
       k = &g_batch_graph;
+      break;
+    case OZAKI2_KNOB_BATCH_PERSIST:
+      if (value < -1 || value > 1) return OZAKI2_ERR_INVALID_ARG;
+      k = &g_batch_persist;
       break;
     default:
       return OZAKI2_ERR_INVALID_ARG;

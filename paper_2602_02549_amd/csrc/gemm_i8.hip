@@ -104,7 +104,7 @@ __device__ inline int swz(int r) { return (r >> 1) & 7; }
 // rows of 128 bytes.  `bid` is the workgroup's index among the `launched`
 // workgroups of this product (launched >= tiles_x * tiles_y * nz; the
 // surplus exits at once).
-template <int BX, int BY, int NWX, int NWY, int EPI, bool BF16>
+template <int BX, int BY, int NWX, int NWY, int EPI, bool BF16, bool FOLD>
 __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t sx,
                                           const int8_t* __restrict__ Y, size_t sy, int tiles_x,
                                           int tiles_y, int nz, int k_pad, const CrtConsts& cc,
@@ -358,8 +358,10 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   // adds at most 127^2 2^17 < 2^31 - 127 in magnitude to a reduced value, so
   // every partial sum stays exact in INT32 and the result is congruent to
   // C'_l mod p_z.  For p = 256 the two's-complement wrap is already exact
-  // mod 256.  The inner loop is the same for every chunk.
-  constexpr bool kFold = EPI == 0 || EPI == 4;
+  // mod 256.  The inner loop is the same for every chunk.  FOLD selects the
+  // build of the kernel for k_pad > 2^17, so that the usual one keeps the
+  // plain loop and its register budget.
+  constexpr bool kFold = FOLD && (EPI == 0 || EPI == 4);
   const int chunk = kFold ? kFoldGroups : NG;
   auto fold = [&]() {
     const int p = cc.p[z];
@@ -412,6 +414,241 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   finish();
 }
 
+// Persistent form of the residue products (EPI 0) for batches: a grid of
+// resident workgroups walks the block map in a fixed stride (workgroup g
+// takes entries g, g + G, g + 2G, ...; G a multiple of 8, so every entry
+// runs on the XCD its local index maps to, as in the one-workgroup-per-entry
+// launch).  While a workgroup consumes the last k-group of one tile it
+// already copies the first k-group of its next tile into the other LDS
+// buffer, so that copy overlaps the last MFMAs and the epilogue instead of
+// starting the next tile cold; short-k problems spend most of their time in
+// that first copy.  The arithmetic of every tile is the one of gemm_body
+// (the same fragment order, MFMAs and epilogue), so the results are the same
+// bits.
+template <int BX, int BY, int NWX, int NWY, bool FOLD>
+__device__ __forceinline__ void gemm_persist(const ProbDesc* __restrict__ P,
+                                             const BlockRef* __restrict__ map, int items,
+                                             const CrtConsts* __restrict__ ctab) {
+  constexpr int BK = 128;
+  constexpr int NW = NWX * NWY;
+  constexpr int WX = BX / NWX, WY = BY / NWY;
+  constexpr int TX = WX / 32, TY = WY / 32;
+  constexpr int CPR = BK / 16;
+  constexpr int RPI = 1024 / BK;
+  constexpr int IX = BX / RPI / NW, IY = BY / RPI / NW;
+  static_assert(IX % 2 == 0 && IY % 2 == 0 && WX % 32 == 0 && WY % 32 == 0, "tile / wave shape");
+  static_assert(BX == BY, "square tiles");
+  constexpr int GROUP_BYTES = (BX + BY) * BK;
+  constexpr int GROUP = 8;
+  __shared__ __attribute__((aligned(1024))) int8_t lds[2 * GROUP_BYTES];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wx = wave / NWY, wy = wave % NWY;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  const int lr = lane / CPR, slot = lane % CPR;
+  const int ch_e = (slot ^ swz(lr)) * 16, ch_o = (slot ^ swz(RPI + lr)) * 16;
+  const int frow = lane & 31;
+  int fo[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) fo[j] = frow * BK + (((2 * j + (lane >> 5)) ^ swz(frow)) * 16);
+
+  // One tile of one residue product.
+  struct Job {
+    const int8_t* xs;   // this lane's first copy source row of X (slice z, k = 0)
+    const int8_t* ys;
+    int8_t* Wz;
+    int k_pad, ldw, x0, y0, z, p;
+    double pinv;
+  };
+  // Entry i of the map as a job; false for the padding entries.
+  auto decode = [&](int i, Job& j) -> bool {
+    const BlockRef e = map[i];
+    const ProbDesc& d = P[e.x];
+    const int tiles_x = d.mp / BX, tiles_y = d.np / BY, nz = d.N;
+    const int launched = group_gemm_blocks(d.mp, d.np, BX, nz);
+    const int total = tiles_x * tiles_y * nz;
+    int bid = e.y;
+    {
+      const int xcd = bid % kXcds, loc = bid / kXcds;
+      const int per = launched / kXcds, extra = launched % kXcds;
+      bid = xcd * per + min(xcd, extra) + loc;
+    }
+    if (bid >= total) return false;
+    const int per_slice = tiles_x * tiles_y;
+    const int z = bid / per_slice;
+    int t = bid % per_slice;
+    const int group_span = GROUP * tiles_y;
+    const int g = t / group_span;
+    const int gx0 = g * GROUP;
+    const int gsz = min(GROUP, tiles_x - gx0);
+    t -= g * group_span;
+    j.x0 = (gx0 + t % gsz) * BX;
+    j.y0 = (t / gsz) * BY;
+    j.z = z;
+    j.k_pad = d.kp;
+    j.ldw = d.mp;
+    j.xs = d.As + (size_t)z * d.mp * d.kp + (size_t)(j.x0 + wave * IX * RPI + lr) * d.kp;
+    j.ys = d.Bs + (size_t)z * d.np * d.kp + (size_t)(j.y0 + wave * IY * RPI + lr) * d.kp;
+    j.Wz = d.W + (size_t)z * d.np * d.mp;
+    j.p = ctab[d.N].p[z];
+    j.pinv = ctab[d.N].pinv[z];
+    return true;
+  };
+  auto issue_x = [&](int8_t* buf, const Job& j, int k0) {
+    const uint32_t b = lds_addr(buf);
+    const size_t rowstep = (size_t)RPI * j.k_pad;
+#pragma unroll
+    for (int q = 0; q < IX; ++q)
+      dma16(j.xs + k0 + q * rowstep + ((q & 1) ? ch_o : ch_e),
+            b + (uint32_t)((wave_u * IX + q) * 1024));
+  };
+  auto issue_y = [&](int8_t* buf, const Job& j, int k0) {
+    const uint32_t b = lds_addr(buf);
+    const size_t rowstep = (size_t)RPI * j.k_pad;
+#pragma unroll
+    for (int q = 0; q < IY; ++q)
+      dma16(j.ys + k0 + q * rowstep + ((q & 1) ? ch_o : ch_e),
+            b + (uint32_t)(BX * BK + (wave_u * IY + q) * 1024));
+  };
+  auto next_job = [&](int i, Job& j) -> int {   // first valid entry at or after i (stride G)
+    for (; i < items; i += (int)gridDim.x)
+      if (decode(i, j)) return i;
+    return items;
+  };
+
+  v16i acc[TX][TY];
+  auto load_frags = [&](const int8_t* buf, int j, v4i (&a)[TX], v4i (&b)[TY]) {
+#pragma unroll
+    for (int tx = 0; tx < TX; ++tx)
+      a[tx] = *reinterpret_cast<const v4i*>(buf + (wx * WX + tx * 32) * BK + fo[j]);
+#pragma unroll
+    for (int ty = 0; ty < TY; ++ty)
+      b[ty] = *reinterpret_cast<const v4i*>(buf + (BX + wy * WY + ty * 32) * BK + fo[j]);
+  };
+  auto mfmas = [&](const v4i (&a)[TX], const v4i (&b)[TY]) {
+#pragma unroll
+    for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+      for (int ty = 0; ty < TY; ++ty)
+        acc[tx][ty] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[tx], b[ty], acc[tx][ty], 0, 0, 0);
+  };
+  auto interleave = [&]() {
+#pragma unroll
+    for (int q = 0; q < TX + TY; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+    if constexpr (TX * TY > TX + TY) __builtin_amdgcn_sched_group_barrier(0x008, TX * TY - (TX + TY), 0);
+  };
+
+  Job cur, nxt;
+  int i = next_job((int)blockIdx.x, cur);
+  if (i >= items) return;   // whole workgroup, before any barrier
+  issue_x(lds, cur, 0);
+  issue_y(lds, cur, 0);
+  int ph = 0;               // LDS buffer of the current job's group 0
+  for (;;) {
+    const int inext = next_job(i + (int)gridDim.x, nxt);
+    const bool more = inext < items;
+#pragma unroll
+    for (int a = 0; a < TX; ++a)
+#pragma unroll
+      for (int b = 0; b < TY; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
+    const int NG = cur.k_pad / 128;
+    for (int g0 = 0; g0 < NG; g0 += FOLD ? kFoldGroups : NG) {
+      const int g1 = FOLD ? min(NG, g0 + kFoldGroups) : NG;
+      for (int gi = g0; gi < g1; ++gi) {
+        int8_t* const buf = lds + ((ph + gi) & 1) * GROUP_BYTES;
+        int8_t* const next = lds + ((ph + gi + 1) & 1) * GROUP_BYTES;
+        wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+        v4i a0[TX], b0[TY], a1[TX], b1[TY];
+        load_frags(buf, 0, a0, b0);
+        if (gi + 1 < NG)
+          issue_x(next, cur, (gi + 1) * 128);
+        else if (more)
+          issue_x(next, nxt, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_frags(buf, 1, a1, b1);
+        mfmas(a0, b0);
+        interleave();
+        __builtin_amdgcn_sched_barrier(0);
+        if (gi + 1 < NG)
+          issue_y(next, cur, (gi + 1) * 128);
+        else if (more)
+          issue_y(next, nxt, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_frags(buf, 2, a0, b0);
+        mfmas(a1, b1);
+        interleave();
+        __builtin_amdgcn_sched_barrier(0);
+        load_frags(buf, 3, a1, b1);
+        mfmas(a0, b0);
+        interleave();
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(a1, b1);
+      }
+      if (FOLD && g1 < NG && cur.p != 256) {   // reduction every 2^17 of k (see gemm_body)
+        const double pd = (double)cur.p;
+#pragma unroll
+        for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+          for (int ty = 0; ty < TY; ++ty)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[tx][ty][r] = mod_odd(acc[tx][ty][r], pd, cur.pinv);
+      }
+    }
+    ph = (ph + NG) & 1;
+    // epilogue: W_z = mod(C'_z, p_z), as in gemm_body
+    const int xb = cur.x0 + wx * WX, yb = cur.y0 + wy * WY;
+    auto store_block = [&](int tx, int ty, uint32_t R0, uint32_t R1, uint32_t R2, uint32_t R3) {
+      const auto s02 = __builtin_amdgcn_permlane32_swap(R0, R2, false, false);
+      const auto s13 = __builtin_amdgcn_permlane32_swap(R1, R3, false, false);
+      const int x = xb + tx * 32 + 16 * (lane >> 5);
+      const int y = yb + ty * 32 + (lane & 31);
+      uint4 v;
+      v.x = s02[0];
+      v.y = s02[1];
+      v.z = s13[0];
+      v.w = s13[1];
+      *reinterpret_cast<uint4*>(cur.Wz + (size_t)y * cur.ldw + x) = v;
+    };
+    if (cur.p == 256) {
+#pragma unroll
+      for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+        for (int ty = 0; ty < TY; ++ty) {
+          uint32_t R[4];
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4)
+            R[r4] = pack_bytes(acc[tx][ty][4 * r4 + 0], acc[tx][ty][4 * r4 + 1],
+                               acc[tx][ty][4 * r4 + 2], acc[tx][ty][4 * r4 + 3]);
+          store_block(tx, ty, R[0], R[1], R[2], R[3]);
+        }
+    } else {
+      const double pd = (double)cur.p, pinv = cur.pinv;
+#pragma unroll
+      for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+        for (int ty = 0; ty < TY; ++ty) {
+          uint32_t R[4];
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4)
+            R[r4] = pack_bytes(mod_odd(acc[tx][ty][4 * r4 + 0], pd, pinv),
+                               mod_odd(acc[tx][ty][4 * r4 + 1], pd, pinv),
+                               mod_odd(acc[tx][ty][4 * r4 + 2], pd, pinv),
+                               mod_odd(acc[tx][ty][4 * r4 + 3], pd, pinv));
+          store_block(tx, ty, R[0], R[1], R[2], R[3]);
+        }
+    }
+    if (!more) break;
+    cur = nxt;
+    i = inext;
+  }
+}
+
 // Wave grid and residency of the two tile sizes.
 template <int B>
 struct TileShape;
@@ -428,28 +665,36 @@ constexpr int tile_threads() {
   return 64 * TileShape<B>::NWX * TileShape<B>::NWY;
 }
 
-template <int B, int EPI, bool BF16 = false>
+template <int B, int EPI, bool BF16 = false, bool FOLD = false>
 __global__ __launch_bounds__(tile_threads<B>(), TileShape<B>::OCC) void k_gemm_i8(
     const int8_t* __restrict__ X, size_t sx, const int8_t* __restrict__ Y, size_t sy, int tiles_x,
     int tiles_y, int nz, int k_pad, CrtConsts cc, int8_t* __restrict__ W, size_t sw, int ldw,
     int* __restrict__ xmax, int* __restrict__ ymax) {
-  gemm_body<B, B, TileShape<B>::NWX, TileShape<B>::NWY, EPI, BF16>(
+  gemm_body<B, B, TileShape<B>::NWX, TileShape<B>::NWY, EPI, BF16, FOLD>(
       X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax, blockIdx.x, gridDim.x);
 }
 
 // Grouped: the scaling product (EPI 1) or the N residue products (EPI 0) of
 // every problem of a batch.
-template <int B, int EPI>
+template <int B, int EPI, bool FOLD>
 __global__ __launch_bounds__(tile_threads<B>(), TileShape<B>::OCC) void kg_gemm(
     const ProbDesc* __restrict__ P, const BlockRef* __restrict__ map,
     const CrtConsts* __restrict__ ctab) {
   const BlockRef e = map[blockIdx.x];
   const ProbDesc& d = P[e.x];
   const int nz = EPI == 0 ? d.N : 1;
-  gemm_body<B, B, TileShape<B>::NWX, TileShape<B>::NWY, EPI, false>(
+  gemm_body<B, B, TileShape<B>::NWX, TileShape<B>::NWY, EPI, false, FOLD>(
       d.As, EPI == 0 ? (size_t)d.mp * d.kp : 0, d.Bs, EPI == 0 ? (size_t)d.np * d.kp : 0, d.mp / B,
       d.np / B, nz, d.kp, ctab[d.N], d.W, (size_t)d.np * d.mp, d.mp, d.rmax, d.cmax, e.y,
       group_gemm_blocks(d.mp, d.np, B, nz));
+}
+
+// Persistent grouped residue products (see gemm_persist).
+template <int B, bool FOLD>
+__global__ __launch_bounds__(tile_threads<B>(), TileShape<B>::OCC) void kp_gemm(
+    const ProbDesc* __restrict__ P, const BlockRef* __restrict__ map, int items,
+    const CrtConsts* __restrict__ ctab) {
+  gemm_persist<B, B, TileShape<B>::NWX, TileShape<B>::NWY, FOLD>(P, map, items, ctab);
 }
 
 template <int B>
@@ -458,10 +703,15 @@ void launch_cfg(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t
                 size_t sw, int ldw, int* xmax, int* ymax) {
   const int tiles_x = nx_pad / B, tiles_y = ny_pad / B;
   const dim3 grid((unsigned)(tiles_x * tiles_y * nz)), block(tile_threads<B>());
+  const bool fold = k_pad > kFoldGroups * 128;
   switch (epi) {
     case 0:
-      hipLaunchKernelGGL((k_gemm_i8<B, 0>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
-                         k_pad, cc, W, sw, ldw, xmax, ymax);
+      if (fold)
+        hipLaunchKernelGGL((k_gemm_i8<B, 0, false, true>), grid, block, 0, s, X, sx, Y, sy, tiles_x,
+                           tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+      else
+        hipLaunchKernelGGL((k_gemm_i8<B, 0>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y,
+                           nz, k_pad, cc, W, sw, ldw, xmax, ymax);
       break;
     case 1:
       hipLaunchKernelGGL((k_gemm_i8<B, 1>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
@@ -472,8 +722,12 @@ void launch_cfg(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t
                          k_pad, cc, W, sw, ldw, xmax, ymax);
       break;
     default:
-      hipLaunchKernelGGL((k_gemm_i8<B, 4>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
-                         k_pad, cc, W, sw, ldw, xmax, ymax);
+      if (fold)
+        hipLaunchKernelGGL((k_gemm_i8<B, 4, false, true>), grid, block, 0, s, X, sx, Y, sy, tiles_x,
+                           tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+      else
+        hipLaunchKernelGGL((k_gemm_i8<B, 4>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y,
+                           nz, k_pad, cc, W, sw, ldw, xmax, ymax);
       break;
   }
 }
@@ -500,6 +754,41 @@ bool use_256(int nx_pad, int ny_pad, int nz) {
 
 std::atomic<int> g_gemm_tile{0};
 
+int persist_grid(int tile) {
+  int dev = 0, cus = 0, occ = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  const void* k = tile == 256 ? reinterpret_cast<const void*>(kp_gemm<256, true>)
+                              : reinterpret_cast<const void*>(kp_gemm<128, true>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, tile == 256 ? tile_threads<256>()
+                                                                        : tile_threads<128>(),
+                                                   0) != hipSuccess ||
+      occ < 1)
+    occ = 1;
+  return (cus * occ + 7) / 8 * 8;   // a multiple of 8: entries keep their XCD
+}
+
+void launch_group_gemm_persist(hipStream_t s, int tile, bool fold, int grid, const ProbDesc* P,
+                               const BlockRef* map, int items, const CrtConsts* ctab) {
+  if (items <= 0) return;
+  const dim3 g((unsigned)(grid < items ? grid : (items + 7) / 8 * 8));
+  if (tile == 256) {
+    const dim3 b(tile_threads<256>());
+    if (fold)
+      hipLaunchKernelGGL((kp_gemm<256, true>), g, b, 0, s, P, map, items, ctab);
+    else
+      hipLaunchKernelGGL((kp_gemm<256, false>), g, b, 0, s, P, map, items, ctab);
+  } else {
+    const dim3 b(tile_threads<128>());
+    if (fold)
+      hipLaunchKernelGGL((kp_gemm<128, true>), g, b, 0, s, P, map, items, ctab);
+    else
+      hipLaunchKernelGGL((kp_gemm<128, false>), g, b, 0, s, P, map, items, ctab);
+  }
+}
+
 void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const BlockRef* map,
                        int blocks, const CrtConsts* ctab) {
   if (blocks <= 0) return;
@@ -507,15 +796,15 @@ void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, cons
   if (tile == 256) {
     const dim3 b(tile_threads<256>());
     if (epi == 0)
-      hipLaunchKernelGGL((kg_gemm<256, 0>), g, b, 0, s, P, map, ctab);
+      hipLaunchKernelGGL((kg_gemm<256, 0, true>), g, b, 0, s, P, map, ctab);
     else
-      hipLaunchKernelGGL((kg_gemm<256, 1>), g, b, 0, s, P, map, ctab);
+      hipLaunchKernelGGL((kg_gemm<256, 1, false>), g, b, 0, s, P, map, ctab);
   } else {
     const dim3 b(tile_threads<128>());
     if (epi == 0)
-      hipLaunchKernelGGL((kg_gemm<128, 0>), g, b, 0, s, P, map, ctab);
+      hipLaunchKernelGGL((kg_gemm<128, 0, true>), g, b, 0, s, P, map, ctab);
     else
-      hipLaunchKernelGGL((kg_gemm<128, 1>), g, b, 0, s, P, map, ctab);
+      hipLaunchKernelGGL((kg_gemm<128, 1, false>), g, b, 0, s, P, map, ctab);
   }
 }
 

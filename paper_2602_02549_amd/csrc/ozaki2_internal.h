@@ -242,6 +242,13 @@ void launch_group_slices(hipStream_t s, Prec pr, int mode, bool aside, int path,
                          const CrtConsts* ctab);
 void launch_group_gemm(hipStream_t s, int epi, int tile, const ProbDesc* P, const BlockRef* map,
                        int blocks, const CrtConsts* ctab);
+// Persistent grouped residue products: `grid` resident workgroups (a multiple
+// of 8, from persist_grid, queried outside any capture) walk the `items`
+// entries of the block map.
+int persist_grid(int tile);
+// `fold`: some problem has k_pad > 2^17 (the build with reductions mod p).
+void launch_group_gemm_persist(hipStream_t s, int tile, bool fold, int grid, const ProbDesc* P,
+                               const BlockRef* map, int items, const CrtConsts* ctab);
 void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const BlockRef* map, int blocks,
                       int count, const CrtConsts* ctab, int* status);
 

@@ -89,15 +89,18 @@ def test_batched_one_residue_path(N, dtype):
                 assert np.array_equal(got, os_ii(A, B, Nq)), f"problem {q} vs oracle"
 
 
+@pytest.mark.parametrize("persist", [1, 0])
 @pytest.mark.parametrize("split", [0, 1000000, 4])
-def test_batched_tile_splits_and_eager(split):
-    # Every tile split (all 256x256, all 128x128, mixed) and the eager
-    # (uncaptured) launch sequence give the same bits.
-    announce(f"batched split={split}")
+def test_batched_tile_splits_and_eager(split, persist):
+    # Every tile split (all 256x256, all 128x128, mixed), both forms of the
+    # residue products (persistent workgroups walking the block map, one
+    # workgroup per tile) and the eager (uncaptured) launch sequence give the
+    # same bits.
+    announce(f"batched split={split} persist={persist}")
     cases = SMALL[:6] + SMALL[9:]
     As, Bs = make_batch(cases, np.float64, seed=300)
     Ns = [c[3] for c in cases]
-    with oz.tuning(oz.KNOB_BATCH_SPLIT, split):
+    with oz.tuning(oz.KNOB_BATCH_SPLIT, split), oz.tuning(oz.KNOB_BATCH_PERSIST, persist):
         _, _, C1, _ = run_batched(As, Bs, Ns)
         with oz.tuning(oz.KNOB_BATCH_GRAPH, 0):
             _, _, C2, _ = run_batched(As, Bs, Ns)
@@ -105,6 +108,26 @@ def test_batched_tile_splits_and_eager(split):
         ref = single(A, B, N)
         assert np.array_equal(host(C1[q]).T, ref), f"graph, problem {q}"
         assert np.array_equal(host(C2[q]).T, ref), f"eager, problem {q}"
+
+
+def test_batched_persistent_many_problems_and_long_k():
+    # More entries than resident workgroups (each workgroup walks several
+    # tiles of different problems and k), problems ordered by k, and one
+    # problem with k > 2^17 (the build with reductions mod p inside k).
+    cases = [(200 + 13 * q, 150 + 7 * q, 64 + 97 * q, 12 + q % 5) for q in range(40)]
+    cases += [(24, 20, 2 ** 17 + 300, 14), (640, 512, 700, 16)]
+    announce(f"batched persistent: {len(cases)} problems, one with k > 2^17")
+    As, Bs = make_batch(cases, np.float64, seed=700)
+    Ns = [c[3] for c in cases]
+    with oz.tuning(oz.KNOB_BATCH_PERSIST, 1):
+        _, _, Ccm, _ = run_batched(As, Bs, Ns)
+    assert oz.ozaki2_sync_status() == oz.OK
+    for q, (A, B, N) in enumerate(zip(As, Bs, Ns)):
+        assert np.array_equal(host(Ccm[q]).T, single(A, B, N)), f"problem {q} {cases[q]}"
+    q = len(cases) - 2
+    rows, cols = np.array([0, 11, 23]), np.array([0, 19])
+    assert np.array_equal(host(Ccm[q]).T[np.ix_(rows, cols)],
+                          os_ii(As[q], Bs[q], Ns[q], rows=rows, cols=cols))
 
 
 def test_batched_graph_replays():
