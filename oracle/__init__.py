@@ -13,6 +13,11 @@ Contents
   bounds     Theorem 1 (eq. thm:err-1), its simplified form (eq. thm:err-2)
              and the required-moduli reading of the planner
   exact      exact reference products (Fractions / Dekker + fsum)
+  moduli     per-N moduli of largest product (Section 3.1), branch and bound
+  complex_gemm  complex products on the real embedding (reading R23)
+  twin       loader of os_ii_twin.cpp, a plain C++ (OpenMP) second
+             implementation of Algorithms 1-3, compared stage by stage with
+             ozaki2 and timed on every host core
 
 Every floating-point step is either exact by a stated argument (and asserted),
 or emulated with exact rational arithmetic followed by one correct rounding.

@@ -73,3 +73,33 @@ def test_noalloc_edge_cases_and_status():
                                 Ad.data_ptr(), 4096, 14)
     assert rc == oz.ERR_WORKSPACE
     assert torch.all(Ad == 0).item()
+
+
+def test_noalloc_captured_in_a_graph():
+    # The callers this entry point is for include code under stream capture:
+    # after one call has set up the device's array, a call is captured into a
+    # graph and replayed three times, with other allocation-free calls on the
+    # same array (which overwrite it) between the replays; every replay must
+    # give the eager call's bits.
+    announce("noalloc captured in a graph")
+    m, n, k, N = 300, 200, 500, 14
+    A, B = gemm_inputs(m, n, k, phi=1.0, seed=41)
+    ref = _call("noalloc", 64, A, B, N)
+    dA, dB = dev(np.ascontiguousarray(A.T)), dev(np.ascontiguousarray(B.T))
+    C = torch.full((n, m), float("nan"), dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        rc = oz.ozaki2_gemm_noalloc(64, m, n, k, dA.data_ptr(), m, dB.data_ptr(), k, C.data_ptr(), m, N)
+    assert rc == oz.OK
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    for rep in range(3):
+        C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(C).T, ref), f"replay {rep}"
+        X, Y = gemm_inputs(120, 90, 150, seed=50 + rep)
+        assert np.array_equal(_call("noalloc", 64, X, Y, 12), os_ii(X, Y, 12))
+    assert oz.ozaki2_sync_status() == oz.OK
