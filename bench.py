@@ -151,11 +151,11 @@ def extras_measurement(torch, oz) -> dict:
 
 
 def complex_measurement(torch, oz, rng) -> dict:
-    """Complex FP64 4096^3 (ZGEMM emulation through the real embedding)
-    against native complex128 matmul: time, effective TFLOPS (8 m n k / t,
-    the real flops of a complex product) and sampled error relative to
-    (|Ar|+|Ai|)(|Br|+|Bi|) -- the real embedding's |A||B| -- for N = 14..17,
-    and the smallest N matching the native error."""
+    """Complex FP64 4096^3 (ZGEMM emulation through the real embedding, and
+    the 3-product form) against native complex128 matmul: time, effective
+    TFLOPS (8 m n k / t, the real flops of a complex product) and sampled
+    error relative to (|Ar|+|Ai|)(|Br|+|Bi|) -- the real embedding's |A||B|
+    -- for N = 14..17, and the smallest N matching the native error."""
     from workload import complex_gemm_inputs
     from workload.reference import ExactSamples
 
@@ -181,22 +181,26 @@ def complex_measurement(torch, oz, rng) -> dict:
     flops = 8.0 * n ** 3
     nat_ms = _time_ms(torch, lambda: torch.matmul(dA, dB), 3)
     nat_err = sampled(torch.matmul(dA, dB))
-    res = {}
+    res, res3 = {}, {}
     for N in (14, 15, 16, 17):
-        def emu():
-            r = oz.ozaki2_zgemm(n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, Ccm.data_ptr(), n, N)
-            if r != oz.OK:
-                raise oz.Ozaki2Error("ozaki2_zgemm", r)
+        for name, f, out in (("ozaki2_zgemm", oz.ozaki2_zgemm, res),
+                             ("ozaki2_zgemm3m", oz.ozaki2_zgemm3m, res3)):
+            def emu():
+                r = f(n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, Ccm.data_ptr(), n, N)
+                if r != oz.OK:
+                    raise oz.Ozaki2Error(name, r)
 
-        ms = _time_ms(torch, emu, 3)
-        res[str(N)] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
-                       "rel_err_sampled": sampled(Ccm.t())}
+            ms = _time_ms(torch, emu, 3)
+            out[str(N)] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                           "rel_err_sampled": sampled(Ccm.t())}
     matched = next((int(k) for k, v in res.items() if v["rel_err_sampled"] <= nat_err), None)
+    matched3 = next((int(k) for k, v in res3.items() if v["rel_err_sampled"] <= nat_err), None)
     del dA, dB, Acm, Bcm, Ccm
     torch.cuda.empty_cache()
     return {"workload": "complex FP64 4096^3, each part (U-0.5)exp(0.5 Z), seed 0",
             "native_ms": round(nat_ms, 3), "native_tflops": round(flops / (nat_ms * 1e-3) / 1e12, 2),
-            "native_rel_err_sampled": nat_err, "emulated": res, "matched_N": matched}
+            "native_rel_err_sampled": nat_err, "emulated": res, "matched_N": matched,
+            "emulated_3m": res3, "matched_N_3m": matched3}
 
 
 def certified_measurement(torch, oz, rng) -> list:

@@ -111,8 +111,27 @@ int ozaki2_zgemm(int m, int n, int k, const double *A, int lda, const double *B,
                  double *C, int ldc, int N);
 int ozaki2_cgemm(int m, int n, int k, const float *A, int lda, const float *B, int ldb, float *C,
                  int ldc, int N);
-/* Bytes of device workspace ozaki2_zgemm (prec 64) / ozaki2_cgemm (prec 32)
- * needs; 0 for arguments they would reject and for m, n or k == 0. */
+/*
+ * ozaki2_zgemm3m / ozaki2_cgemm3m - the same products with three real
+ * residue products per modulus instead of four (Gauss's identity):
+ * T1 = A'r B'r, T2 = A'i B'i, T3 = (A'r + A'i)(B'r + B'i), Re = T1 - T2,
+ * Im = T3 - T1 - T2, reduced mod p_l and rebuilt by the CRT of Algorithm 3.
+ * The three products share one shift per row of A and per column of B, so
+ * Algorithm 2 runs on the complex matrices as wholes: mu' is one lower than
+ * the real one and Abar = ceil(2^mu' |Ar|) + ceil(2^mu' |Ai|), so that
+ * Lemma 0 bounds (|A'r| + |A'i|)(|B'r| + |B'i|), hence both parts, below P/2.
+ * The results differ from ozaki2_zgemm's (other shifts); each part's error
+ * is bounded as stated in the library's documentation of this form.
+ *   k : 0 <= k < 2^19.  Other arguments as ozaki2_zgemm / ozaki2_cgemm.
+ */
+int ozaki2_zgemm3m(int m, int n, int k, const double *A, int lda, const double *B, int ldb,
+                   double *C, int ldc, int N);
+int ozaki2_cgemm3m(int m, int n, int k, const float *A, int lda, const float *B, int ldb,
+                   float *C, int ldc, int N);
+/* Bytes of device workspace the complex calls (prec 64: ozaki2_zgemm,
+ * ozaki2_zgemm3m; prec 32: ozaki2_cgemm, ozaki2_cgemm3m) need: the larger of
+ * the two forms (the 3-product form only, for k >= 2^18); 0 for arguments
+ * they would reject and for m, n or k == 0. */
 size_t ozaki2_complex_workspace_bytes(int prec, int m, int n, int k, int N);
 
 /*

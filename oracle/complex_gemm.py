@@ -87,8 +87,12 @@ def _split(X):
     return X.real.astype(np.float64), X.imag.astype(np.float64)
 
 
-def scaling_3m(A: np.ndarray, B: np.ndarray, N: int, table: str = "paper") -> dict:
-    """Algorithm 2 on complex A, B for the 3-product form (see above)."""
+def scaling_3m(A: np.ndarray, B: np.ndarray, N: int, table: str = "paper", rows=None,
+               cols=None) -> dict:
+    """Algorithm 2 on complex A, B for the 3-product form (see above).  With
+    `rows`/`cols` given, mu and the scaled parts are produced only for those
+    rows of A and columns of B (the maxima of Cbar are still taken over the
+    full matrices)."""
     from .constants import constants
     from .ozaki2 import exact_int_matmul, shift, to_int_objects
 
@@ -98,8 +102,9 @@ def scaling_3m(A: np.ndarray, B: np.ndarray, N: int, table: str = "paper") -> di
         raise ValueError("A and B must both be complex128 or both complex64")
     m, k = A.shape
     n = B.shape[1]
-    if 2 * k > 2 ** 19 - 1:
-        raise ValueError("k must be below 2^18 (three products share the real limit)")
+    from .constants import K_MAX_EXT
+    if k > K_MAX_EXT:
+        raise ValueError("k must be below 2^19 (Cbar <= 2^12 k as in the real method)")
     Ar, Ai = _split(A)
     Br, Bi = _split(B)
     if not all(np.all(np.isfinite(X)) for X in (Ar, Ai, Br, Bi)):
@@ -124,15 +129,24 @@ def scaling_3m(A: np.ndarray, B: np.ndarray, N: int, table: str = "paper") -> di
     mu_p, nu_p = mu_prime(mxA), mu_prime(mxB)
     Abar = bar(Ar, mu_p[:, None]) + bar(Ai, mu_p[:, None])
     Bbar = bar(Br, nu_p[None, :]) + bar(Bi, nu_p[None, :])
-    Cbar = exact_int_matmul(Abar, Bbar, 64.0 * 64.0 * max(k, 1))
-    rmax = Cbar.max(axis=1) if n else np.zeros(m, np.int64)
-    cmax = Cbar.max(axis=0) if m else np.zeros(n, np.int64)
-    mu = np.array([shift(mu_p[i], rmax[i], const) for i in range(m)], dtype=np.int64)
-    nu = np.array([shift(nu_p[j], cmax[j], const) for j in range(n)], dtype=np.int64)
+    bound = 64.0 * 64.0 * max(k, 1)
+    if rows is None and cols is None:
+        Cbar = exact_int_matmul(Abar, Bbar, bound)
+        rmax = Cbar.max(axis=1) if n else np.zeros(m, np.int64)
+        cmax = Cbar.max(axis=0) if m else np.zeros(n, np.int64)
+        rows, cols = np.arange(m), np.arange(n)
+    else:
+        rows = np.arange(m) if rows is None else np.asarray(rows)
+        cols = np.arange(n) if cols is None else np.asarray(cols)
+        rmax = exact_int_matmul(Abar[rows], Bbar, bound).max(axis=1)
+        cmax = exact_int_matmul(Abar, Bbar[:, cols], bound).max(axis=0)
+    mu = np.array([shift(mu_p[i], rmax[t], const) for t, i in enumerate(rows)], dtype=np.int64)
+    nu = np.array([shift(nu_p[j], cmax[t], const) for t, j in enumerate(cols)], dtype=np.int64)
     sc = lambda X, s: to_int_objects(np.trunc(np.ldexp(X, s.astype(np.int32))))
-    return dict(b=b, const=const, mu_p=mu_p, nu_p=nu_p, Abar=Abar, Bbar=Bbar, rmax=rmax,
-                cmax=cmax, mu=mu, nu=nu, Apr=sc(Ar, mu[:, None]), Api=sc(Ai, mu[:, None]),
-                Bpr=sc(Br, nu[None, :]), Bpi=sc(Bi, nu[None, :]))
+    return dict(b=b, const=const, rows=rows, cols=cols, mu_p=mu_p, nu_p=nu_p, Abar=Abar,
+                Bbar=Bbar, rmax=rmax, cmax=cmax, mu=mu, nu=nu,
+                Apr=sc(Ar[rows], mu[:, None]), Api=sc(Ai[rows], mu[:, None]),
+                Bpr=sc(Br[:, cols], nu[None, :]), Bpi=sc(Bi[:, cols], nu[None, :]))
 
 
 def residue_products_3m(st: dict) -> dict:
@@ -162,14 +176,15 @@ def residue_products_3m(st: dict) -> dict:
 
 
 def os_ii_complex_3m(A: np.ndarray, B: np.ndarray, N: int, stages: bool = False,
-                     table: str = "paper"):
-    """Complex C by the 3-product form (reading R25): Algorithm 2 as above,
-    three residue products per modulus, the CRT of Algorithm 3 on the real
-    and on the imaginary residues, and the inverse scaling of Algorithm 1."""
+                     table: str = "paper", rows=None, cols=None):
+    """Complex C (len(rows) x len(cols)) by the 3-product form (reading R25):
+    Algorithm 2 as above, three residue products per modulus, the CRT of
+    Algorithm 3 on the real and on the imaginary residues, and the inverse
+    scaling of Algorithm 1."""
     from .ozaki2 import crt_reconstruct, unscale
 
-    st = scaling_3m(A, B, N, table)
-    m, n = A.shape[0], B.shape[1]
+    st = scaling_3m(A, B, N, table, rows, cols)
+    m, n = len(st["rows"]), len(st["cols"])
     if A.shape[1] == 0 or m == 0 or n == 0:
         C = np.zeros((m, n), dtype=A.dtype)
         return (C, st) if stages else C

@@ -43,6 +43,8 @@ _SIGS = {
     "ozaki2_zgemm": ([_c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int], _c_int),
     "ozaki2_cgemm": ([_c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int], _c_int),
     "ozaki2_complex_workspace_bytes": ([_c_int, _c_int, _c_int, _c_int, _c_int], _c_size),
+    "ozaki2_zgemm3m": ([_c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int], _c_int),
+    "ozaki2_cgemm3m": ([_c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int], _c_int),
     "ozaki2_set_stream": ([_c_ptr], _c_int),
     "ozaki2_set_moduli_table": ([_c_int], _c_int),
     "ozaki2_moduli": ([_c_int, _c_int, ctypes.POINTER(_c_int)], _c_int),
@@ -127,6 +129,14 @@ def ozaki2_zgemm(m, n, k, A, lda, B, ldb, C, ldc, N):
 
 def ozaki2_cgemm(m, n, k, A, lda, B, ldb, C, ldc, N):
     return _call("ozaki2_cgemm", m, n, k, A, lda, B, ldb, C, ldc, N)
+
+
+def ozaki2_zgemm3m(m, n, k, A, lda, B, ldb, C, ldc, N):
+    return _call("ozaki2_zgemm3m", m, n, k, A, lda, B, ldb, C, ldc, N)
+
+
+def ozaki2_cgemm3m(m, n, k, A, lda, B, ldb, C, ldc, N):
+    return _call("ozaki2_cgemm3m", m, n, k, A, lda, B, ldb, C, ldc, N)
 
 
 def ozaki2_complex_workspace_bytes(prec, m, n, k, N):
@@ -293,17 +303,20 @@ def gemm(A, B, N: int, out=None):
     return Ccm.t()
 
 
-def zgemm(A, B, N: int):
+def zgemm(A, B, N: int, form: str = "4m"):
     """C = A @ B for complex CUDA tensors (complex128: ozaki2_zgemm,
-    complex64: ozaki2_cgemm).  Returns C (m x n), a transposed view of a
-    column-major buffer."""
+    complex64: ozaki2_cgemm; form="3m": ozaki2_zgemm3m / ozaki2_cgemm3m).
+    Returns C (m x n), a transposed view of a column-major buffer."""
     torch = _torch()
     m, k = A.shape
     n = B.shape[1]
     Acm, Bcm = col_major(A), col_major(B)
     Ccm = torch.empty((n, m), dtype=A.dtype, device=A.device)
     _set_current_stream()
-    f = ozaki2_zgemm if A.dtype == torch.complex128 else ozaki2_cgemm
+    if form == "3m":
+        f = ozaki2_zgemm3m if A.dtype == torch.complex128 else ozaki2_cgemm3m
+    else:
+        f = ozaki2_zgemm if A.dtype == torch.complex128 else ozaki2_cgemm
     rc = f(m, n, k, Acm.data_ptr(), max(m, 1), Bcm.data_ptr(), max(k, 1), Ccm.data_ptr(), max(m, 1), N)
     if rc != OK:
         raise Ozaki2Error("ozaki2_zgemm", rc)

@@ -469,9 +469,10 @@ ZLayout zlayout(int m, int n, int k, int N, size_t s) {
 }
 
 // Argument checks of the complex calls (leading dimensions in complex
-// elements); the embedded problem must be a valid real one.
+// elements).  kmax: the largest k of the form (the embedding doubles k; the
+// 3-product form keeps it).
 int check_complex_args(int m, int n, int k, const void* A, int lda, const void* B, int ldb,
-                       const void* C, int ldc) {
+                       const void* C, int ldc, int kmax) {
   if (m < 0 || n < 0 || k < 0 || m > kMaxDim / 2 || n > kMaxDim) return OZAKI2_ERR_INVALID_ARG;
   if (lda < (m > 1 ? m : 1) || ldb < (k > 1 ? k : 1) || ldc < (m > 1 ? m : 1))
     return OZAKI2_ERR_INVALID_ARG;
@@ -479,14 +480,14 @@ int check_complex_args(int m, int n, int k, const void* A, int lda, const void* 
   if ((size_t)m * k > 0 && !A) return OZAKI2_ERR_INVALID_ARG;
   if ((size_t)k * n > 0 && !B) return OZAKI2_ERR_INVALID_ARG;
   if ((size_t)m * n > 0 && !C) return OZAKI2_ERR_INVALID_ARG;
-  if (k > kMaxK / 2) return OZAKI2_ERR_K_RANGE;
+  if (k > kmax) return OZAKI2_ERR_K_RANGE;
   return OZAKI2_OK;
 }
 
 int zgemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
                void* C, int ldc, int N) {
   const int b = pr == Prec::F64 ? 64 : 32;
-  int rc = check_complex_args(m, n, k, A, lda, B, ldb, C, ldc);
+  int rc = check_complex_args(m, n, k, A, lda, B, ldb, C, ldc, kMaxK / 2);
   if (rc) return rc;
   if ((rc = check_N(N, b))) return rc;
   if (m == 0 || n == 0) return OZAKI2_OK;
@@ -507,6 +508,102 @@ int zgemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void*
                     Z.L, ws + Z.real, status, s, false);
   if (rc) return rc;
   launch_interleave_complex(s, pr, ws + Z.Ch, m, n, C, ldc);
+  return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
+}
+
+// The complex 3-product form (reading R25): one shift per row of A and per
+// column of B for both parts (Algorithm 2 on Abar = bar(Ar) + bar(Ai) with
+// mu' one lower), residues of A'r, A'i and A'r + A'i, three residue products
+// per modulus, W_re = mod(T1 - T2), W_im = mod(T3 - T1 - T2), the CRT on
+// each part and the inverse scaling.  Workspace: the four real planes, the
+// 2m x n real result, then the layout of the m x n x k problem with 3N
+// slices and 3N W (the three groups of N back to back).
+struct Z3Layout {
+  size_t Ar, Ai, Br, Bi, Ch, real, total;
+  Layout L;
+};
+
+Z3Layout z3layout(int m, int n, int k, int N, size_t s) {
+  Z3Layout Z;
+  Z.Ar = 0;
+  Z.Ai = rup(Z.Ar + s * (size_t)m * k, 256);
+  Z.Br = rup(Z.Ai + s * (size_t)m * k, 256);
+  Z.Bi = rup(Z.Br + s * (size_t)k * n, 256);
+  Z.Ch = rup(Z.Bi + s * (size_t)k * n, 256);
+  Z.real = rup(Z.Ch + s * 2 * (size_t)m * n, 256);
+  Z.L = layout(m, n, k, 3 * N, single_row_pad(m, n, N));
+  Z.total = Z.real + Z.L.total;
+  return Z;
+}
+
+int zgemm3m_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+                 void* C, int ldc, int N) {
+  const int b = pr == Prec::F64 ? 64 : 32;
+  int rc = check_complex_args(m, n, k, A, lda, B, ldb, C, ldc, kMaxK);
+  if (rc) return rc;
+  if ((rc = check_N(N, b))) return rc;
+  if (m == 0 || n == 0) return OZAKI2_OK;
+  hipStream_t s = g_stream;
+  if (k == 0) {
+    launch_fill_zero(s, pr, C, 2 * ldc, 2 * m, n);
+    return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
+  }
+  CrtConsts cc;
+  if ((rc = get_consts(N, b, &cc))) return rc;
+  const size_t es = pr == Prec::F64 ? 8 : 4;
+  const Z3Layout Z = z3layout(m, n, k, N, es);
+  char* ws;
+  int* status;
+  if ((rc = get_workspace(Z.total, &ws, &status))) return rc;
+  const Layout& L = Z.L;
+  char* w = ws + Z.real;
+  void *Ar = ws + Z.Ar, *Ai = ws + Z.Ai, *Br = ws + Z.Br, *Bi = ws + Z.Bi;
+  uint64_t* rowbits = at<uint64_t>(w, L.rowbits);
+  uint64_t* colbits = at<uint64_t>(w, L.colbits);
+  int* rmax = at<int>(w, L.rmax);
+  int* cmax = at<int>(w, L.cmax);
+  int* flag = at<int>(w, L.flag);
+  int* mu = at<int>(w, L.mu);
+  int* nu = at<int>(w, L.nu);
+  const size_t sa = (size_t)L.mp * L.kp, sb = (size_t)L.np * L.kp, sw = (size_t)L.np * L.mp;
+  int8_t* X[3] = {at<int8_t>(w, L.A), at<int8_t>(w, L.A) + N * sa, at<int8_t>(w, L.A) + 2 * N * sa};
+  int8_t* Y[3] = {at<int8_t>(w, L.B), at<int8_t>(w, L.B) + N * sb, at<int8_t>(w, L.B) + 2 * N * sb};
+  int8_t* W[3] = {at<int8_t>(w, L.W), at<int8_t>(w, L.W) + N * sw, at<int8_t>(w, L.W) + 2 * N * sw};
+  launch_split_complex(s, pr, A, lda, m, k, Ar, Ai);
+  launch_split_complex(s, pr, B, ldb, k, n, Br, Bi);
+  // Algorithm 2 on the complex matrices: abs-max over both parts (the two
+  // passes share the atomic maxima), bars summed over the parts.
+  launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
+  launch_absmax_rows(s, pr, Ar, m, m, k, rowbits, flag);
+  launch_absmax_rows(s, pr, Ai, m, m, k, rowbits, flag);
+  launch_absmax_cols(s, pr, Br, k, k, n, colbits, flag);
+  launch_absmax_cols(s, pr, Bi, k, k, n, colbits, flag);
+  launch_slices(s, pr, 2, true, Ar, m, m, k, L.mp, L.kp, rowbits, nullptr, cc, X[0]);
+  launch_slices(s, pr, 2, true, Ai, m, m, k, L.mp, L.kp, rowbits, nullptr, cc, X[1]);
+  launch_add_bars(s, X[0], X[1], X[2], sa);
+  launch_slices(s, pr, 2, false, Br, k, n, k, L.np, L.kp, colbits, nullptr, cc, Y[0]);
+  launch_slices(s, pr, 2, false, Bi, k, n, k, L.np, L.kp, colbits, nullptr, cc, Y[1]);
+  launch_add_bars(s, Y[0], Y[1], Y[2], sb);
+  launch_gemm_i8(s, 1, X[2], 0, Y[2], 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax);
+  launch_shifts(s, rowbits, rmax, m, colbits, cmax, n, cc.Pprime, cc.c, at<int>(w, L.mu_p),
+                at<int>(w, L.nu_p), mu, nu, nullptr, -1);
+  // Algorithm 3: residues of A'r, A'i and A'r + A'i (and of B), three
+  // residue products per modulus, the real and imaginary residues.
+  launch_slices(s, pr, 1, true, Ar, m, m, k, L.mp, L.kp, nullptr, mu, cc, X[0]);
+  launch_slices(s, pr, 1, true, Ai, m, m, k, L.mp, L.kp, nullptr, mu, cc, X[1]);
+  launch_sum_residues(s, X[0], X[1], X[2], sa, cc);
+  launch_slices(s, pr, 1, false, Br, k, n, k, L.np, L.kp, nullptr, nu, cc, Y[0]);
+  launch_slices(s, pr, 1, false, Bi, k, n, k, L.np, L.kp, nullptr, nu, cc, Y[1]);
+  launch_sum_residues(s, Y[0], Y[1], Y[2], sb, cc);
+  for (int q = 0; q < 3; ++q)
+    launch_gemm_i8(s, 0, X[q], sa, Y[q], sb, L.mp, L.np, L.kp, N, cc, W[q], sw, L.mp, nullptr,
+                   nullptr);
+  launch_combine_w(s, W[0], W[1], W[2], sw, cc);
+  char* Ch = ws + Z.Ch;
+  launch_crt(s, pr, W[0], sw, L.mp, mu, nu, m, n, cc, flag, Ch, 2 * m);
+  launch_crt(s, pr, W[1], sw, L.mp, mu, nu, m, n, cc, flag, Ch + es * m, 2 * m);
+  launch_interleave_complex(s, pr, Ch, m, n, C, ldc);
+  launch_or_status(s, flag, status);
   return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
 }
 
@@ -995,11 +1092,25 @@ int ozaki2_cgemm(int m, int n, int k, const float* A, int lda, const float* B, i
   return zgemm_impl(Prec::F32, m, n, k, A, lda, B, ldb, C, ldc, N);
 }
 
+int ozaki2_zgemm3m(int m, int n, int k, const double* A, int lda, const double* B, int ldb,
+                   double* C, int ldc, int N) {
+  return zgemm3m_impl(Prec::F64, m, n, k, A, lda, B, ldb, C, ldc, N);
+}
+
+int ozaki2_cgemm3m(int m, int n, int k, const float* A, int lda, const float* B, int ldb,
+                   float* C, int ldc, int N) {
+  return zgemm3m_impl(Prec::F32, m, n, k, A, lda, B, ldb, C, ldc, N);
+}
+
 size_t ozaki2_complex_workspace_bytes(int prec, int m, int n, int k, int N) {
   if ((prec != 64 && prec != 32) || m < 0 || n < 0 || k < 0) return 0;
-  if (m > kMaxDim / 2 || n > kMaxDim || k > kMaxK / 2 || check_N(N, prec) != OZAKI2_OK) return 0;
+  if (m > kMaxDim / 2 || n > kMaxDim || k > kMaxK || check_N(N, prec) != OZAKI2_OK) return 0;
   if (m == 0 || n == 0 || k == 0) return 0;
-  return zlayout(m, n, k, N, prec == 64 ? 8 : 4).total;
+  const size_t s = prec == 64 ? 8 : 4;
+  const size_t t3 = z3layout(m, n, k, N, s).total;
+  if (k > kMaxK / 2) return t3;   // only the 3-product form takes such k
+  const size_t t4 = zlayout(m, n, k, N, s).total;
+  return t3 > t4 ? t3 : t4;
 }
 
 int ozaki2_set_stream(void* stream) {

@@ -68,6 +68,80 @@ __global__ __launch_bounds__(kThreads) void k_interleave_c(const T* __restrict__
   }
 }
 
+// ---- the 3-product form (ozaki2_zgemm3m) ---------------------------------
+// Real and imaginary parts of an interleaved column-major matrix (rows x
+// cols, leading dimension ld complex elements) as two planes with leading
+// dimension `rows`.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_split(const T* __restrict__ X, int ld, int rows,
+                                                     int cols, T* __restrict__ re,
+                                                     T* __restrict__ im) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = t % rows, j = t / rows;
+    const T* x = X + 2 * (i + j * ld);
+    re[t] = x[0];
+    im[t] = x[1];
+  }
+}
+
+// Abar = (bar of the real part) + (bar of the imaginary part), each at most
+// 32, as INT8 (count bytes, a multiple of 16).
+__global__ __launch_bounds__(kThreads) void k_add_bars(const int8_t* __restrict__ a,
+                                                        const int8_t* __restrict__ b,
+                                                        int8_t* __restrict__ out, int64_t count) {
+  const int64_t n16 = count / 16;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < n16;
+       t += (int64_t)gridDim.x * kThreads) {
+    const int4 x = reinterpret_cast<const int4*>(a)[t], y = reinterpret_cast<const int4*>(b)[t];
+    // bytes in [0, 32]: lane-wise byte sums cannot carry into the next byte
+    int4 r;
+    r.x = x.x + y.x;
+    r.y = x.y + y.y;
+    r.z = x.z + y.z;
+    r.w = x.w + y.w;
+    reinterpret_cast<int4*>(out)[t] = r;
+  }
+}
+
+// mod(x, p) in the symmetric INT8 range for a small integer x (|x| < 3 p).
+__device__ inline int mod_small(int x, int p) {
+  int r = x % p;
+  if (r < 0) r += p;
+  return r >= (p + 1) / 2 ? r - p : r;
+}
+
+// Residues of A'r + A'i: slice l of X3 = mod(X1 + X2, p_l) (slices of `per`
+// bytes, N of them).
+__global__ __launch_bounds__(kThreads) void k_sum_residues(const int8_t* __restrict__ x1,
+                                                            const int8_t* __restrict__ x2,
+                                                            int8_t* __restrict__ x3, int64_t per,
+                                                            CrtConsts cc) {
+  const int64_t total = per * cc.N;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * kThreads) {
+    const int p = cc.p[t / per];
+    x3[t] = (int8_t)mod_small((int)x1[t] + (int)x2[t], p);
+  }
+}
+
+// W of the three products per modulus into the real and imaginary residues,
+// in place: W1 <- mod(W1 - W2, p), W2 <- mod(W3 - W1 - W2, p).
+__global__ __launch_bounds__(kThreads) void k_combine_w(int8_t* __restrict__ w1,
+                                                         int8_t* __restrict__ w2,
+                                                         const int8_t* __restrict__ w3, int64_t per,
+                                                         CrtConsts cc) {
+  const int64_t total = per * cc.N;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * kThreads) {
+    const int p = cc.p[t / per];
+    const int a = w1[t], b = w2[t], c = w3[t];
+    w1[t] = (int8_t)mod_small(a - b, p);
+    w2[t] = (int8_t)mod_small(c - a - b, p);
+  }
+}
+
 dim3 grid_for(int64_t total) {
   const int64_t b = (total + kThreads - 1) / kThreads;
   return dim3((unsigned)(b < kMaxBlocks ? (b > 0 ? b : 1) : kMaxBlocks));
@@ -85,6 +159,34 @@ void launch_embed_complex(hipStream_t s, Prec pr, const void* A, int lda, const 
     hipLaunchKernelGGL(k_embed_a<float>, ga, blk, 0, s, (const float*)A, lda, m, k, (float*)Ah);
     hipLaunchKernelGGL(k_embed_b<float>, gb, blk, 0, s, (const float*)B, ldb, k, n, (float*)Bh);
   }
+}
+
+void launch_split_complex(hipStream_t s, Prec pr, const void* X, int ld, int rows, int cols,
+                          void* re, void* im) {
+  const dim3 g = grid_for((int64_t)rows * cols), blk(kThreads);
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL(k_split<double>, g, blk, 0, s, (const double*)X, ld, rows, cols, (double*)re,
+                       (double*)im);
+  else
+    hipLaunchKernelGGL(k_split<float>, g, blk, 0, s, (const float*)X, ld, rows, cols, (float*)re,
+                       (float*)im);
+}
+
+void launch_add_bars(hipStream_t s, const int8_t* a, const int8_t* b, int8_t* out, size_t count) {
+  hipLaunchKernelGGL(k_add_bars, grid_for((int64_t)count / 16), dim3(kThreads), 0, s, a, b, out,
+                     (int64_t)count);
+}
+
+void launch_sum_residues(hipStream_t s, const int8_t* x1, const int8_t* x2, int8_t* x3, size_t per,
+                         const CrtConsts& cc) {
+  hipLaunchKernelGGL(k_sum_residues, grid_for((int64_t)per * cc.N), dim3(kThreads), 0, s, x1, x2,
+                     x3, (int64_t)per, cc);
+}
+
+void launch_combine_w(hipStream_t s, int8_t* w1, int8_t* w2, const int8_t* w3, size_t per,
+                      const CrtConsts& cc) {
+  hipLaunchKernelGGL(k_combine_w, grid_for((int64_t)per * cc.N), dim3(kThreads), 0, s, w1, w2, w3,
+                     (int64_t)per, cc);
 }
 
 void launch_interleave_complex(hipStream_t s, Prec pr, const void* Ch, int m, int n, void* C,

@@ -164,9 +164,11 @@ constexpr int kAbsBarWaveK = 2048;   // up to here one wave per column, else a w
 int absbar_group_blocks(int n_pad, int k_pad);
 void launch_absbar_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n, int n_pad,
                         int k_pad, uint64_t* colbits, int* flag, int8_t* out);
+// bias: added to mu' and nu' of nonzero rows and columns (0 for Algorithm 2;
+// -1 for the complex 3-product form, whose bars sum two parts).
 void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int m,
                    const uint64_t* colbits, const int* cmax, int n, float Pprime, float c,
-                   int* mu_p, int* nu_p, int* mu, int* nu, float* ef);
+                   int* mu_p, int* nu_p, int* mu, int* nu, float* ef, int bias = 0);
 void launch_log2f(hipStream_t s, const float* d, float* out, int count);
 
 // Tuning and test knobs (ozaki2_debug_tuning): a cap on the workgroups of a
@@ -183,6 +185,7 @@ void init_slice_launch(int dev);
 //   src element (r, h) is at  trans ? src[r + h*ld] : src[h + r*ld].
 //   mode 0 (bar):     S = 1, byte = ceil(2^shift |x|) (>= 1 if x != 0),
 //                     shift = mu' computed from `bits` (row abs-max bit patterns)
+//   mode 2 (bar):     mode 0 with shift = mu' - 1 (the complex 3-product form)
 //   mode 1 (residue): S = N, byte_l = mod(trunc(2^shift x), p_l), shift from `shift`
 void launch_slices(hipStream_t s, Prec pr, int mode, bool trans, const void* src, int ld, int rows,
                    int k, int rows_pad, int k_pad, const uint64_t* bits, const int* shift,
@@ -273,6 +276,18 @@ void launch_embed_complex(hipStream_t s, Prec pr, const void* A, int lda, const 
                           int m, int n, int k, void* Ah, void* Bh);
 void launch_interleave_complex(hipStream_t s, Prec pr, const void* Ch, int m, int n, void* C,
                                int ldc);
+// The 3-product form: real and imaginary planes of an interleaved matrix
+// (leading dimension `rows` each); Abar as the sum of two INT8 bars (count a
+// multiple of 16); slice l of x3 = mod(x1 + x2, p_l) over N slices of `per`
+// bytes; and the real and imaginary residues from the three products,
+// W1 <- mod(W1 - W2, p_l), W2 <- mod(W3 - W1 - W2, p_l), in place.
+void launch_split_complex(hipStream_t s, Prec pr, const void* X, int ld, int rows, int cols,
+                          void* re, void* im);
+void launch_add_bars(hipStream_t s, const int8_t* a, const int8_t* b, int8_t* out, size_t count);
+void launch_sum_residues(hipStream_t s, const int8_t* x1, const int8_t* x2, int8_t* x3, size_t per,
+                         const CrtConsts& cc);
+void launch_combine_w(hipStream_t s, int8_t* w1, int8_t* w2, const int8_t* w3, size_t per,
+                      const CrtConsts& cc);
 
 // api.cpp: Algorithm 1 for one problem on a workspace of `cap` bytes that
 // `get` supplies, with its sticky status word; checks the arguments and the

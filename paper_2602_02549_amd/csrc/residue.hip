@@ -183,7 +183,7 @@ __device__ __forceinline__ void tile_loads(const T* __restrict__ src, int ld, in
 template <int MODE>
 __device__ __forceinline__ int64_t row_aux(const void* __restrict__ aux, int rows, int r0) {
   const int rg = min(r0 + (int)(threadIdx.x >> 3), rows - 1);
-  if (MODE == 0) return (int64_t)static_cast<const uint64_t*>(aux)[rg];
+  if (MODE != 1) return (int64_t)static_cast<const uint64_t*>(aux)[rg];
   return static_cast<const int*>(aux)[rg];
 }
 
@@ -284,8 +284,8 @@ __device__ __forceinline__ void tile_finish(const double* tile, int64_t aux, int
   }
   int8_t* dst = out + (size_t)rg * k_pad + h0 + 16 * c;
 
-  if (MODE == 0) {
-    const int sh = rg < rows ? shift_prime_bits((uint64_t)aux) : 0;
+  if (MODE != 1) {
+    const int sh = rg < rows ? shift_prime_bits((uint64_t)aux) - (MODE == 2 ? 1 : 0) : 0;
     int b[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -570,7 +570,7 @@ struct SliceLaunch {
 
 template <typename T, bool TR, int MODE, int PATH>
 void launch_one(hipStream_t s, const SliceLaunch<T>& L, const CrtConsts& cc) {
-  const int variant = MODE == 0 ? 0 : 1 + PATH;
+  const int variant = MODE != 1 ? 0 : 1 + PATH;   // mode 2 has mode 0's resources
   const dim3 grid((unsigned)slice_grid(std::is_same<T, float>::value, TR, variant, L.tiles));
   hipLaunchKernelGGL((k_slices<T, TR, MODE, PATH>), grid, dim3(256), 0, s, L.src, L.ld, L.rows,
                      L.k, L.k_pad, L.gy, L.tiles, L.slice, L.aux, cc, L.out);
@@ -580,6 +580,10 @@ template <typename T, bool TR>
 void launch_side(hipStream_t s, int mode, const SliceLaunch<T>& L, const CrtConsts& cc) {
   if (mode == 0) {
     launch_one<T, TR, 0, kAnyPath>(s, L, cc);
+    return;
+  }
+  if (mode == 2) {
+    launch_one<T, TR, 2, kAnyPath>(s, L, cc);
     return;
   }
   switch (residue_path(cc)) {
@@ -601,10 +605,10 @@ void launch_t(hipStream_t s, int mode, bool trans, const T* src, int ld, int row
   L.rows = rows;
   L.k = k;
   L.k_pad = k_pad;
-  L.gy = mode == 0 ? rows_pad / kTR : cdiv_i(rows, kTR);
+  L.gy = mode != 1 ? rows_pad / kTR : cdiv_i(rows, kTR);
   L.tiles = (k_pad / kTK) * L.gy;
   L.slice = (size_t)rows_pad * k_pad;
-  L.aux = mode == 0 ? (const void*)bits : (const void*)shift;
+  L.aux = mode != 1 ? (const void*)bits : (const void*)shift;
   L.out = out;
   if (L.tiles <= 0) return;
   if (trans)

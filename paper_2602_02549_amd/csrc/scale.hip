@@ -294,13 +294,13 @@ __device__ __forceinline__ void shifts_body(const uint64_t* __restrict__ rowbits
                                    const int* __restrict__ cmax, int n, float Pprime, float c,
                                    int* __restrict__ mu_p, int* __restrict__ nu_p,
                                    int* __restrict__ mu, int* __restrict__ nu,
-                                   float* __restrict__ ef, int t) {
+                                   float* __restrict__ ef, int t, int bias = 0) {
   if (t >= m + n) return;
   const bool row = t < m;
   const int idx = row ? t : t - m;
   const uint64_t bits = row ? rowbits[idx] : colbits[idx];
   const int M = row ? rmax[idx] : cmax[idx];
-  const int sp = shift_prime_bits(bits);
+  const int sp = shift_prime_bits(bits) + (bits ? bias : 0);
   const float d = single_up_int(M > 1 ? M : 1);       // R7: a zero maximum is treated as 1
   const float e = log2f_rn(d);
   const int s = sp + floor_fma(c, e, Pprime);
@@ -320,9 +320,10 @@ __global__ __launch_bounds__(256) void k_shifts(const uint64_t* __restrict__ row
                                                 const int* __restrict__ cmax, int n, float Pprime,
                                                 float c, int* __restrict__ mu_p,
                                                 int* __restrict__ nu_p, int* __restrict__ mu,
-                                                int* __restrict__ nu, float* __restrict__ ef) {
+                                                int* __restrict__ nu, float* __restrict__ ef,
+                                                int bias) {
   shifts_body(rowbits, rmax, m, colbits, cmax, n, Pprime, c, mu_p, nu_p, mu, nu, ef,
-              blockIdx.x * 256 + threadIdx.x);
+              blockIdx.x * 256 + threadIdx.x, bias);
 }
 
 // ---- grouped versions ------------------------------------------------------
@@ -428,9 +429,9 @@ void launch_absbar_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, i
 
 void launch_shifts(hipStream_t s, const uint64_t* rowbits, const int* rmax, int m,
                    const uint64_t* colbits, const int* cmax, int n, float Pprime, float c,
-                   int* mu_p, int* nu_p, int* mu, int* nu, float* ef) {
+                   int* mu_p, int* nu_p, int* mu, int* nu, float* ef, int bias) {
   hipLaunchKernelGGL(k_shifts, dim3(cdiv(m + n, 256)), dim3(256), 0, s, rowbits, rmax, m, colbits,
-                     cmax, n, Pprime, c, mu_p, nu_p, mu, nu, ef);
+                     cmax, n, Pprime, c, mu_p, nu_p, mu, nu, ef, bias);
 }
 
 void launch_log2f(hipStream_t s, const float* d, float* out, int count) {

@@ -125,8 +125,28 @@ def test_complex_argument_errors_and_workspace():
     got = q(64, 300, 200, 250, 14)
     assert got >= real + 8 * (4 * 300 * 250 + 2 * 250 * 200 + 2 * 300 * 200)
     assert q(32, 300, 200, 250, 14) < got
-    assert q(64, 300, 200, 2 ** 18, 14) == 0 and q(64, 300, 200, 2 ** 18 - 1, 14) > 0
+    # k >= 2^18 is served by the 3-product form only; k >= 2^19 by neither
+    assert q(64, 300, 200, 2 ** 19, 14) == 0 and q(64, 300, 200, 2 ** 19 - 1, 14) > 0
+    assert q(64, 300, 200, 2 ** 18, 14) > 0
     assert q(32, 300, 200, 250, 17) == 0 and q(64, 0, 4, 4, 14) == 0
+
+
+def test_complex3m_argument_errors_and_workspace():
+    # Host-side checks of ozaki2_zgemm3m / ozaki2_cgemm3m (nothing reaches a device).
+    z, c, q = oz.ozaki2_zgemm3m, oz.ozaki2_cgemm3m, oz.ozaki2_complex_workspace_bytes
+    assert z(4, 4, 4, FAKE, 3, FAKE, 4, FAKE, 4, 10) == oz.ERR_INVALID_ARG     # lda < m
+    assert z(4, 4, 4, FAKE, 4, FAKE, 3, FAKE, 4, 10) == oz.ERR_INVALID_ARG     # ldb < k
+    assert z(4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 3, 10) == oz.ERR_INVALID_ARG     # ldc < m
+    assert z(4, 4, 4, FAKE, 4, None, 4, FAKE, 4, 10) == oz.ERR_INVALID_ARG
+    assert z(4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 1) == oz.ERR_N_RANGE
+    assert c(4, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 17) == oz.ERR_N_RANGE
+    assert z(4, 4, 2 ** 19, FAKE, 4, FAKE, 2 ** 19, FAKE, 4, 10) == oz.ERR_K_RANGE
+    assert c(-1, 4, 4, FAKE, 4, FAKE, 4, FAKE, 4, 10) == oz.ERR_INVALID_ARG
+    assert z(4, 0, 4, FAKE, 4, None, 4, None, 4, 10) == oz.OK
+    # 3 INT32 product planes per modulus instead of the embedded 2m x n
+    # plane; the query covers both forms
+    four = q(64, 300, 200, 250, 14)
+    assert four > 0 and q(64, 300, 200, 2 ** 18 + 5, 14) > four
 
 
 def test_debug_and_log2f_argument_errors():

@@ -248,3 +248,11 @@ def test_3m_planted_mistake_is_caught(monkeypatch, mistake):
     monkeypatch.setattr(cg, "residue_products_3m", wrong)
     A, B = complex_gemm_inputs(4, 3, 5, phi=1.0, seed=3)
     assert check_3m(A, B, 14) != []
+
+
+def test_3m_sampled_rows_and_cols_match_full():
+    A, B = complex_gemm_inputs(9, 7, 11, phi=1.0, seed=19)
+    full = cg.os_ii_complex_3m(A, B, 13)
+    rows, cols = np.array([0, 4, 8]), np.array([2, 6])
+    got = cg.os_ii_complex_3m(A, B, 13, rows=rows, cols=cols)
+    assert np.array_equal(got, full[np.ix_(rows, cols)])
