@@ -576,8 +576,8 @@ int zgemm3m_impl(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
   launch_absmax_rows(s, pr, Ar, m, m, k, rowbits, flag);
   launch_absmax_rows(s, pr, Ai, m, m, k, rowbits, flag);
-  launch_absmax_cols(s, pr, Br, k, k, n, colbits, flag);
-  launch_absmax_cols(s, pr, Bi, k, k, n, colbits, flag);
+  launch_absmax_cols(s, pr, Br, k, k, n, colbits, flag, true);
+  launch_absmax_cols(s, pr, Bi, k, k, n, colbits, flag, true);
   launch_slices(s, pr, 2, true, Ar, m, m, k, L.mp, L.kp, rowbits, nullptr, cc, X[0]);
   launch_slices(s, pr, 2, true, Ai, m, m, k, L.mp, L.kp, rowbits, nullptr, cc, X[1]);
   launch_add_bars(s, X[0], X[1], X[2], sa);

@@ -105,40 +105,88 @@ __global__ __launch_bounds__(kThreads) void k_add_bars(const int8_t* __restrict_
   }
 }
 
-// mod(x, p) in the symmetric INT8 range for a small integer x (|x| < 3 p).
-__device__ inline int mod_small(int x, int p) {
-  int r = x % p;
-  if (r < 0) r += p;
-  return r >= (p + 1) / 2 ? r - p : r;
+// mod(x, p) in the symmetric INT8 range of Section 1.2 ([-(p-1)/2, (p-1)/2]
+// for odd p, [-128, 127] for p = 256; hi = (p - 1) / 2) for |x| < 2^10: the
+// FP32 quotient x (1/p) is within 2^-13 of x/p, so its rounding is within
+// one of the nearest quotient, and one correction either way lands r in the
+// range.
+__device__ inline int mod_small(int x, int p, float pinv, int hi) {
+  int r = x - (int)rintf((float)x * pinv) * p;
+  r -= r > hi ? p : 0;
+  r += r < hi + 1 - p ? p : 0;
+  return r;
 }
 
-// Residues of A'r + A'i: slice l of X3 = mod(X1 + X2, p_l) (slices of `per`
-// bytes, N of them).
+// Signed byte i of a 32-bit word.
+__device__ inline int sbyte(uint32_t w, int i) { return (int)(w << (24 - 8 * i)) >> 24; }
+
+struct SmallMod {
+  int p, hi;
+  float pinv;
+  __device__ explicit SmallMod(const CrtConsts& cc, int l)
+      : p(cc.p[l]), hi((cc.p[l] - 1) / 2), pinv((float)cc.pinv[l]) {}
+  __device__ uint32_t byte(int x, int i) const {
+    return (uint32_t)(mod_small(x, p, pinv, hi) & 0xFF) << (8 * i);
+  }
+};
+
+// Residues of A'r + A'i: slice l of X3 = mod(X1 + X2, p_l), N slices of
+// 16 * per16 bytes; workgroup row blockIdx.y is slice l, 16 bytes a thread.
 __global__ __launch_bounds__(kThreads) void k_sum_residues(const int8_t* __restrict__ x1,
                                                             const int8_t* __restrict__ x2,
-                                                            int8_t* __restrict__ x3, int64_t per,
+                                                            int8_t* __restrict__ x3, int64_t per16,
                                                             CrtConsts cc) {
-  const int64_t total = per * cc.N;
-  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total;
+  const int l = blockIdx.y;
+  const SmallMod md(cc, l);
+  const uint4* a = reinterpret_cast<const uint4*>(x1) + l * per16;
+  const uint4* b = reinterpret_cast<const uint4*>(x2) + l * per16;
+  uint4* c = reinterpret_cast<uint4*>(x3) + l * per16;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < per16;
        t += (int64_t)gridDim.x * kThreads) {
-    const int p = cc.p[t / per];
-    x3[t] = (int8_t)mod_small((int)x1[t] + (int)x2[t], p);
+    const uint4 u = a[t], v = b[t];
+    const uint32_t uw[4] = {u.x, u.y, u.z, u.w}, vw[4] = {v.x, v.y, v.z, v.w};
+    uint32_t r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      r[q] = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r[q] |= md.byte(sbyte(uw[q], i) + sbyte(vw[q], i), i);
+    }
+    c[t] = make_uint4(r[0], r[1], r[2], r[3]);
   }
 }
 
 // W of the three products per modulus into the real and imaginary residues,
-// in place: W1 <- mod(W1 - W2, p), W2 <- mod(W3 - W1 - W2, p).
+// in place: W1 <- mod(W1 - W2, p), W2 <- mod(W3 - W1 - W2, p) (layout as
+// k_sum_residues).
 __global__ __launch_bounds__(kThreads) void k_combine_w(int8_t* __restrict__ w1,
                                                          int8_t* __restrict__ w2,
-                                                         const int8_t* __restrict__ w3, int64_t per,
-                                                         CrtConsts cc) {
-  const int64_t total = per * cc.N;
-  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total;
+                                                         const int8_t* __restrict__ w3,
+                                                         int64_t per16, CrtConsts cc) {
+  const int l = blockIdx.y;
+  const SmallMod md(cc, l);
+  uint4* a = reinterpret_cast<uint4*>(w1) + l * per16;
+  uint4* b = reinterpret_cast<uint4*>(w2) + l * per16;
+  const uint4* c = reinterpret_cast<const uint4*>(w3) + l * per16;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < per16;
        t += (int64_t)gridDim.x * kThreads) {
-    const int p = cc.p[t / per];
-    const int a = w1[t], b = w2[t], c = w3[t];
-    w1[t] = (int8_t)mod_small(a - b, p);
-    w2[t] = (int8_t)mod_small(c - a - b, p);
+    const uint4 u = a[t], v = b[t], z = c[t];
+    const uint32_t uw[4] = {u.x, u.y, u.z, u.w}, vw[4] = {v.x, v.y, v.z, v.w},
+                   zw[4] = {z.x, z.y, z.z, z.w};
+    uint32_t re[4], im[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      re[q] = 0;
+      im[q] = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t1 = sbyte(uw[q], i), t2 = sbyte(vw[q], i), t3 = sbyte(zw[q], i);
+        re[q] |= md.byte(t1 - t2, i);
+        im[q] |= md.byte(t3 - t1 - t2, i);
+      }
+    }
+    a[t] = make_uint4(re[0], re[1], re[2], re[3]);
+    b[t] = make_uint4(im[0], im[1], im[2], im[3]);
   }
 }
 
@@ -177,16 +225,24 @@ void launch_add_bars(hipStream_t s, const int8_t* a, const int8_t* b, int8_t* ou
                      (int64_t)count);
 }
 
+// Grid of the slice-wise byte kernels: N rows of workgroups, each row
+// covering one slice of per / 16 chunks (per is a multiple of 16: slices are
+// padded to whole tiles).
+dim3 byte_slice_grid(size_t per, int N) {
+  const int64_t b = ((int64_t)(per / 16) + kThreads - 1) / kThreads;
+  return dim3((unsigned)(b < 1024 ? (b > 0 ? b : 1) : 1024), (unsigned)N);
+}
+
 void launch_sum_residues(hipStream_t s, const int8_t* x1, const int8_t* x2, int8_t* x3, size_t per,
                          const CrtConsts& cc) {
-  hipLaunchKernelGGL(k_sum_residues, grid_for((int64_t)per * cc.N), dim3(kThreads), 0, s, x1, x2,
-                     x3, (int64_t)per, cc);
+  hipLaunchKernelGGL(k_sum_residues, byte_slice_grid(per, cc.N), dim3(kThreads), 0, s, x1, x2, x3,
+                     (int64_t)(per / 16), cc);
 }
 
 void launch_combine_w(hipStream_t s, int8_t* w1, int8_t* w2, const int8_t* w3, size_t per,
                       const CrtConsts& cc) {
-  hipLaunchKernelGGL(k_combine_w, grid_for((int64_t)per * cc.N), dim3(kThreads), 0, s, w1, w2, w3,
-                     (int64_t)per, cc);
+  hipLaunchKernelGGL(k_combine_w, byte_slice_grid(per, cc.N), dim3(kThreads), 0, s, w1, w2, w3,
+                     (int64_t)(per / 16), cc);
 }
 
 void launch_interleave_complex(hipStream_t s, Prec pr, const void* Ch, int m, int n, void* C,

@@ -155,8 +155,10 @@ void launch_init(hipStream_t s, uint64_t* rowbits, int m_pad, uint64_t* colbits,
                  int* rmax, int* cmax, int* flag);
 void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, int k,
                         uint64_t* rowbits, int* flag);
+// accumulate: merge into the maxima already in colbits (atomicMax) instead of
+// storing them.
 void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,
-                        uint64_t* colbits, int* flag);
+                        uint64_t* colbits, int* flag, bool accumulate = false);
 // Abs-max of the columns of B and Bbar (slice 0, K-major [n_pad][k_pad]) in
 // one read of B; for k_pad <= kAbsBarMaxK.
 constexpr int kAbsBarMaxK = 8192;

@@ -71,8 +71,10 @@ __global__ __launch_bounds__(256) void k_absmax_rows(const T* __restrict__ A, in
 
 // B column-major (k x n): one wave per column j (four columns per
 // workgroup), 16 loads in flight per lane; the wave's maximum is stored
-// directly (the wave owns the column).
-template <typename T>
+// directly (the wave owns the column), or with ACC merged into the maximum
+// already there (atomicMax: the complex 3-product form takes one maximum
+// over the real and the imaginary part in two passes).
+template <typename T, bool ACC = false>
 __device__ __forceinline__ void absmax_cols_body(const T* __restrict__ B, int ldb, int k, int n,
                                         uint64_t* __restrict__ colbits, int* __restrict__ flag,
                                         int wg) {
@@ -97,15 +99,19 @@ __device__ __forceinline__ void absmax_cols_body(const T* __restrict__ B, int ld
   }
   if (lane == 0) {
     if ((mx & kExpMask) == kExpMask) atomicOr(flag, 1);
-    colbits[j] = mx;
+    if constexpr (ACC) {
+      if (mx) atomicMax((unsigned long long*)&colbits[j], (unsigned long long)mx);
+    } else {
+      colbits[j] = mx;
+    }
   }
 }
 
-template <typename T>
+template <typename T, bool ACC>
 __global__ __launch_bounds__(256) void k_absmax_cols(const T* __restrict__ B, int ldb, int k, int n,
                                                      uint64_t* __restrict__ colbits,
                                                      int* __restrict__ flag) {
-  absmax_cols_body<T>(B, ldb, k, n, colbits, flag, blockIdx.x);
+  absmax_cols_body<T, ACC>(B, ldb, k, n, colbits, flag, blockIdx.x);
 }
 
 // B column-major (k x n) with k_pad <= kAbsBarMaxK: the abs-max pass and the
@@ -403,14 +409,23 @@ void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, i
 }
 
 void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,
-                        uint64_t* colbits, int* flag) {
+                        uint64_t* colbits, int* flag, bool accumulate) {
   dim3 grid((unsigned)absmax_cols_blocks(n));
-  if (pr == Prec::F64)
-    hipLaunchKernelGGL(k_absmax_cols<double>, grid, dim3(256), 0, s, (const double*)B, ldb, k, n,
-                       colbits, flag);
-  else
-    hipLaunchKernelGGL(k_absmax_cols<float>, grid, dim3(256), 0, s, (const float*)B, ldb, k, n,
-                       colbits, flag);
+  if (pr == Prec::F64) {
+    if (accumulate)
+      hipLaunchKernelGGL((k_absmax_cols<double, true>), grid, dim3(256), 0, s, (const double*)B,
+                         ldb, k, n, colbits, flag);
+    else
+      hipLaunchKernelGGL((k_absmax_cols<double, false>), grid, dim3(256), 0, s, (const double*)B,
+                         ldb, k, n, colbits, flag);
+  } else {
+    if (accumulate)
+      hipLaunchKernelGGL((k_absmax_cols<float, true>), grid, dim3(256), 0, s, (const float*)B, ldb,
+                         k, n, colbits, flag);
+    else
+      hipLaunchKernelGGL((k_absmax_cols<float, false>), grid, dim3(256), 0, s, (const float*)B,
+                         ldb, k, n, colbits, flag);
+  }
 }
 
 int absbar_group_blocks(int n_pad, int k_pad) { return absbar_blocks(n_pad, k_pad); }
