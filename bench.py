@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--vendor-int8", action="store_true",
                     help="also time the vendor INT8 GEMM (torch._int_mm, hipBLASLt) at size^3: "
                          "context for the INT8 roofline of the residue products")
+    ap.add_argument("--complex", type=int, default=0, metavar="SIZE",
+                    help="only measure complex FP64 SIZE^3 (ozaki2_zgemm and ozaki2_zgemm3m, "
+                         "N = 14..17, against native complex128) and print it as one JSON object")
     ap.add_argument("--extras", action="store_true",
                     help="also measure the 4096^3 phi sweep (N from the bound at 1e-15), the "
                          "certified call at 1e-14 on the same inputs, and the FP32 16384^3 "
@@ -150,8 +153,8 @@ def extras_measurement(torch, oz) -> dict:
     return out
 
 
-def complex_measurement(torch, oz, rng) -> dict:
-    """Complex FP64 4096^3 (ZGEMM emulation through the real embedding, and
+def complex_measurement(torch, oz, rng, n: int = 4096) -> dict:
+    """Complex FP64 n^3 (ZGEMM emulation through the real embedding, and
     the 3-product form) against native complex128 matmul: time, effective
     TFLOPS (8 m n k / t, the real flops of a complex product) and sampled
     error relative to (|Ar|+|Ai|)(|Br|+|Bi|) -- the real embedding's |A||B|
@@ -160,7 +163,6 @@ def complex_measurement(torch, oz, rng) -> dict:
     from workload.reference import ExactSamples
 
     dev = torch.device("cuda:0")
-    n = 4096
     A, B = complex_gemm_inputs(n, n, n, phi=0.5, seed=0)
     rows = np.sort(rng.choice(n, 8, replace=False))
     cols = np.sort(rng.choice(n, 8, replace=False))
@@ -197,7 +199,7 @@ def complex_measurement(torch, oz, rng) -> dict:
     matched3 = next((int(k) for k, v in res3.items() if v["rel_err_sampled"] <= nat_err), None)
     del dA, dB, Acm, Bcm, Ccm
     torch.cuda.empty_cache()
-    return {"workload": "complex FP64 4096^3, each part (U-0.5)exp(0.5 Z), seed 0",
+    return {"workload": f"complex FP64 {n}^3, each part (U-0.5)exp(0.5 Z), seed 0",
             "native_ms": round(nat_ms, 3), "native_tflops": round(flops / (nat_ms * 1e-3) / 1e12, 2),
             "native_rel_err_sampled": nat_err, "emulated": res, "matched_N": matched,
             "emulated_3m": res3, "matched_N_3m": matched3}
@@ -473,6 +475,11 @@ def main():
     from workload.reference import ExactSamples
 
     dev = torch.device("cuda:0")
+    if args.complex:
+        oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        res = complex_measurement(torch, oz, np.random.default_rng(4321), args.complex)
+        print(json.dumps({"complex": res}), flush=True)
+        return
     m = n = k = args.size
     A, B = gemm_inputs(m, n, k, phi=0.5, seed=0)
     dA = torch.from_numpy(A).to(dev)

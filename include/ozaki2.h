@@ -72,6 +72,11 @@ typedef enum {
  * k == 0 writes C = 0; m == 0 or n == 0 does nothing.
  * If an input entry is non-finite every entry of C is set to NaN and
  * ozaki2_sync_status later returns OZAKI2_ERR_NONFINITE.
+ * Split-k: when C has too few output tiles to occupy the GPU and k is long,
+ * the scaling product and the residue products run over k ranges in
+ * parallel; the partial products are combined exactly (mod p_l for the
+ * residue products, as INT32 sums for Cbar), so the results are the same
+ * bits.  The workspace includes room for the partials.
  * Returns OZAKI2_OK or an argument / HIP error.
  */
 int ozaki2_gemm(int m, int n, int k, const double *A, int lda, const double *B, int ldb,
@@ -342,6 +347,9 @@ const char *ozaki2_profile_name(int phase);
  *   OZAKI2_KNOB_BATCH_PERSIST    : batched residue products: -1 = autotune
  *                                  (default), 0 = one workgroup per tile,
  *                                  1 = persistent workgroups
+ *   OZAKI2_KNOB_SPLIT_K          : single-problem products: 0 = split k
+ *                                  when few output tiles would leave the
+ *                                  compute units idle (default), 1 = never
  * Returns OZAKI2_OK, or OZAKI2_ERR_INVALID_ARG for an unknown knob or value.
  */
 enum {
@@ -349,7 +357,8 @@ enum {
   OZAKI2_KNOB_GEMM_TILE = 1,
   OZAKI2_KNOB_BATCH_SPLIT = 2,
   OZAKI2_KNOB_BATCH_GRAPH = 3,
-  OZAKI2_KNOB_BATCH_PERSIST = 4
+  OZAKI2_KNOB_BATCH_PERSIST = 4,
+  OZAKI2_KNOB_SPLIT_K = 5
 };
 int ozaki2_debug_tuning(int knob, int value, int *previous);
 

@@ -69,6 +69,7 @@ _SIGS = {
 }
 
 KNOB_SLICE_WORKGROUPS, KNOB_GEMM_TILE, KNOB_BATCH_SPLIT, KNOB_BATCH_GRAPH, KNOB_BATCH_PERSIST = 0, 1, 2, 3, 4
+KNOB_SPLIT_K = 5
 
 
 class Ozaki2Error(RuntimeError):

@@ -93,7 +93,8 @@ size_t rup(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   int mp, np, kp;
-  size_t rowbits, colbits, rmax, cmax, mu_p, nu_p, mu, nu, ef, flag, A, B, W, total;
+  size_t rowbits, colbits, rmax, cmax, mu_p, nu_p, mu, nu, ef, flag, A, B, W, part, part_bytes,
+      total;
 };
 
 // Row padding of one problem's layout.  The products use 256x256 tiles when
@@ -119,7 +120,9 @@ int batch_row_pad(int m, int n) {
   return (8 * a256 <= 9 * a128 && a256 >= 4 * 256 * 256) ? 256 : 128;
 }
 
-Layout layout(int m, int n, int k, int N, int pad) {
+// split_nz > 0: room for the split-k partials of the scaling product and of
+// residue-product launches of split_nz slices (single-problem calls).
+Layout layout(int m, int n, int k, int N, int pad, int split_nz = 0) {
   Layout L;
   L.mp = (int)rup((size_t)(m > 0 ? m : 1), pad);
   L.np = (int)rup((size_t)(n > 0 ? n : 1), pad);
@@ -143,6 +146,8 @@ Layout layout(int m, int n, int k, int N, int pad) {
   L.A = take((size_t)N * L.mp * L.kp);
   L.B = take((size_t)N * L.np * L.kp);
   L.W = take((size_t)N * L.np * L.mp);
+  L.part_bytes = split_nz > 0 ? split_scratch_bytes(L.mp, L.np, L.kp, split_nz) : 0;
+  L.part = take(L.part_bytes);
   L.total = off;
   return L;
 }
@@ -283,11 +288,21 @@ struct PreScale {
   int* flag;
 };
 
+// Output of the real embedding of a complex product (m even): rows i and
+// m/2 + i of the real result are the real and imaginary parts of row i of
+// the complex C (ldc in complex elements), which the CRT writes as pairs.
+struct ComplexOut {
+  void* C;
+  int ldc;
+};
+
 // The launch sequence of Algorithm 1 for one problem (m, n, k >= 1).  With
-// `pre`, the scaling pass is taken from there and not run again.
+// `pre`, the scaling pass is taken from there and not run again; with `zc`,
+// the result goes to the complex C described there (C, ldc unused).
 int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
                  void* C, int ldc, const CrtConsts& cc, const Layout& L, char* ws, int* status,
-                 hipStream_t s, bool want_ef, const PreScale* pre = nullptr) {
+                 hipStream_t s, bool want_ef, const PreScale* pre = nullptr,
+                 const ComplexOut* zc = nullptr) {
   uint64_t* rowbits = at<uint64_t>(ws, L.rowbits);
   uint64_t* colbits = at<uint64_t>(ws, L.colbits);
   int* rmax = at<int>(ws, L.rmax);
@@ -334,7 +349,8 @@ int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const voi
     // Cbar = Abar Bbar; keep row maxima (over j) and column maxima (over i).
     {
       Scope sc(PH_GEMM_SCALE, s);
-      launch_gemm_i8(s, 1, As, 0, Bs, 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax);
+      launch_gemm_i8(s, 1, As, 0, Bs, 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax,
+                     at<int8_t>(ws, L.part), L.part_bytes);
     }
   }
   {
@@ -353,11 +369,16 @@ int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   {
     Scope sc(PH_GEMM_RES, s);
     launch_gemm_i8(s, 0, As, (size_t)L.mp * L.kp, Bs, (size_t)L.np * L.kp, L.mp, L.np, L.kp,
-                   cc.N, cc, W, (size_t)L.np * L.mp, L.mp, nullptr, nullptr);
+                   cc.N, cc, W, (size_t)L.np * L.mp, L.mp, nullptr, nullptr, at<int8_t>(ws, L.part),
+                   L.part_bytes);
   }
   {
     Scope sc(PH_CRT, s);
-    launch_crt(s, pr, W, (size_t)L.np * L.mp, L.mp, mu, nu, m, n, cc, flag, C, ldc);
+    if (zc)
+      launch_crt_complex(s, pr, W, W + m / 2, (size_t)L.np * L.mp, L.mp, mu, mu + m / 2, nu, m / 2,
+                         n, cc, flag, zc->C, zc->ldc);
+    else
+      launch_crt(s, pr, W, (size_t)L.np * L.mp, L.mp, mu, nu, m, n, cc, flag, C, ldc);
   }
   launch_or_status(s, flag, status);
   return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
@@ -377,7 +398,7 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
   }
   CrtConsts cc;
   if ((rc = get_consts(N, b, &cc))) return rc;
-  Layout L = layout(m, n, k, N, single_row_pad(m, n, N));
+  Layout L = layout(m, n, k, N, single_row_pad(m, n, N), N);
   char* ws;
   int* status;
   if ((rc = get_workspace(L.total, &ws, &status))) return rc;
@@ -449,11 +470,11 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
 
 // Complex C = AB (reading R23): the real Algorithm 1 on the embedding
 // Ahat = [[Ar, -Ai], [Ai, Ar]] (2m x 2k), Bhat = [[Br], [Bi]] (2k x n),
-// whose product holds Re AB in rows 1..m and Im AB in rows m+1..2m.  The
-// workspace holds Ahat, Bhat and the 2m x n real result, then the real
-// layout of the 2m x n x 2k problem.
+// whose product holds Re AB in rows 1..m and Im AB in rows m+1..2m; the CRT
+// writes the two halves as complex pairs.  The workspace holds Ahat and
+// Bhat, then the real layout of the 2m x n x 2k problem.
 struct ZLayout {
-  size_t Ah, Bh, Ch, real, total;
+  size_t Ah, Bh, real, total;
   Layout L;
 };
 
@@ -461,9 +482,8 @@ ZLayout zlayout(int m, int n, int k, int N, size_t s) {
   ZLayout Z;
   Z.Ah = 0;
   Z.Bh = rup(Z.Ah + s * 4 * (size_t)m * k, 256);
-  Z.Ch = rup(Z.Bh + s * 2 * (size_t)k * n, 256);
-  Z.real = rup(Z.Ch + s * 2 * (size_t)m * n, 256);
-  Z.L = layout(2 * m, n, 2 * k, N, single_row_pad(2 * m, n, N));
+  Z.real = rup(Z.Bh + s * 2 * (size_t)k * n, 256);
+  Z.L = layout(2 * m, n, 2 * k, N, single_row_pad(2 * m, n, N), N);
   Z.total = Z.real + Z.L.total;
   return Z;
 }
@@ -504,22 +524,20 @@ int zgemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void*
   int* status;
   if ((rc = get_workspace(Z.total, &ws, &status))) return rc;
   launch_embed_complex(s, pr, A, lda, B, ldb, m, n, k, ws + Z.Ah, ws + Z.Bh);
-  rc = run_pipeline(pr, 2 * m, n, 2 * k, ws + Z.Ah, 2 * m, ws + Z.Bh, 2 * k, ws + Z.Ch, 2 * m, cc,
-                    Z.L, ws + Z.real, status, s, false);
-  if (rc) return rc;
-  launch_interleave_complex(s, pr, ws + Z.Ch, m, n, C, ldc);
-  return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
+  const ComplexOut zc{C, ldc};
+  return run_pipeline(pr, 2 * m, n, 2 * k, ws + Z.Ah, 2 * m, ws + Z.Bh, 2 * k, nullptr, 0, cc, Z.L,
+                      ws + Z.real, status, s, false, nullptr, &zc);
 }
 
 // The complex 3-product form (reading R25): one shift per row of A and per
 // column of B for both parts (Algorithm 2 on Abar = bar(Ar) + bar(Ai) with
 // mu' one lower), residues of A'r, A'i and A'r + A'i, three residue products
 // per modulus, W_re = mod(T1 - T2), W_im = mod(T3 - T1 - T2), the CRT on
-// each part and the inverse scaling.  Workspace: the four real planes, the
-// 2m x n real result, then the layout of the m x n x k problem with 3N
+// each part and the inverse scaling, written as complex pairs.  Workspace:
+// the four real planes, then the layout of the m x n x k problem with 3N
 // slices and 3N W (the three groups of N back to back).
 struct Z3Layout {
-  size_t Ar, Ai, Br, Bi, Ch, real, total;
+  size_t Ar, Ai, Br, Bi, real, total;
   Layout L;
 };
 
@@ -529,9 +547,8 @@ Z3Layout z3layout(int m, int n, int k, int N, size_t s) {
   Z.Ai = rup(Z.Ar + s * (size_t)m * k, 256);
   Z.Br = rup(Z.Ai + s * (size_t)m * k, 256);
   Z.Bi = rup(Z.Br + s * (size_t)k * n, 256);
-  Z.Ch = rup(Z.Bi + s * (size_t)k * n, 256);
-  Z.real = rup(Z.Ch + s * 2 * (size_t)m * n, 256);
-  Z.L = layout(m, n, k, 3 * N, single_row_pad(m, n, N));
+  Z.real = rup(Z.Bi + s * (size_t)k * n, 256);
+  Z.L = layout(m, n, k, 3 * N, single_row_pad(m, n, N), N);
   Z.total = Z.real + Z.L.total;
   return Z;
 }
@@ -584,7 +601,8 @@ int zgemm3m_impl(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   launch_slices(s, pr, 2, false, Br, k, n, k, L.np, L.kp, colbits, nullptr, cc, Y[0]);
   launch_slices(s, pr, 2, false, Bi, k, n, k, L.np, L.kp, colbits, nullptr, cc, Y[1]);
   launch_add_bars(s, Y[0], Y[1], Y[2], sb);
-  launch_gemm_i8(s, 1, X[2], 0, Y[2], 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax);
+  launch_gemm_i8(s, 1, X[2], 0, Y[2], 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax,
+                 at<int8_t>(w, L.part), L.part_bytes);
   launch_shifts(s, rowbits, rmax, m, colbits, cmax, n, cc.Pprime, cc.c, at<int>(w, L.mu_p),
                 at<int>(w, L.nu_p), mu, nu, nullptr, -1);
   // Algorithm 3: residues of A'r, A'i and A'r + A'i (and of B), three
@@ -597,12 +615,9 @@ int zgemm3m_impl(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   launch_sum_residues(s, Y[0], Y[1], Y[2], sb, cc);
   for (int q = 0; q < 3; ++q)
     launch_gemm_i8(s, 0, X[q], sa, Y[q], sb, L.mp, L.np, L.kp, N, cc, W[q], sw, L.mp, nullptr,
-                   nullptr);
+                   nullptr, at<int8_t>(w, L.part), L.part_bytes);
   launch_combine_w(s, W[0], W[1], W[2], sw, cc);
-  char* Ch = ws + Z.Ch;
-  launch_crt(s, pr, W[0], sw, L.mp, mu, nu, m, n, cc, flag, Ch, 2 * m);
-  launch_crt(s, pr, W[1], sw, L.mp, mu, nu, m, n, cc, flag, Ch + es * m, 2 * m);
-  launch_interleave_complex(s, pr, Ch, m, n, C, ldc);
+  launch_crt_complex(s, pr, W[0], W[1], sw, L.mp, mu, mu, nu, m, n, cc, flag, C, ldc);
   launch_or_status(s, flag, status);
   return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
 }
@@ -621,7 +636,7 @@ int gemm_on_buffer(Prec pr, int m, int n, int k, const void* A, int lda, const v
   if (rc) return rc;
   if ((rc = check_N(N, b))) return rc;
   if (m == 0 || n == 0) return OZAKI2_OK;
-  const Layout L = layout(m, n, k > 0 ? k : 1, N, single_row_pad(m, n, N));
+  const Layout L = layout(m, n, k > 0 ? k : 1, N, single_row_pad(m, n, N), N);
   if (L.total > cap) return OZAKI2_ERR_WORKSPACE;
   hipStream_t s = g_stream;
   if (k == 0) {
@@ -1156,7 +1171,7 @@ int ozaki2_debug_constants(int prec, int table, int N, double* out) {
 size_t ozaki2_workspace_bytes(int prec, int m, int n, int k, int N) {
   if ((prec != 64 && prec != 32) || m < 0 || n < 0 || k < 0 || k > kMaxK) return 0;
   if (m > kMaxDim || n > kMaxDim || check_N(N, prec) != OZAKI2_OK) return 0;
-  return layout(m, n, k, N, single_row_pad(m, n, N)).total;
+  return layout(m, n, k, N, single_row_pad(m, n, N), N).total;
 }
 
 int ozaki2_set_workspace(void* dptr, size_t bytes) {
@@ -1327,7 +1342,7 @@ int plan_search(const PlanLayout& L, char* ws, int m, int n, int k, double eps, 
 size_t certified_bytes(int m, int n, int k, int N, size_t* gemm_off) {
   const size_t off = rup(plan_layout(m, n, k).total, 256);
   if (gemm_off) *gemm_off = off;
-  return off + layout(m, n, k, N, single_row_pad(m, n, N)).total;
+  return off + layout(m, n, k, N, single_row_pad(m, n, N), N).total;
 }
 
 }  // namespace
@@ -1413,7 +1428,7 @@ int ozaki2_gemm_certified(int prec, int m, int n, int k, const void* A, int lda,
     }
     CrtConsts cc;
     if ((rc = get_consts(N, b, &cc))) return rc;
-    const Layout Lg = layout(m, n, k, N, single_row_pad(m, n, N));
+    const Layout Lg = layout(m, n, k, N, single_row_pad(m, n, N), N);
     char* wg = ws + off;
     // The planner terms include the scaling pass of Algorithm 2 on the same
     // inputs (the same kernels, so the same bits): the runs start from it.
@@ -1521,6 +1536,10 @@ int ozaki2_debug_tuning(int knob, int value, int* previous) {
     case OZAKI2_KNOB_BATCH_PERSIST:
       if (value < -1 || value > 1) return OZAKI2_ERR_INVALID_ARG;
       k = &g_batch_persist;
+      break;
+    case OZAKI2_KNOB_SPLIT_K:
+      if (value != 0 && value != 1) return OZAKI2_ERR_INVALID_ARG;
+      k = &g_split_k;
       break;
     default:
       return OZAKI2_ERR_INVALID_ARG;

@@ -5,11 +5,11 @@
 //
 // The real Algorithm 1 runs unchanged on (Ahat, Bhat), so every quantity of
 // Algorithms 1-3 and the Theorem 1 bound are those of the real 2m x n x 2k
-// product.  These kernels only move data: they write Ahat (2m x 2k) and
-// Bhat (2k x n) column-major into the workspace from the interleaved
-// (re, im) column-major inputs, and interleave the 2m x n real result into
-// the complex output.  Indices run in 64-bit; threads walk consecutive rows,
-// so every load and store of a wave is contiguous.
+// product.  The embedding kernels only move data: they write Ahat (2m x 2k)
+// and Bhat (2k x n) column-major into the workspace from the interleaved
+// (re, im) column-major inputs (the CRT writes the result as complex pairs).
+// Indices run in 64-bit; threads walk consecutive rows, so every load and
+// store of a wave is contiguous.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -51,20 +51,6 @@ __global__ __launch_bounds__(kThreads) void k_embed_b(const T* __restrict__ B, i
     T* c = Bh + j * ldh;               // column j: [Br; Bi]
     c[h] = b[0];
     c[k + h] = b[1];
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_interleave_c(const T* __restrict__ Ch, int m, int n,
-                                                            T* __restrict__ C, int ldc) {
-  const int64_t total = (int64_t)m * n, ldh = 2 * (int64_t)m;
-  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * kThreads) {
-    const int64_t i = t % m, j = t / m;
-    const T* c = Ch + j * ldh;
-    T* o = C + 2 * (i + j * ldc);
-    o[0] = c[i];
-    o[1] = c[m + i];
   }
 }
 
@@ -243,17 +229,6 @@ void launch_combine_w(hipStream_t s, int8_t* w1, int8_t* w2, const int8_t* w3, s
                       const CrtConsts& cc) {
   hipLaunchKernelGGL(k_combine_w, byte_slice_grid(per, cc.N), dim3(kThreads), 0, s, w1, w2, w3,
                      (int64_t)(per / 16), cc);
-}
-
-void launch_interleave_complex(hipStream_t s, Prec pr, const void* Ch, int m, int n, void* C,
-                               int ldc) {
-  const dim3 g = grid_for((int64_t)m * n), blk(kThreads);
-  if (pr == Prec::F64)
-    hipLaunchKernelGGL(k_interleave_c<double>, g, blk, 0, s, (const double*)Ch, m, n, (double*)C,
-                       ldc);
-  else
-    hipLaunchKernelGGL(k_interleave_c<float>, g, blk, 0, s, (const float*)Ch, m, n, (float*)C,
-                       ldc);
 }
 
 }  // namespace oz2

@@ -25,22 +25,15 @@ namespace {
 // next, so small-m problems keep every lane busy.
 // With DBG, C'(1), C'(2), Q and C'' of every entry are also stored, as FP64
 // column-major m x n arrays at dbg + s * m * n for s = 0..3 (stage dumps).
-template <typename T, int R, bool DBG = false>
-__device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw, int ldw,
-                                const int* __restrict__ mu, const int* __restrict__ nu, int m,
-                                int n, const CrtConsts& cc, const int* __restrict__ flag,
-                                T* __restrict__ C, int ldc, int64_t g,
-                                double* __restrict__ dbg = nullptr) {
-  static_assert(R == 2 || R == 4 || R == 8, "rows per thread");
+// C'(1) and C'(2) of R consecutive rows (wp: row i0 of column j of slice 0).
+// ALIGNED: wp is a multiple of R bytes, so each slice's R bytes are one load;
+// otherwise they are gathered byte by byte.
+template <typename T, int R, bool ALIGNED = true>
+__device__ __forceinline__ void crt_sums(const int8_t* __restrict__ wp, size_t sw,
+                                         const CrtConsts& cc, double (&c1)[R], double (&c2)[R]) {
   typedef typename std::conditional<R == 2, uint16_t,
                                     typename std::conditional<R == 4, uint32_t, uint64_t>::type>::type
       WordT;
-  const int chunks = cdiv_i(m, R);
-  const int j = (int)(g / chunks);
-  if (j >= n) return;
-  const int i0 = (int)(g - (int64_t)j * chunks) * R;
-  const int8_t* wp = W + (size_t)j * ldw + i0;
-  double c1[R], c2[R];
 #pragma unroll
   for (int e = 0; e < R; ++e) c1[e] = c2[e] = 0.0;
   // Moduli in groups of 4, loads first (clamped to the last slice); a modulus
@@ -52,8 +45,16 @@ __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw
   for (int l0 = 0; l0 < cc.N; l0 += 4) {
     uint64_t wv[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      wv[u] = *reinterpret_cast<const WordT*>(wp + (size_t)min(l0 + u, cc.N - 1) * sw);
+    for (int u = 0; u < 4; ++u) {
+      const int8_t* src = wp + (size_t)min(l0 + u, cc.N - 1) * sw;
+      if constexpr (ALIGNED) {
+        wv[u] = *reinterpret_cast<const WordT*>(src);
+      } else {
+        wv[u] = 0;
+#pragma unroll
+        for (int e = 0; e < R; ++e) wv[u] |= (uint64_t)(uint8_t)src[e] << (8 * e);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int l = min(l0 + u, cc.N - 1);
@@ -69,25 +70,52 @@ __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw
       }
     }
   }
+}
+
+// Q, C'' and the output 2^ex C'' (NaN when the non-finite flag is set) of
+// one entry from its C'(1), C'(2).
+template <typename T>
+__device__ __forceinline__ T crt_value(double c1, double c2, const CrtConsts& cc, int ex, bool bad,
+                                       double* q_out, double* cpp_out) {
+  const double q = rint(c1 * cc.Pinv);
+  const double t = fma(-q, cc.P1, c1);
+  double cppd;
+  T out;
+  if (sizeof(T) == 8) {
+    const double cpp = fma(-q, cc.P2, t + c2);
+    out = bad ? (T)NAN : (T)ldexp(cpp, ex);
+    cppd = cpp;
+  } else {
+    const float cpp = (float)t;
+    out = bad ? (T)NAN : (T)ldexp((double)cpp, ex);
+    cppd = (double)cpp;
+  }
+  *q_out = q;
+  *cpp_out = cppd;
+  return out;
+}
+
+template <typename T, int R, bool DBG = false>
+__device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw, int ldw,
+                                const int* __restrict__ mu, const int* __restrict__ nu, int m,
+                                int n, const CrtConsts& cc, const int* __restrict__ flag,
+                                T* __restrict__ C, int ldc, int64_t g,
+                                double* __restrict__ dbg = nullptr) {
+  static_assert(R == 2 || R == 4 || R == 8, "rows per thread");
+  const int chunks = cdiv_i(m, R);
+  const int j = (int)(g / chunks);
+  if (j >= n) return;
+  const int i0 = (int)(g - (int64_t)j * chunks) * R;
+  double c1[R], c2[R];
+  crt_sums<T, R>(W + (size_t)j * ldw + i0, sw, cc, c1, c2);
   const bool bad = *flag != 0;
   const int nuj = nu[j];
   T out[R];
 #pragma unroll
   for (int e = 0; e < R; ++e) {
     const int i = min(i0 + e, m - 1);
-    const double q = rint(c1[e] * cc.Pinv);
-    const double t = fma(-q, cc.P1, c1[e]);
-    const int ex = -mu[i] - nuj;
-    double cppd;
-    if (sizeof(T) == 8) {
-      const double cpp = fma(-q, cc.P2, t + c2[e]);
-      out[e] = bad ? (T)NAN : (T)ldexp(cpp, ex);
-      cppd = cpp;
-    } else {
-      const float cpp = (float)t;
-      out[e] = bad ? (T)NAN : (T)ldexp((double)cpp, ex);
-      cppd = (double)cpp;
-    }
+    double q, cppd;
+    out[e] = crt_value<T>(c1[e], c2[e], cc, -mu[i] - nuj, bad, &q, &cppd);
     if constexpr (DBG) {
       if (i0 + e < m) {
         const size_t mn = (size_t)m * n, o = (size_t)j * m + i0 + e;
@@ -119,6 +147,76 @@ __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw
     for (int e = 0; e < R; ++e)
       if (i0 + e < m) cp[e] = out[e];
   }
+}
+
+// Complex output: the real parts from (Wr, mur) and the imaginary parts from
+// (Wi, mui), both with the column shifts nu, written as interleaved (re, im)
+// pairs into the column-major complex C (ldc in complex elements).  The
+// loads of a partial last chunk read up to row rup(m, R) - 1 past Wr and Wi,
+// inside the padded column (the embedding's column holds 2m rows padded to a
+// multiple of 128, at least m + rup(m, R)).
+template <typename T, int R>
+__device__ __forceinline__ void crt_complex_body(const int8_t* __restrict__ Wr,
+                                                 const int8_t* __restrict__ Wi, size_t sw, int ldw,
+                                                 const int* __restrict__ mur,
+                                                 const int* __restrict__ mui,
+                                                 const int* __restrict__ nu, int m, int n,
+                                                 const CrtConsts& cc, const int* __restrict__ flag,
+                                                 T* __restrict__ C, int ldc, int64_t g) {
+  const int chunks = cdiv_i(m, R);
+  const int j = (int)(g / chunks);
+  if (j >= n) return;
+  const int i0 = (int)(g - (int64_t)j * chunks) * R;
+  const bool bad = *flag != 0;
+  const int nuj = nu[j];
+  double c1[R], c2[R], q, cppd;
+  T re[R], im[R];
+  crt_sums<T, R>(Wr + (size_t)j * ldw + i0, sw, cc, c1, c2);
+#pragma unroll
+  for (int e = 0; e < R; ++e)
+    re[e] = crt_value<T>(c1[e], c2[e], cc, -mur[min(i0 + e, m - 1)] - nuj, bad, &q, &cppd);
+  // the imaginary rows of the real embedding start at row m, which need not
+  // be a multiple of R (uniform over the launch)
+  if (((uintptr_t)Wi & (R - 1)) == 0)
+    crt_sums<T, R, true>(Wi + (size_t)j * ldw + i0, sw, cc, c1, c2);
+  else
+    crt_sums<T, R, false>(Wi + (size_t)j * ldw + i0, sw, cc, c1, c2);
+#pragma unroll
+  for (int e = 0; e < R; ++e)
+    im[e] = crt_value<T>(c1[e], c2[e], cc, -mui[min(i0 + e, m - 1)] - nuj, bad, &q, &cppd);
+  T* cp = C + 2 * ((size_t)j * ldc + i0);
+  if (i0 + R <= m && ((uintptr_t)cp & (2 * sizeof(T) - 1)) == 0) {
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+      if (sizeof(T) == 8) {
+        double2 v;
+        v.x = (double)re[e];
+        v.y = (double)im[e];
+        *reinterpret_cast<double2*>(cp + 2 * e) = v;
+      } else {
+        float2 v;
+        v.x = (float)re[e];
+        v.y = (float)im[e];
+        *reinterpret_cast<float2*>(cp + 2 * e) = v;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+      if (i0 + e < m) {
+        cp[2 * e] = re[e];
+        cp[2 * e + 1] = im[e];
+      }
+  }
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_crt_complex(
+    const int8_t* __restrict__ Wr, const int8_t* __restrict__ Wi, size_t sw, int ldw,
+    const int* __restrict__ mur, const int* __restrict__ mui, const int* __restrict__ nu, int m,
+    int n, CrtConsts cc, const int* __restrict__ flag, T* __restrict__ C, int ldc) {
+  crt_complex_body<T, R>(Wr, Wi, sw, ldw, mur, mui, nu, m, n, cc, flag, C, ldc,
+                         (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 template <typename T, int R>
@@ -206,6 +304,18 @@ void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, con
     launch_crt_t<double>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
   else
     launch_crt_t<float>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
+}
+
+void launch_crt_complex(hipStream_t s, Prec pr, const int8_t* Wr, const int8_t* Wi, size_t sw,
+                        int ldw, const int* mur, const int* mui, const int* nu, int m, int n,
+                        const CrtConsts& cc, const int* flag, void* C, int ldc) {
+  const dim3 grid((unsigned)crt_blocks(m, n)), block(256);
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL((k_crt_complex<double, kCrtRows>), grid, block, 0, s, Wr, Wi, sw, ldw, mur,
+                       mui, nu, m, n, cc, flag, (double*)C, ldc);
+  else
+    hipLaunchKernelGGL((k_crt_complex<float, kCrtRows>), grid, block, 0, s, Wr, Wi, sw, ldw, mur,
+                       mui, nu, m, n, cc, flag, (float*)C, ldc);
 }
 
 void launch_crt_debug(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,

@@ -31,6 +31,7 @@
 //
 // Accumulator layout of the 32x32x32 MFMA (lane l, register r):
 //   row (X side) = 8*(r/4) + 4*(l/32) + r%4,   column (Y side) = l%32.
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <type_traits>
@@ -102,15 +103,19 @@ __device__ inline int swz(int r) { return (r >> 1) & 7; }
 // global->LDS, every 128-byte line requested as one unit) run while the
 // MFMAs consume group g.  A group buffer holds the X tile then the Y tile as
 // rows of 128 bytes.  `bid` is the workgroup's index among the `launched`
-// workgroups of this product (launched >= tiles_x * tiles_y * nz; the
-// surplus exits at once).
+// workgroups of this product (launched >= tiles_x * tiles_y * nz * nsplit;
+// the surplus exits at once).  Split-k: with nsplit > 1, workgroup index
+// sidx = bid / (tiles * nz) takes the k-groups [sidx G / nsplit,
+// (sidx + 1) G / nsplit) of the G = k_pad / 128 (nsplit <= G), and its
+// epilogue writes slice sidx * nz + z of W (EPI 0: mod p_z of its partial
+// sum; EPI 4: the INT32 partial sum); the caller reduces the partials.
 template <int BX, int BY, int NWX, int NWY, int EPI, bool BF16, bool FOLD>
 __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t sx,
                                           const int8_t* __restrict__ Y, size_t sy, int tiles_x,
                                           int tiles_y, int nz, int k_pad, const CrtConsts& cc,
                                           int8_t* __restrict__ W, size_t sw, int ldw,
                                           int* __restrict__ xmax, int* __restrict__ ymax, int bid,
-                                          int launched) {
+                                          int launched, int nsplit = 1) {
   constexpr int BK = 128;                        // bytes of k per LDS row (one group)
   constexpr int NW = NWX * NWY;                  // waves
   constexpr int WX = BX / NWX, WY = BY / NWY;
@@ -127,7 +132,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   __shared__ __attribute__((aligned(1024))) int8_t lds[2 * GROUP_BYTES];
 
   // ---- workgroup -> (slice z, tile) ------------------------------------
-  const int total = tiles_x * tiles_y * nz;
+  const int total = tiles_x * tiles_y * nz * nsplit;
   {
     const int xcd = bid % kXcds, loc = bid / kXcds;
     const int per = launched / kXcds, extra = launched % kXcds;
@@ -135,6 +140,8 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   }
   if (bid >= total) return;   // whole workgroup, before any barrier
   const int per_slice = tiles_x * tiles_y;
+  const int sidx = bid / (per_slice * nz);
+  bid -= sidx * per_slice * nz;
   const int z = bid / per_slice;
   int t = bid % per_slice;
   const int group_span = GROUP * tiles_y;
@@ -235,7 +242,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   auto finish = [&]() {
     if constexpr (EPI == 4) {
       // INT32 accumulators of slice z stored column-major: D_z[y][x]
-      int* Dz = reinterpret_cast<int*>(W) + (size_t)z * sw;
+      int* Dz = reinterpret_cast<int*>(W) + (size_t)(sidx * nz + z) * sw;
 #pragma unroll
       for (int tx = 0; tx < TX; ++tx)
 #pragma unroll
@@ -266,7 +273,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
           }
     } else if constexpr (EPI == 0) {
       const int p = cc.p[z];
-      int8_t* Wz = W + (size_t)z * sw;
+      int8_t* Wz = W + (size_t)(sidx * nz + z) * sw;
       // The modulus is uniform: one branch for the whole tile.
       if (p == 256) {
 #pragma unroll
@@ -341,7 +348,9 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   // barrier) before use, which also certifies that every wave has finished
   // reading group gi-1.  No branch encloses an MFMA, so the accumulators stay
   // in place across iterations.
-  const int NG = k_pad / 128;
+  const int NGall = k_pad / 128;
+  const int g_lo = (int)((int64_t)sidx * NGall / nsplit);
+  const int NG = (int)((int64_t)(sidx + 1) * NGall / nsplit);   // end of this workgroup's groups
   // Within each 32-k sub-step the fragment reads of the next sub-step (into
   // the other register set) alternate one for one with the MFMAs of the
   // current one; the remaining MFMAs follow.
@@ -362,7 +371,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   // build of the kernel for k_pad > 2^17, so that the usual one keeps the
   // plain loop and its register budget.
   constexpr bool kFold = FOLD && (EPI == 0 || EPI == 4);
-  const int chunk = kFold ? kFoldGroups : NG;
+  const int chunk = kFold ? kFoldGroups : NG - g_lo;
   auto fold = [&]() {
     const int p = cc.p[z];
     if (p == 256) return;
@@ -374,9 +383,9 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[tx][ty][r] = mod_odd(acc[tx][ty][r], pd, pinv);
   };
-  issue_x(lds, z, 0);
-  issue_y(lds, z, 0);
-  for (int g0 = 0; g0 < NG; g0 += chunk) {
+  issue_x(lds + (g_lo & 1) * GROUP_BYTES, z, g_lo * 128);
+  issue_y(lds + (g_lo & 1) * GROUP_BYTES, z, g_lo * 128);
+  for (int g0 = g_lo; g0 < NG; g0 += chunk) {
   const int g1 = min(NG, g0 + chunk);
   for (int gi = g0; gi < g1; ++gi) {
     int8_t* const buf = lds + (gi & 1) * GROUP_BYTES;
@@ -669,9 +678,78 @@ template <int B, int EPI, bool BF16 = false, bool FOLD = false>
 __global__ __launch_bounds__(tile_threads<B>(), TileShape<B>::OCC) void k_gemm_i8(
     const int8_t* __restrict__ X, size_t sx, const int8_t* __restrict__ Y, size_t sy, int tiles_x,
     int tiles_y, int nz, int k_pad, CrtConsts cc, int8_t* __restrict__ W, size_t sw, int ldw,
-    int* __restrict__ xmax, int* __restrict__ ymax) {
+    int* __restrict__ xmax, int* __restrict__ ymax, int nsplit) {
   gemm_body<B, B, TileShape<B>::NWX, TileShape<B>::NWY, EPI, BF16, FOLD>(
-      X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax, blockIdx.x, gridDim.x);
+      X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax, blockIdx.x, gridDim.x,
+      nsplit);
+}
+
+// ---- split-k reductions ------------------------------------------------------
+// mod(x, p) in the range of Section 1.2 ([hi + 1 - p, hi], hi = (p - 1) / 2)
+// for |x| < 2^14: the FP32 quotient x (1/p) is within one of the nearest
+// integer to x/p, and one correction either way lands r in the range.
+__device__ inline int mod_small(int x, int p, float pinv, int hi) {
+  int r = x - (int)rintf((float)x * pinv) * p;
+  r -= r > hi ? p : 0;
+  r += r < hi + 1 - p ? p : 0;
+  return r;
+}
+
+// W (EPI 0): slice z = mod(sum over s of partial slice s * nz + z, p_z); each
+// partial is in [-128, 127], so for nsplit <= 64 the sum stays below 2^13 in
+// magnitude.  Workgroup row blockIdx.y is slice z; 16 bytes a thread.
+__global__ __launch_bounds__(256) void k_reduce_w(const int8_t* __restrict__ part, int nsplit,
+                                                  int nz, int64_t sw16, CrtConsts cc,
+                                                  int8_t* __restrict__ W) {
+  const int z = blockIdx.y;
+  const int p = cc.p[z], hi = (p - 1) / 2;
+  const float pinv = (float)cc.pinv[z];
+  const uint4* src = reinterpret_cast<const uint4*>(part);
+  uint4* dst = reinterpret_cast<uint4*>(W) + z * sw16;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < sw16;
+       t += (int64_t)gridDim.x * 256) {
+    int acc[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0;
+    for (int sidx = 0; sidx < nsplit; ++sidx) {
+      const uint4 v = src[((int64_t)sidx * nz + z) * sw16 + t];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[e] += (int)(w[e >> 2] << (24 - 8 * (e & 3))) >> 24;
+    }
+    uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      o[e >> 2] |= (uint32_t)(mod_small(acc[e], p, pinv, hi) & 0xFF) << (8 * (e & 3));
+    dst[t] = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+// Cbar (EPI 1) from nsplit INT32 partial sums (column-major, ld nx): one
+// entry (x, y) per thread, workgroups of 64 x by 4 y.  Each wave (64
+// consecutive x of one y) sends its maximum to ymax[y]; the four rows of a
+// workgroup are combined in LDS and sent to xmax[x] (atomicMax, order-free;
+// Cbar >= 0).  nx is a multiple of 128.
+__global__ __launch_bounds__(256) void k_reduce_cbar(const int* __restrict__ part, int nsplit,
+                                                     int nx, int ny, int* __restrict__ xmax,
+                                                     int* __restrict__ ymax) {
+  __shared__ int rows[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x = blockIdx.x * 64 + tx, y = blockIdx.y * 4 + ty;
+  const size_t per = (size_t)nx * ny;
+  int v = 0;
+  if (y < ny) {
+    const int* src = part + (size_t)y * nx + x;
+    for (int sidx = 0; sidx < nsplit; ++sidx) v += src[sidx * per];
+    int cm = v;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cm = max(cm, __shfl_xor(cm, off));
+    if (tx == 0) atomicMax(&ymax[y], cm);
+  }
+  rows[ty][tx] = v;
+  __syncthreads();
+  if (ty == 0)
+    atomicMax(&xmax[x], max(max(rows[0][tx], rows[1][tx]), max(rows[2][tx], rows[3][tx])));
 }
 
 // Grouped: the scaling product (EPI 1) or the N residue products (EPI 0) of
@@ -700,36 +778,33 @@ __global__ __launch_bounds__(tile_threads<B>(), TileShape<B>::OCC) void kp_gemm(
 template <int B>
 void launch_cfg(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                 int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
-                size_t sw, int ldw, int* xmax, int* ymax) {
+                size_t sw, int ldw, int* xmax, int* ymax, int nsplit, bool fold) {
   const int tiles_x = nx_pad / B, tiles_y = ny_pad / B;
-  const dim3 grid((unsigned)(tiles_x * tiles_y * nz)), block(tile_threads<B>());
-  const bool fold = k_pad > kFoldGroups * 128;
+  const dim3 grid((unsigned)(tiles_x * tiles_y * nz * nsplit)), block(tile_threads<B>());
+#define OZ2_GEMM(E, F)                                                                          \
+  hipLaunchKernelGGL((k_gemm_i8<B, E, false, F>), grid, block, 0, s, X, sx, Y, sy, tiles_x,      \
+                     tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax, nsplit)
   switch (epi) {
     case 0:
       if (fold)
-        hipLaunchKernelGGL((k_gemm_i8<B, 0, false, true>), grid, block, 0, s, X, sx, Y, sy, tiles_x,
-                           tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+        OZ2_GEMM(0, true);
       else
-        hipLaunchKernelGGL((k_gemm_i8<B, 0>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y,
-                           nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+        OZ2_GEMM(0, false);
       break;
     case 1:
-      hipLaunchKernelGGL((k_gemm_i8<B, 1>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
-                         k_pad, cc, W, sw, ldw, xmax, ymax);
+      OZ2_GEMM(1, false);
       break;
     case 3:
-      hipLaunchKernelGGL((k_gemm_i8<B, 3>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y, nz,
-                         k_pad, cc, W, sw, ldw, xmax, ymax);
+      OZ2_GEMM(3, false);
       break;
     default:
       if (fold)
-        hipLaunchKernelGGL((k_gemm_i8<B, 4, false, true>), grid, block, 0, s, X, sx, Y, sy, tiles_x,
-                           tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+        OZ2_GEMM(4, true);
       else
-        hipLaunchKernelGGL((k_gemm_i8<B, 4>), grid, block, 0, s, X, sx, Y, sy, tiles_x, tiles_y,
-                           nz, k_pad, cc, W, sw, ldw, xmax, ymax);
+        OZ2_GEMM(4, false);
       break;
   }
+#undef OZ2_GEMM
 }
 
 // Tile configuration: 0 = automatic; 1 = 256x256, 2 = 128x128 (g_gemm_tile,
@@ -750,7 +825,47 @@ bool use_256(int nx_pad, int ny_pad, int nz) {
   return fits256 && t256 > 128;
 }
 
+// Split-k of a product with few output workgroups (EPI 0 and 1): with W0 =
+// tiles * nz workgroups and G = k_pad / 128 groups of k, nsplit = the number
+// of copies of W0 that fill the workgroup slots once (CUs x occupancy: 256
+// for 256x256 tiles, 512 for 128x128), at most G / gmin and smax; 1 when W0
+// already fills a quarter of the slots.  The residue products take gmin = 4
+// (512 k or more per split), smax = 64; the scaling product, whose partials
+// are INT32 and which is one product against N, gmin = 32 and smax = 16.
+// Measured (FP64, N = 14): 512^2 x 32768 (224 residue workgroups) ran 3%
+// slower with two splits than with none; at 1024^2 x 1024 and x 4096 a
+// scaling product split 2 and 8 ways was slower than unsplit; at
+// 256^2 x 131072 the split products ran 2.4x faster.  A fixed count of 256
+// CUs keeps the choice, and with it the workspace size, a function of the
+// shape alone.
+struct SplitRule {
+  int gmin, smax;
+};
+constexpr SplitRule kSplitRes{4, 64}, kSplitCbar{32, 16};
+int choose_split(int nx_pad, int ny_pad, int k_pad, int nz, SplitRule r) {
+  if (g_split_k.load(std::memory_order_relaxed) == 1) return 1;
+  const int B = use_256(nx_pad, ny_pad, nz) ? 256 : 128;
+  const long w0 = (long)(nx_pad / B) * (ny_pad / B) * nz;
+  const long slots = B == 256 ? 256 : 512;
+  if (w0 <= 0 || 4 * w0 > slots) return 1;
+  long sp = slots / w0;
+  sp = std::min<long>(sp, (k_pad / 128) / r.gmin);
+  sp = std::min<long>(sp, r.smax);
+  return sp >= 2 ? (int)sp : 1;
+}
+
 }  // namespace
+
+std::atomic<int> g_split_k{0};
+
+size_t split_scratch_bytes(int nx_pad, int ny_pad, int k_pad, int nz) {
+  const size_t plane = (size_t)nx_pad * ny_pad;
+  const int s0 = choose_split(nx_pad, ny_pad, k_pad, nz, kSplitRes);
+  const int s1 = choose_split(nx_pad, ny_pad, k_pad, 1, kSplitCbar);
+  const size_t b0 = s0 > 1 ? (size_t)s0 * nz * plane : 0;
+  const size_t b1 = s1 > 1 ? (size_t)s1 * plane * 4 : 0;
+  return b0 > b1 ? b0 : b1;
+}
 
 std::atomic<int> g_gemm_tile{0};
 
@@ -817,22 +932,59 @@ void launch_gemm_bf16_store(hipStream_t s, const uint16_t* X, const uint16_t* Y,
     const int tiles_x = nx_pad / 256, tiles_y = ny_pad / 256;
     hipLaunchKernelGGL((k_gemm_i8<256, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
                        dim3(tile_threads<256>()), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0,
-                       tiles_x, tiles_y, 1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
+                       tiles_x, tiles_y, 1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr, 1);
   } else {
     const int tiles_x = nx_pad / 128, tiles_y = ny_pad / 128;
     hipLaunchKernelGGL((k_gemm_i8<128, 2, true>), dim3((unsigned)(tiles_x * tiles_y)),
                        dim3(tile_threads<128>()), 0, s, (const int8_t*)X, 0, (const int8_t*)Y, 0,
-                       tiles_x, tiles_y, 1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr);
+                       tiles_x, tiles_y, 1, kb, cc, (int8_t*)S, 0, lds_, nullptr, nullptr, 1);
   }
 }
 
 void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                     int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
-                    size_t sw, int ldw, int* xmax, int* ymax) {
-  if (use_256(nx_pad, ny_pad, nz))
-    launch_cfg<256>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw, xmax, ymax);
-  else
-    launch_cfg<128>(s, epi, X, sx, Y, sy, nx_pad, ny_pad, k_pad, nz, cc, W, sw, ldw, xmax, ymax);
+                    size_t sw, int ldw, int* xmax, int* ymax, int8_t* part, size_t part_bytes) {
+  const bool b256 = use_256(nx_pad, ny_pad, nz);
+  const int G = k_pad / 128;
+  int sp = 1;
+  if (epi == 0 || epi == 1) {
+    sp = epi == 0 ? choose_split(nx_pad, ny_pad, k_pad, nz, kSplitRes)
+                  : choose_split(nx_pad, ny_pad, k_pad, 1, kSplitCbar);
+    const size_t plane = (size_t)nx_pad * ny_pad;
+    const size_t need = epi == 0 ? (size_t)sp * nz * plane : (size_t)sp * plane * 4;
+    // the partials use the plane layout (stride nx_pad * ny_pad, rows of
+    // nx_pad): W must have it too
+    const bool plane_w = epi == 1 || (sw == plane && ldw == nx_pad);
+    if (sp > 1 && (!part || part_bytes < need || !plane_w)) sp = 1;
+  }
+  // every split keeps at least one group; fold when a split spans more than 2^17 of k
+  const bool fold = (G + sp - 1) / sp > kFoldGroups;
+  auto launch = [&](int e, int8_t* out, size_t so, int ld, int* xm, int* ym, int z, bool f) {
+    if (b256)
+      launch_cfg<256>(s, e, X, sx, Y, sy, nx_pad, ny_pad, k_pad, z, cc, out, so, ld, xm, ym, sp, f);
+    else
+      launch_cfg<128>(s, e, X, sx, Y, sy, nx_pad, ny_pad, k_pad, z, cc, out, so, ld, xm, ym, sp, f);
+  };
+  if (sp == 1) {
+    launch(epi, W, sw, ldw, xmax, ymax, nz, fold && (epi == 0 || epi == 4));
+    return;
+  }
+  const size_t plane = (size_t)nx_pad * ny_pad;
+  if (epi == 0) {
+    // partial W of every split (mod p of its partial sum), then their sum mod p
+    launch(0, part, plane, nx_pad, nullptr, nullptr, nz, fold);
+    const int64_t sw16 = (int64_t)(plane / 16);
+    const int64_t b = (sw16 + 255) / 256;
+    hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)(b < 1024 ? b : 1024), (unsigned)nz), dim3(256),
+                       0, s, part, sp, nz, sw16, cc, W);
+  } else {
+    // INT32 partial sums of Cbar (never reduced mod p: Cbar < 2^31), then
+    // their sum and its row and column maxima
+    launch(4, part, plane, nx_pad, nullptr, nullptr, 1, false);
+    const dim3 g((unsigned)(nx_pad / 64), (unsigned)((ny_pad + 3) / 4));
+    hipLaunchKernelGGL(k_reduce_cbar, g, dim3(256), 0, s, (const int*)part, sp, nx_pad, ny_pad,
+                       xmax, ymax);
+  }
 }
 
 }  // namespace oz2

@@ -178,6 +178,8 @@ void launch_log2f(hipStream_t s, const float* d, float* out, int count);
 // products (0: automatic, 1: 256x256, 2: 128x128; gemm_i8.hip).
 extern std::atomic<int> g_slice_cap;
 extern std::atomic<int> g_gemm_tile;
+// Split-k of the single-problem products: 0 automatic (default), 1 off.
+extern std::atomic<int> g_split_k;
 
 // residue.hip: per-device launch figures of the slice kernels (resident workgroups);
 // called once per device before its first launch, outside stream capture.
@@ -206,9 +208,18 @@ void launch_plan_slices(hipStream_t s, Prec pr, bool trans, const void* src, int
 //   epi 1: xmax[x] = max_y D, ymax[y] = max_x D (atomicMax; D >= 0).
 //   epi 3: epi 1, and W[y][x] = (D != 0) as one byte (row length ldw).
 //   epi 4: D_z[y][x] as INT32 into (int*)W + z*sw, row length ldw (elements).
+//   part, part_bytes: scratch for split-k (epi 0 and 1, when few output
+//   tiles leave the CUs idle): the partial products of the k ranges go there
+//   and a reduction kernel combines them into the same result (epi 0: the
+//   sum of the partial mod-p bytes, mod p; epi 1: the INT32 sum, then its
+//   maxima).  With too little scratch (or none) the product is not split.
 void launch_gemm_i8(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t* Y, size_t sy,
                     int nx_pad, int ny_pad, int k_pad, int nz, const CrtConsts& cc, int8_t* W,
-                    size_t sw, int ldw, int* xmax, int* ymax);
+                    size_t sw, int ldw, int* xmax, int* ymax, int8_t* part = nullptr,
+                    size_t part_bytes = 0);
+// Scratch bytes that lets launch_gemm_i8 split both the scaling product (epi
+// 1) and the nz residue products (epi 0) of this shape; 0 if neither splits.
+size_t split_scratch_bytes(int nx_pad, int ny_pad, int k_pad, int nz);
 
 // S[y][x] = sum_h X[x][h] Y[y][h] over BF16 slices (FP32 accumulation on
 // the matrix cores), stored column-major with row length lds_.
@@ -261,6 +272,12 @@ void launch_group_crt(hipStream_t s, Prec pr, const ProbDesc* P, const BlockRef*
 void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,
                 const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
                 int ldc);
+// The CRT of a complex result: real parts from (Wr, mur), imaginary parts
+// from (Wi, mui), column shifts nu, written as interleaved (re, im) pairs into
+// the column-major complex C (ldc in complex elements).
+void launch_crt_complex(hipStream_t s, Prec pr, const int8_t* Wr, const int8_t* Wi, size_t sw,
+                        int ldw, const int* mur, const int* mui, const int* nu, int m, int n,
+                        const CrtConsts& cc, const int* flag, void* C, int ldc);
 // launch_crt plus C'(1), C'(2), Q, C'' as FP64 [4][n][m] into dbg (stage dumps).
 void launch_crt_debug(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,
                       const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
@@ -272,12 +289,9 @@ void launch_or_status(hipStream_t s, const int* flag, int* status);
 // complex.hip: the real embedding of a complex product (interleaved (re, im)
 // column-major inputs; leading dimensions in complex elements) into
 // Ahat = [[Ar, -Ai], [Ai, Ar]] (2m x 2k, ld 2m) and Bhat = [[Br], [Bi]]
-// (2k x n, ld 2k), and the 2m x n real result (ld 2m) back into the
-// interleaved complex C.
+// (2k x n, ld 2k).
 void launch_embed_complex(hipStream_t s, Prec pr, const void* A, int lda, const void* B, int ldb,
                           int m, int n, int k, void* Ah, void* Bh);
-void launch_interleave_complex(hipStream_t s, Prec pr, const void* Ch, int m, int n, void* C,
-                               int ldc);
 // The 3-product form: real and imaginary planes of an interleaved matrix
 // (leading dimension `rows` each); Abar as the sum of two INT8 bars (count a
 // multiple of 16); slice l of x3 = mod(x1 + x2, p_l) over N slices of `per`
