@@ -109,7 +109,9 @@ __device__ inline int swz(int r) { return (r >> 1) & 7; }
 // (sidx + 1) G / nsplit) of the G = k_pad / 128 (nsplit <= G), and its
 // epilogue writes slice sidx * nz + z of W (EPI 0: mod p_z of its partial
 // sum; EPI 4: the INT32 partial sum); the caller reduces the partials.
-template <int BX, int BY, int NWX, int NWY, int EPI, bool BF16, bool FOLD>
+// SPLIT selects that build; without it nsplit is 1 and the k loop is the
+// plain one from group 0 (a dynamic start cost 2% at 8192^3).
+template <int BX, int BY, int NWX, int NWY, int EPI, bool BF16, bool FOLD, bool SPLIT = false>
 __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t sx,
                                           const int8_t* __restrict__ Y, size_t sy, int tiles_x,
                                           int tiles_y, int nz, int k_pad, const CrtConsts& cc,
@@ -132,6 +134,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   __shared__ __attribute__((aligned(1024))) int8_t lds[2 * GROUP_BYTES];
 
   // ---- workgroup -> (slice z, tile) ------------------------------------
+  if constexpr (!SPLIT) nsplit = 1;
   const int total = tiles_x * tiles_y * nz * nsplit;
   {
     const int xcd = bid % kXcds, loc = bid / kXcds;
@@ -140,7 +143,7 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   }
   if (bid >= total) return;   // whole workgroup, before any barrier
   const int per_slice = tiles_x * tiles_y;
-  const int sidx = bid / (per_slice * nz);
+  const int sidx = SPLIT ? bid / (per_slice * nz) : 0;
   bid -= sidx * per_slice * nz;
   const int z = bid / per_slice;
   int t = bid % per_slice;
@@ -349,8 +352,8 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
   // reading group gi-1.  No branch encloses an MFMA, so the accumulators stay
   // in place across iterations.
   const int NGall = k_pad / 128;
-  const int g_lo = (int)((int64_t)sidx * NGall / nsplit);
-  const int NG = (int)((int64_t)(sidx + 1) * NGall / nsplit);   // end of this workgroup's groups
+  const int g_lo = SPLIT ? (int)((int64_t)sidx * NGall / nsplit) : 0;
+  const int NG = SPLIT ? (int)((int64_t)(sidx + 1) * NGall / nsplit) : NGall;   // end of this workgroup's groups
   // Within each 32-k sub-step the fragment reads of the next sub-step (into
   // the other register set) alternate one for one with the MFMAs of the
   // current one; the remaining MFMAs follow.
@@ -383,8 +386,8 @@ __device__ __forceinline__ void gemm_body(const int8_t* __restrict__ X, size_t s
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[tx][ty][r] = mod_odd(acc[tx][ty][r], pd, pinv);
   };
-  issue_x(lds + (g_lo & 1) * GROUP_BYTES, z, g_lo * 128);
-  issue_y(lds + (g_lo & 1) * GROUP_BYTES, z, g_lo * 128);
+  issue_x(lds + (SPLIT ? (g_lo & 1) * GROUP_BYTES : 0), z, g_lo * 128);
+  issue_y(lds + (SPLIT ? (g_lo & 1) * GROUP_BYTES : 0), z, g_lo * 128);
   for (int g0 = g_lo; g0 < NG; g0 += chunk) {
   const int g1 = min(NG, g0 + chunk);
   for (int gi = g0; gi < g1; ++gi) {
@@ -674,12 +677,12 @@ constexpr int tile_threads() {
   return 64 * TileShape<B>::NWX * TileShape<B>::NWY;
 }
 
-template <int B, int EPI, bool BF16 = false, bool FOLD = false>
+template <int B, int EPI, bool BF16 = false, bool FOLD = false, bool SPLIT = false>
 __global__ __launch_bounds__(tile_threads<B>(), TileShape<B>::OCC) void k_gemm_i8(
     const int8_t* __restrict__ X, size_t sx, const int8_t* __restrict__ Y, size_t sy, int tiles_x,
     int tiles_y, int nz, int k_pad, CrtConsts cc, int8_t* __restrict__ W, size_t sw, int ldw,
     int* __restrict__ xmax, int* __restrict__ ymax, int nsplit) {
-  gemm_body<B, B, TileShape<B>::NWX, TileShape<B>::NWY, EPI, BF16, FOLD>(
+  gemm_body<B, B, TileShape<B>::NWX, TileShape<B>::NWY, EPI, BF16, FOLD, SPLIT>(
       X, sx, Y, sy, tiles_x, tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax, blockIdx.x, gridDim.x,
       nsplit);
 }
@@ -781,27 +784,37 @@ void launch_cfg(hipStream_t s, int epi, const int8_t* X, size_t sx, const int8_t
                 size_t sw, int ldw, int* xmax, int* ymax, int nsplit, bool fold) {
   const int tiles_x = nx_pad / B, tiles_y = ny_pad / B;
   const dim3 grid((unsigned)(tiles_x * tiles_y * nz * nsplit)), block(tile_threads<B>());
-#define OZ2_GEMM(E, F)                                                                          \
-  hipLaunchKernelGGL((k_gemm_i8<B, E, false, F>), grid, block, 0, s, X, sx, Y, sy, tiles_x,      \
+#define OZ2_GEMM(E, F, S)                                                                       \
+  hipLaunchKernelGGL((k_gemm_i8<B, E, false, F, S>), grid, block, 0, s, X, sx, Y, sy, tiles_x,   \
                      tiles_y, nz, k_pad, cc, W, sw, ldw, xmax, ymax, nsplit)
+  const bool split = nsplit > 1;
   switch (epi) {
     case 0:
-      if (fold)
-        OZ2_GEMM(0, true);
-      else
-        OZ2_GEMM(0, false);
+      if (split) {
+        if (fold)
+          OZ2_GEMM(0, true, true);
+        else
+          OZ2_GEMM(0, false, true);
+      } else {
+        if (fold)
+          OZ2_GEMM(0, true, false);
+        else
+          OZ2_GEMM(0, false, false);
+      }
       break;
     case 1:
-      OZ2_GEMM(1, false);
+      OZ2_GEMM(1, false, false);
       break;
     case 3:
-      OZ2_GEMM(3, false);
+      OZ2_GEMM(3, false, false);
       break;
     default:
-      if (fold)
-        OZ2_GEMM(4, true);
+      if (split)
+        OZ2_GEMM(4, false, true);   // the split scaling product (never folded)
+      else if (fold)
+        OZ2_GEMM(4, true, false);
       else
-        OZ2_GEMM(4, false);
+        OZ2_GEMM(4, false, false);
       break;
   }
 #undef OZ2_GEMM
