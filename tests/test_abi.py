@@ -216,3 +216,24 @@ def test_tuning_knobs():
     with oz.tuning(oz.KNOB_BATCH_SPLIT, 4):
         assert t(oz.KNOB_BATCH_SPLIT, 4) == (oz.OK, 4)
     assert t(oz.KNOB_BATCH_SPLIT, -1) == (oz.OK, -1)
+
+
+def test_split_k_scratch_in_workspace():
+    # A small output with long k splits its products: the workspace holds the
+    # partial results.  64 x 64 x 262144, N = 14 (one 128 x 128 tile, 2048
+    # groups of 128 k): the residue products split 512 / 14 = 36 ways (36 x 14
+    # partial planes of 128 x 128 bytes), the scaling product 16 ways (INT32,
+    # a smaller region).  With split-k off the region is absent.
+    q = oz.ozaki2_workspace_bytes
+    shapes = [(64, 64, 262144, 14), (4096, 4096, 4096, 14)]
+    with_split = [q(64, *s) for s in shapes]
+    rc, prev = oz.ozaki2_debug_tuning(oz.KNOB_SPLIT_K, 1)
+    assert rc == oz.OK
+    try:
+        without = [q(64, *s) for s in shapes]
+    finally:
+        oz.ozaki2_debug_tuning(oz.KNOB_SPLIT_K, prev)
+    assert with_split[0] - without[0] == 36 * 14 * 128 * 128
+    # an output that fills the GPU does not split: no region
+    assert with_split[1] == without[1]
+    assert oz.ozaki2_debug_tuning(oz.KNOB_SPLIT_K, 7)[0] == oz.ERR_INVALID_ARG
