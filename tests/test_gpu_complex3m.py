@@ -109,3 +109,32 @@ def test_zgemm3m_4096_sampled():
     want = os_ii_complex_3m(A, B, N, rows=rows, cols=cols)
     assert np.array_equal(got[np.ix_(rows, cols)], want)
     assert oz.ozaki2_sync_status() == oz.OK
+
+
+def test_zgemm3m_captured_in_a_graph():
+    # ozaki2_zgemm3m enqueues kernels only; after a first call has grown the
+    # workspace it can be captured and replayed, each replay giving the eager
+    # call's bits (other work and a reset of C between replays).
+    announce("ozaki2_zgemm3m captured in a graph")
+    m, n, k, N = 200, 150, 120, 13
+    A, B = complex_gemm_inputs(m, n, k, phi=1.0, seed=13)
+    ref = host(oz.zgemm(dev(A), dev(B), N, form="3m"))
+    assert np.array_equal(ref, os_ii_complex_3m(A, B, N))
+    dA, dB = dev(np.ascontiguousarray(A.T)), dev(np.ascontiguousarray(B.T))
+    C = torch.full((n, m), float("nan"), dtype=torch.complex128, device="cuda:0")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        rc = oz.ozaki2_zgemm3m(m, n, k, dA.data_ptr(), m, dB.data_ptr(), k, C.data_ptr(), m, N)
+    assert rc == oz.OK
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    for rep in range(2):
+        C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(C).T, ref), f"replay {rep}"
+        X, Y = complex_gemm_inputs(40, 30, 50, seed=70 + rep)
+        assert np.array_equal(host(oz.zgemm(dev(X), dev(Y), 10, form="3m")),
+                              os_ii_complex_3m(X, Y, 10))
