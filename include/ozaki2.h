@@ -155,6 +155,18 @@ size_t ozaki2_complex_workspace_bytes(int prec, int m, int n, int k, int N);
  */
 int ozaki2_required_moduli(int prec, int m, int n, int k, const void *A, int lda, const void *B,
                            int ldb, double eps, int *N_out);
+/*
+ * ozaki2_zrequired_moduli - the same for the complex product of ozaki2_zgemm
+ * (prec 64, complex128 pairs) or ozaki2_cgemm (prec 32): the planner applied
+ * to the real embedding [[Ar, -Ai], [Ai, Ar]] x [[Br], [Bi]] on which those
+ * calls run, so that every real and imaginary part of C meets the target
+ * relative to its entry of |Ahat||Bhat| ((|Ar||Br| + |Ai||Bi|) for the real
+ * part, (|Ai||Br| + |Ar||Bi|) for the imaginary part).  Arguments as
+ * ozaki2_zgemm (no C); k < 2^18.  The 3-product form has other shifts and is
+ * not covered.
+ */
+int ozaki2_zrequired_moduli(int prec, int m, int n, int k, const void *A, int lda,
+                            const void *B, int ldb, double eps, int *N_out);
 
 /*
  * ozaki2_gemm_certified - C := A*B like ozaki2_gemm (prec 64) or ozaki2_sgemm

@@ -37,6 +37,8 @@ _SIGS = {
     "ozaki2_sgemm": ([_c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int], _c_int),
     "ozaki2_required_moduli": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_double,
                                 ctypes.POINTER(_c_int)], _c_int),
+    "ozaki2_zrequired_moduli": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int,
+                                 _c_double, ctypes.POINTER(_c_int)], _c_int),
     "ozaki2_gemm_certified": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int,
                                _c_double, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)], _c_int),
     "ozaki2_certified_workspace_bytes": ([_c_int, _c_int, _c_int, _c_int, _c_int], _c_size),
@@ -104,6 +106,12 @@ def ozaki2_gemm(m, n, k, A, lda, B, ldb, C, ldc, N):
 
 def ozaki2_sgemm(m, n, k, A, lda, B, ldb, C, ldc, N):
     return _call("ozaki2_sgemm", m, n, k, A, lda, B, ldb, C, ldc, N)
+
+
+def ozaki2_zrequired_moduli(prec, m, n, k, A, lda, B, ldb, eps):
+    out = _c_int(0)
+    rc = _call("ozaki2_zrequired_moduli", prec, m, n, k, A, lda, B, ldb, eps, ctypes.byref(out))
+    return rc, out.value
 
 
 def ozaki2_required_moduli(prec, m, n, k, A, lda, B, ldb, eps):
@@ -325,12 +333,17 @@ def zgemm(A, B, N: int, form: str = "4m"):
 
 
 def required_moduli(A, B, eps: float):
-    """(rc, N) from ozaki2_required_moduli for logical A (m x k), B (k x n)."""
+    """(rc, N) from ozaki2_required_moduli for logical A (m x k), B (k x n);
+    complex tensors go to ozaki2_zrequired_moduli (the real embedding)."""
     torch = _torch()
     m, k = A.shape
     n = B.shape[1]
     Acm, Bcm = col_major(A), col_major(B)
     _set_current_stream()
+    if A.dtype in (torch.complex128, torch.complex64):
+        prec = 64 if A.dtype == torch.complex128 else 32
+        return ozaki2_zrequired_moduli(prec, m, n, k, Acm.data_ptr(), max(m, 1), Bcm.data_ptr(),
+                                       max(k, 1), eps)
     prec = 64 if A.dtype == torch.float64 else 32
     return ozaki2_required_moduli(prec, m, n, k, Acm.data_ptr(), max(m, 1), Bcm.data_ptr(), max(k, 1), eps)
 

@@ -1349,6 +1349,37 @@ size_t certified_bytes(int m, int n, int k, int N, size_t* gemm_off) {
 
 extern "C" {
 
+// The planner on the real embedding of a complex product (the form of
+// ozaki2_zgemm): Ahat and Bhat are written into the workspace, followed by
+// the planner's own layout for the 2m x n x 2k problem.
+int ozaki2_zrequired_moduli(int prec, int m, int n, int k, const void* A, int lda, const void* B,
+                            int ldb, double eps, int* N_out) {
+  if (prec != 64 && prec != 32) return OZAKI2_ERR_INVALID_ARG;
+  if (!N_out || !(eps > 0.0) || !(eps < INFINITY)) return OZAKI2_ERR_INVALID_ARG;
+  // no C: any non-null stand-in satisfies the output check
+  int rc = check_complex_args(m, n, k, A, lda, B, ldb, N_out, m > 1 ? m : 1, kMaxK / 2);
+  if (rc) return rc;
+  const int nhi = prec == 64 ? kMaxModuli : 16;
+  if (m == 0 || n == 0 || k == 0) {  // AB = 0 is represented exactly
+    *N_out = 2;
+    return OZAKI2_OK;
+  }
+  const Prec pr = prec == 64 ? Prec::F64 : Prec::F32;
+  PlanCoef pc;
+  if ((rc = get_plan_coef(prec, &pc))) return rc;
+  const size_t es = pr == Prec::F64 ? 8 : 4;
+  const size_t Bh = rup(es * 4 * (size_t)m * k, 256);
+  const size_t off = rup(Bh + es * 2 * (size_t)k * n, 256);
+  const PlanLayout L = plan_layout(2 * m, n, 2 * k);
+  char* ws;
+  int* status;
+  if ((rc = get_workspace(off + L.total, &ws, &status))) return rc;
+  hipStream_t s = g_stream;
+  launch_embed_complex(s, pr, A, lda, B, ldb, m, n, k, ws, ws + Bh);
+  plan_terms(pr, 2 * m, n, 2 * k, ws, 2 * m, ws + Bh, 2 * k, L, ws + off, s);
+  return plan_search(L, ws + off, 2 * m, n, 2 * k, eps, pc, nhi, s, N_out);
+}
+
 int ozaki2_required_moduli(int prec, int m, int n, int k, const void* A, int lda, const void* B,
                            int ldb, double eps, int* N_out) {
   if (prec != 64 && prec != 32) return OZAKI2_ERR_INVALID_ARG;

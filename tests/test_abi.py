@@ -237,3 +237,14 @@ def test_split_k_scratch_in_workspace():
     # an output that fills the GPU does not split: no region
     assert with_split[1] == without[1]
     assert oz.ozaki2_debug_tuning(oz.KNOB_SPLIT_K, 7)[0] == oz.ERR_INVALID_ARG
+
+
+def test_complex_planner_argument_errors():
+    # Host-side checks of ozaki2_zrequired_moduli (nothing reaches a device).
+    f = oz.ozaki2_zrequired_moduli
+    assert f(16, 4, 4, 4, FAKE, 4, FAKE, 4, 1e-15)[0] == oz.ERR_INVALID_ARG
+    assert f(64, 4, 4, 4, FAKE, 4, FAKE, 4, 0.0)[0] == oz.ERR_INVALID_ARG
+    assert f(64, 4, 4, 4, FAKE, 3, FAKE, 4, 1e-15)[0] == oz.ERR_INVALID_ARG     # lda < m
+    assert f(64, 4, 4, 4, None, 4, FAKE, 4, 1e-15)[0] == oz.ERR_INVALID_ARG
+    assert f(64, 4, 4, 2 ** 18, FAKE, 4, FAKE, 2 ** 18, 1e-15)[0] == oz.ERR_K_RANGE
+    assert f(32, 0, 4, 4, None, 1, FAKE, 4, 1e-6) == (oz.OK, 2)

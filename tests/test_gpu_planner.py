@@ -133,3 +133,25 @@ def test_required_moduli_exact_zero_entry_is_skipped():
     hi = required_moduli_from_terms(terms, 1e-12 * (1 - slack(90)))
     check_between(rc, Ng, lo, hi, 49)
     assert rc == oz.OK
+
+
+@pytest.mark.parametrize("m,n,k,phi,eps,dt", [
+    (120, 90, 200, 0.5, 1e-15, np.complex128),
+    (70, 65, 300, 3.0, 1e-15, np.complex128),
+    (50, 40, 100, 1.0, 1e-6, np.complex64),
+])
+def test_complex_required_moduli(m, n, k, phi, eps, dt):
+    # ozaki2_zrequired_moduli is the planner on the real embedding on which
+    # ozaki2_zgemm runs: its N lies in the oracle's bracket for the embedded
+    # matrices (2k terms per entry).
+    from oracle.complex_gemm import real_embedding
+    from workload import complex_gemm_inputs
+    announce(f"complex planner m={m} n={n} k={k} phi={phi} eps={eps}")
+    A, B = complex_gemm_inputs(m, n, k, phi=phi, seed=m + n, dtype=dt)
+    rc, Ng = oz.required_moduli(dev(A), dev(B), eps)
+    Ah, Bh = real_embedding(A, B)
+    b = 64 if dt == np.complex128 else 32
+    terms = planner_terms(Ah, Bh)
+    lo = required_moduli_from_terms(terms, eps * (1 + 1e-9), b)
+    hi = required_moduli_from_terms(terms, eps * (1 - slack(2 * k)), b)
+    check_between(rc, Ng, lo, hi, 49 if b == 64 else 16)
