@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--complex", type=int, default=0, metavar="SIZE",
                     help="only measure complex FP64 SIZE^3 (ozaki2_zgemm and ozaki2_zgemm3m, "
                          "N = 14..17, against native complex128) and print it as one JSON object")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="also run the library's MFMA-rate probe (the residue products' INT8 MFMA "
+                         "on changing operands, no memory traffic): the rate the chip sustains for "
+                         "that instruction under its power limit")
     ap.add_argument("--extras", action="store_true",
                     help="also measure the 4096^3 phi sweep (N from the bound at 1e-15), the "
                          "certified call at 1e-14 on the same inputs, and the FP32 16384^3 "
@@ -69,6 +73,26 @@ def _time_ms(torch, f, reps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def mfma_probe(oz, kernel_tops: float) -> dict:
+    """The MFMA-rate probe: best of three runs of 8192 steps after a short
+    warm-up, in TOPS, and the residue products' rate as a fraction of it."""
+    rc, _, _ = oz.ozaki2_debug_mfma_probe(256)
+    if rc != oz.OK:
+        raise oz.Ozaki2Error("ozaki2_debug_mfma_probe", rc)
+    best = None
+    for _ in range(3):
+        rc, ms, ops = oz.ozaki2_debug_mfma_probe(8192)
+        if rc != oz.OK:
+            raise oz.Ozaki2Error("ozaki2_debug_mfma_probe", rc)
+        tops = ops / (ms * 1e-3) / 1e12
+        if best is None or tops > best["tops"]:
+            best = {"ms": round(ms, 4), "ops": ops, "tops": round(tops, 1)}
+    best["residue_products_frac_of_probe"] = round(kernel_tops / best["tops"], 4)
+    best["what"] = ("v_mfma_i32_32x32x32_i8 back to back on operands changing every step, "
+                    "one workgroup of 8 waves per CU, no memory traffic")
+    return best
 
 
 def extras_measurement(torch, oz) -> dict:
@@ -626,6 +650,8 @@ def main():
     torch.cuda.empty_cache()
     if args.vendor_int8:
         out["vendor_int8"] = vendor_int8(torch, dev, m)
+    if args.mfma_probe:
+        out["mfma_probe"] = mfma_probe(oz, out["roofline"]["achieved"])
     if not args.no_batched:
         out["batched"] = batched_measurement(torch, oz, max(1, min(args.steps, 10)))
     if args.extras:

@@ -332,6 +332,18 @@ int ozaki2_debug_stages(int prec, int m, int n, int k, const void *A, int lda, c
 int ozaki2_debug_log2f(const float *d, float *out, int count);
 
 /*
+ * ozaki2_debug_mfma_probe - a measurement aid for the roofline of the residue
+ * products: one workgroup of 8 waves per CU issues `iters` steps of 8
+ * v_mfma_i32_32x32x32_i8 (the residue products' instruction, 2 x 32^3 INT8
+ * operations each) on operands that change every step, with no memory
+ * traffic.  *ms (HOST) receives its duration, *ops (HOST) its operation count;
+ * ops / ms is the INT8 rate the chip sustains for that instruction under its
+ * power limit.  Synchronises the stream.  OZAKI2_ERR_INVALID_ARG for iters < 1
+ * or NULL outputs.
+ */
+int ozaki2_debug_mfma_probe(int iters, float *ms, double *ops);
+
+/*
  * ozaki2_profile - per-kernel timing with HIP events on the library stream.
  *   enable != 0 turns recording on (and clears previous records); 0 off.
  * ozaki2_profile_read copies up to `cap` records (name index, milliseconds)

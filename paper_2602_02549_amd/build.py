@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libozaki2.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = ["tables.cpp", "api.cpp", "scale.hip", "residue.hip", "gemm_i8.hip", "crt.hip",
-           "plan.hip", "noalloc.hip", "complex.hip"]
+           "plan.hip", "noalloc.hip", "complex.hip", "probe.hip"]
 
 # -ffp-contract=off: every fused multiply-add in the library is an explicit
 # fma(); the CRT and double-double code rely on single roundings elsewhere.

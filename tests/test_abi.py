@@ -248,3 +248,7 @@ def test_complex_planner_argument_errors():
     assert f(64, 4, 4, 4, None, 4, FAKE, 4, 1e-15)[0] == oz.ERR_INVALID_ARG
     assert f(64, 4, 4, 2 ** 18, FAKE, 4, FAKE, 2 ** 18, 1e-15)[0] == oz.ERR_K_RANGE
     assert f(32, 0, 4, 4, None, 1, FAKE, 4, 1e-6) == (oz.OK, 2)
+
+
+def test_mfma_probe_argument_errors():
+    assert oz.ozaki2_debug_mfma_probe(0)[0] == oz.ERR_INVALID_ARG
