@@ -53,9 +53,10 @@ def parse():
                     help="only measure complex FP64 SIZE^3 (ozaki2_zgemm and ozaki2_zgemm3m, "
                          "N = 14..17, against native complex128) and print it as one JSON object")
     ap.add_argument("--mfma-probe", action="store_true",
-                    help="also run the library's MFMA-rate probe (the residue products' INT8 MFMA "
-                         "on changing operands, no memory traffic): the rate the chip sustains for "
-                         "that instruction under its power limit")
+                    help="run the library's MFMA-rate probe (the residue products' INT8 MFMA on "
+                         "changing operands, no memory traffic: the rate the chip sustains for that "
+                         "instruction under its power limit); on by default")
+    ap.add_argument("--no-mfma-probe", action="store_true", help="skip the MFMA-rate probe")
     ap.add_argument("--extras", action="store_true",
                     help="also measure the 4096^3 phi sweep (N from the bound at 1e-15), the "
                          "certified call at 1e-14 on the same inputs, and the FP32 16384^3 "
@@ -650,7 +651,7 @@ def main():
     torch.cuda.empty_cache()
     if args.vendor_int8:
         out["vendor_int8"] = vendor_int8(torch, dev, m)
-    if args.mfma_probe:
+    if not args.no_mfma_probe:
         out["mfma_probe"] = mfma_probe(oz, out["roofline"]["achieved"])
     if not args.no_batched:
         out["batched"] = batched_measurement(torch, oz, max(1, min(args.steps, 10)))
