@@ -490,16 +490,15 @@ ZLayout zlayout(int m, int n, int k, int N, size_t s) {
 
 // Argument checks of the complex calls (leading dimensions in complex
 // elements).  kmax: the largest k of the form (the embedding doubles k; the
-// 3-product form keeps it).
+// 3-product form keeps it).  needC: the call writes C (the planner does not).
 int check_complex_args(int m, int n, int k, const void* A, int lda, const void* B, int ldb,
-                       const void* C, int ldc, int kmax) {
+                       const void* C, int ldc, int kmax, bool needC = true) {
   if (m < 0 || n < 0 || k < 0 || m > kMaxDim / 2 || n > kMaxDim) return OZAKI2_ERR_INVALID_ARG;
-  if (lda < (m > 1 ? m : 1) || ldb < (k > 1 ? k : 1) || ldc < (m > 1 ? m : 1))
-    return OZAKI2_ERR_INVALID_ARG;
-  if (ldc > INT32_MAX / 2) return OZAKI2_ERR_INVALID_ARG;
+  if (lda < (m > 1 ? m : 1) || ldb < (k > 1 ? k : 1)) return OZAKI2_ERR_INVALID_ARG;
+  if (needC && (ldc < (m > 1 ? m : 1) || ldc > INT32_MAX / 2)) return OZAKI2_ERR_INVALID_ARG;
   if ((size_t)m * k > 0 && !A) return OZAKI2_ERR_INVALID_ARG;
   if ((size_t)k * n > 0 && !B) return OZAKI2_ERR_INVALID_ARG;
-  if ((size_t)m * n > 0 && !C) return OZAKI2_ERR_INVALID_ARG;
+  if (needC && (size_t)m * n > 0 && !C) return OZAKI2_ERR_INVALID_ARG;
   if (k > kmax) return OZAKI2_ERR_K_RANGE;
   return OZAKI2_OK;
 }
@@ -1356,8 +1355,7 @@ int ozaki2_zrequired_moduli(int prec, int m, int n, int k, const void* A, int ld
                             int ldb, double eps, int* N_out) {
   if (prec != 64 && prec != 32) return OZAKI2_ERR_INVALID_ARG;
   if (!N_out || !(eps > 0.0) || !(eps < INFINITY)) return OZAKI2_ERR_INVALID_ARG;
-  // no C: any non-null stand-in satisfies the output check
-  int rc = check_complex_args(m, n, k, A, lda, B, ldb, N_out, m > 1 ? m : 1, kMaxK / 2);
+  int rc = check_complex_args(m, n, k, A, lda, B, ldb, nullptr, 0, kMaxK / 2, false);
   if (rc) return rc;
   const int nhi = prec == 64 ? kMaxModuli : 16;
   if (m == 0 || n == 0 || k == 0) {  // AB = 0 is represented exactly

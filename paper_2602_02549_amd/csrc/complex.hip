@@ -15,6 +15,7 @@
 #include <cstdint>
 
 #include "ozaki2_internal.h"
+#include "small_mod.h"
 
 namespace oz2 {
 namespace {
@@ -90,31 +91,6 @@ __global__ __launch_bounds__(kThreads) void k_add_bars(const int8_t* __restrict_
     reinterpret_cast<int4*>(out)[t] = r;
   }
 }
-
-// mod(x, p) in the symmetric INT8 range of Section 1.2 ([-(p-1)/2, (p-1)/2]
-// for odd p, [-128, 127] for p = 256; hi = (p - 1) / 2) for |x| < 2^10: the
-// FP32 quotient x (1/p) is within 2^-13 of x/p, so its rounding is within
-// one of the nearest quotient, and one correction either way lands r in the
-// range.
-__device__ inline int mod_small(int x, int p, float pinv, int hi) {
-  int r = x - (int)rintf((float)x * pinv) * p;
-  r -= r > hi ? p : 0;
-  r += r < hi + 1 - p ? p : 0;
-  return r;
-}
-
-// Signed byte i of a 32-bit word.
-__device__ inline int sbyte(uint32_t w, int i) { return (int)(w << (24 - 8 * i)) >> 24; }
-
-struct SmallMod {
-  int p, hi;
-  float pinv;
-  __device__ explicit SmallMod(const CrtConsts& cc, int l)
-      : p(cc.p[l]), hi((cc.p[l] - 1) / 2), pinv((float)cc.pinv[l]) {}
-  __device__ uint32_t byte(int x, int i) const {
-    return (uint32_t)(mod_small(x, p, pinv, hi) & 0xFF) << (8 * i);
-  }
-};
 
 // Residues of A'r + A'i: slice l of X3 = mod(X1 + X2, p_l), N slices of
 // 16 * per16 bytes; workgroup row blockIdx.y is slice l, 16 bytes a thread.

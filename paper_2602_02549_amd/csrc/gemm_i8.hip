@@ -37,6 +37,7 @@
 #include <type_traits>
 
 #include "ozaki2_internal.h"
+#include "small_mod.h"
 
 namespace oz2 {
 namespace {
@@ -688,16 +689,6 @@ __global__ __launch_bounds__(tile_threads<B>(), TileShape<B>::OCC) void k_gemm_i
 }
 
 // ---- split-k reductions ------------------------------------------------------
-// mod(x, p) in the range of Section 1.2 ([hi + 1 - p, hi], hi = (p - 1) / 2)
-// for |x| < 2^14: the FP32 quotient x (1/p) is within one of the nearest
-// integer to x/p, and one correction either way lands r in the range.
-__device__ inline int mod_small(int x, int p, float pinv, int hi) {
-  int r = x - (int)rintf((float)x * pinv) * p;
-  r -= r > hi ? p : 0;
-  r += r < hi + 1 - p ? p : 0;
-  return r;
-}
-
 // W (EPI 0): slice z = mod(sum over s of partial slice s * nz + z, p_z); each
 // partial is in [-128, 127], so for nsplit <= 64 the sum stays below 2^13 in
 // magnitude.  Workgroup row blockIdx.y is slice z; 16 bytes a thread.
@@ -705,8 +696,7 @@ __global__ __launch_bounds__(256) void k_reduce_w(const int8_t* __restrict__ par
                                                   int nz, int64_t sw16, CrtConsts cc,
                                                   int8_t* __restrict__ W) {
   const int z = blockIdx.y;
-  const int p = cc.p[z], hi = (p - 1) / 2;
-  const float pinv = (float)cc.pinv[z];
+  const SmallMod md(cc, z);
   const uint4* src = reinterpret_cast<const uint4*>(part);
   uint4* dst = reinterpret_cast<uint4*>(W) + z * sw16;
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < sw16;
@@ -718,12 +708,11 @@ __global__ __launch_bounds__(256) void k_reduce_w(const int8_t* __restrict__ par
       const uint4 v = src[((int64_t)sidx * nz + z) * sw16 + t];
       const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[e] += (int)(w[e >> 2] << (24 - 8 * (e & 3))) >> 24;
+      for (int e = 0; e < 16; ++e) acc[e] += sbyte(w[e >> 2], e & 3);
     }
     uint32_t o[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
-      o[e >> 2] |= (uint32_t)(mod_small(acc[e], p, pinv, hi) & 0xFF) << (8 * (e & 3));
+    for (int e = 0; e < 16; ++e) o[e >> 2] |= md.byte(acc[e], e & 3);
     dst[t] = make_uint4(o[0], o[1], o[2], o[3]);
   }
 }
