@@ -338,8 +338,8 @@ int ozaki2_debug_log2f(const float *d, float *out, int count);
  * operations each) on operands that change every step, with no memory
  * traffic.  *ms (HOST) receives its duration, *ops (HOST) its operation count;
  * ops / ms is the INT8 rate the chip sustains for that instruction under its
- * power limit.  Synchronises the stream.  OZAKI2_ERR_INVALID_ARG for iters < 1
- * or NULL outputs.
+ * power limit.  Synchronises the stream.  OZAKI2_ERR_INVALID_ARG for iters
+ * outside [1, 2^20] (2^20 steps take about 0.4 s) or NULL outputs.
  */
 int ozaki2_debug_mfma_probe(int iters, float *ms, double *ops);
 

@@ -333,8 +333,10 @@ def zgemm(A, B, N: int, form: str = "4m"):
     _set_current_stream()
     if form == "3m":
         f = ozaki2_zgemm3m if A.dtype == torch.complex128 else ozaki2_cgemm3m
-    else:
+    elif form == "4m":
         f = ozaki2_zgemm if A.dtype == torch.complex128 else ozaki2_cgemm
+    else:
+        raise ValueError(f"form must be '4m' or '3m', not {form!r}")
     rc = f(m, n, k, Acm.data_ptr(), max(m, 1), Bcm.data_ptr(), max(k, 1), Ccm.data_ptr(), max(m, 1), N)
     if rc != OK:
         raise Ozaki2Error("ozaki2_zgemm", rc)

@@ -1509,7 +1509,7 @@ int ozaki2_debug_stages(int prec, int m, int n, int k, const void* A, int lda, c
 }
 
 int ozaki2_debug_mfma_probe(int iters, float* ms, double* ops) {
-  if (iters < 1 || !ms || !ops) return OZAKI2_ERR_INVALID_ARG;
+  if (iters < 1 || iters > (1 << 20) || !ms || !ops) return OZAKI2_ERR_INVALID_ARG;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
