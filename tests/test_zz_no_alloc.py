@@ -51,6 +51,19 @@ def test_noalloc_matches_gemm_on_consecutive_calls(prec):
     assert oz.ozaki2_sync_status() == oz.OK
 
 
+def test_noalloc_split_k():
+    # A small output with long k splits its products; the partial results
+    # live in the fixed scratch array too.  Two calls in a row, the second
+    # smaller (fewer splits), against ozaki2_gemm.
+    for m, n, k, N, seed in [(64, 48, 32768, 14, 11), (40, 30, 9000, 10, 12)]:
+        announce(f"noalloc split-k m={m} n={n} k={k} N={N}")
+        A, B = gemm_inputs(m, n, k, phi=1.0, seed=seed)
+        got = _call("noalloc", 64, A, B, N)
+        ref = _call("workspace", 64, A, B, N)
+        assert np.array_equal(got, ref), f"{int(np.sum(got != ref))} entries differ"
+    assert oz.ozaki2_sync_status() == oz.OK
+
+
 def test_noalloc_edge_cases_and_status():
     announce("noalloc edge cases: k = 0, non-finite input, rejection")
     # k = 0 writes zeros
