@@ -77,23 +77,27 @@ def _time_ms(torch, f, reps):
 
 
 def mfma_probe(oz, kernel_tops: float) -> dict:
-    """The MFMA-rate probe: best of three runs of 8192 steps after a short
-    warm-up, in TOPS, and the residue products' rate as a fraction of it."""
-    rc, _, _ = oz.ozaki2_debug_mfma_probe(256)
-    if rc != oz.OK:
-        raise oz.Ozaki2Error("ozaki2_debug_mfma_probe", rc)
-    best = None
-    for _ in range(3):
-        rc, ms, ops = oz.ozaki2_debug_mfma_probe(8192)
+    """The MFMA-rate probe, on changing and on fixed operands: best of three
+    runs of 8192 steps after a short warm-up, in TOPS, and the residue
+    products' rate as a fraction of the changing-operand rate."""
+    out = {}
+    for name, changing in (("changing_operands", 1), ("fixed_operands", 0)):
+        rc, _, _ = oz.ozaki2_debug_mfma_probe(256, changing)
         if rc != oz.OK:
             raise oz.Ozaki2Error("ozaki2_debug_mfma_probe", rc)
-        tops = ops / (ms * 1e-3) / 1e12
-        if best is None or tops > best["tops"]:
-            best = {"ms": round(ms, 4), "ops": ops, "tops": round(tops, 1)}
-    best["residue_products_frac_of_probe"] = round(kernel_tops / best["tops"], 4)
-    best["what"] = ("v_mfma_i32_32x32x32_i8 back to back on operands changing every step, "
-                    "one workgroup of 8 waves per CU, no memory traffic")
-    return best
+        best = None
+        for _ in range(3):
+            rc, ms, ops = oz.ozaki2_debug_mfma_probe(8192, changing)
+            if rc != oz.OK:
+                raise oz.Ozaki2Error("ozaki2_debug_mfma_probe", rc)
+            tops = ops / (ms * 1e-3) / 1e12
+            if best is None or tops > best["tops"]:
+                best = {"ms": round(ms, 4), "ops": ops, "tops": round(tops, 1)}
+        out[name] = best
+    out["residue_products_frac_of_probe"] = round(kernel_tops / out["changing_operands"]["tops"], 4)
+    out["what"] = ("v_mfma_i32_32x32x32_i8 back to back, one workgroup of 8 waves per CU, no memory "
+                   "traffic; operands changing every step, or fixed")
+    return out
 
 
 def extras_measurement(torch, oz) -> dict:
@@ -653,6 +657,9 @@ def main():
         out["vendor_int8"] = vendor_int8(torch, dev, m)
     if not args.no_mfma_probe:
         out["mfma_probe"] = mfma_probe(oz, out["roofline"]["achieved"])
+        # the whole call's (N + 1) 2mnk against the measured ceiling as well
+        out["mfma_probe"]["whole_call_frac_of_probe"] = round(
+            out["int8_fraction_whole_call"] * PEAK_INT8_TOPS / out["mfma_probe"]["changing_operands"]["tops"], 4)
     if not args.no_batched:
         out["batched"] = batched_measurement(torch, oz, max(1, min(args.steps, 10)))
     if args.extras:

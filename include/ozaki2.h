@@ -335,13 +335,15 @@ int ozaki2_debug_log2f(const float *d, float *out, int count);
  * ozaki2_debug_mfma_probe - a measurement aid for the roofline of the residue
  * products: one workgroup of 8 waves per CU issues `iters` steps of 8
  * v_mfma_i32_32x32x32_i8 (the residue products' instruction, 2 x 32^3 INT8
- * operations each) on operands that change every step, with no memory
- * traffic.  *ms (HOST) receives its duration, *ops (HOST) its operation count;
- * ops / ms is the INT8 rate the chip sustains for that instruction under its
- * power limit.  Synchronises the stream.  OZAKI2_ERR_INVALID_ARG for iters
- * outside [1, 2^20] (2^20 steps take about 0.4 s) or NULL outputs.
+ * operations each), with no memory traffic, on operands that change every
+ * step (changing = 1: the rate the chip sustains for that instruction on
+ * changing data under its power limit) or stay fixed (changing = 0: the
+ * issue rate with little data toggling).  *ms (HOST) receives its duration,
+ * *ops (HOST) its operation count.  Synchronises the stream.
+ * OZAKI2_ERR_INVALID_ARG for iters outside [1, 2^20] (2^20 steps take about
+ * 0.4 s), changing not 0 or 1, or NULL outputs.
  */
-int ozaki2_debug_mfma_probe(int iters, float *ms, double *ops);
+int ozaki2_debug_mfma_probe(int iters, int changing, float *ms, double *ops);
 
 /*
  * ozaki2_profile - per-kernel timing with HIP events on the library stream.

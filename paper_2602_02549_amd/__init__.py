@@ -37,7 +37,8 @@ _SIGS = {
     "ozaki2_sgemm": ([_c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_int], _c_int),
     "ozaki2_required_moduli": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_double,
                                 ctypes.POINTER(_c_int)], _c_int),
-    "ozaki2_debug_mfma_probe": ([_c_int, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_c_double)], _c_int),
+    "ozaki2_debug_mfma_probe": ([_c_int, _c_int, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_c_double)],
+                                _c_int),
     "ozaki2_zrequired_moduli": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int,
                                  _c_double, ctypes.POINTER(_c_int)], _c_int),
     "ozaki2_gemm_certified": ([_c_int, _c_int, _c_int, _c_int, _c_ptr, _c_int, _c_ptr, _c_int, _c_ptr, _c_int,
@@ -109,11 +110,11 @@ def ozaki2_sgemm(m, n, k, A, lda, B, ldb, C, ldc, N):
     return _call("ozaki2_sgemm", m, n, k, A, lda, B, ldb, C, ldc, N)
 
 
-def ozaki2_debug_mfma_probe(iters):
+def ozaki2_debug_mfma_probe(iters, changing=1):
     """(rc, ms, ops) of the MFMA-rate probe."""
     ms = ctypes.c_float(0.0)
     ops = _c_double(0.0)
-    rc = _call("ozaki2_debug_mfma_probe", iters, ctypes.byref(ms), ctypes.byref(ops))
+    rc = _call("ozaki2_debug_mfma_probe", iters, changing, ctypes.byref(ms), ctypes.byref(ops))
     return rc, ms.value, ops.value
 
 

@@ -1508,13 +1508,14 @@ int ozaki2_debug_stages(int prec, int m, int n, int k, const void* A, int lda, c
                    m > 1 ? m : 1, N, all);
 }
 
-int ozaki2_debug_mfma_probe(int iters, float* ms, double* ops) {
+int ozaki2_debug_mfma_probe(int iters, int changing, float* ms, double* ops) {
   if (iters < 1 || iters > (1 << 20) || !ms || !ops) return OZAKI2_ERR_INVALID_ARG;
+  if (changing != 0 && changing != 1) return OZAKI2_ERR_INVALID_ARG;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return OZAKI2_ERR_HIP;
-  return probe_mfma(g_stream, cus, iters, ms, ops);
+  return probe_mfma(g_stream, cus, iters, changing != 0, ms, ops);
 }
 
 int ozaki2_debug_log2f(const float* d, float* out, int count) {

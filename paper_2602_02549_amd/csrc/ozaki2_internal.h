@@ -317,8 +317,9 @@ int gemm_on_buffer(Prec pr, int m, int n, int k, const void* A, int lda, const v
 int* noalloc_status(int dev);
 
 // probe.hip: the MFMA-rate probe (ozaki2_debug_mfma_probe): `blocks`
-// workgroups of 8 waves, `iters` steps of 8 MFMAs each; returns its duration
-// (ms, HIP events on s, synchronised) and its INT8 operation count.
-int probe_mfma(hipStream_t s, int blocks, int iters, float* ms, double* ops);
+// workgroups of 8 waves, `iters` steps of 8 MFMAs each, operands changing
+// every step or fixed; returns its duration (ms, HIP events on s,
+// synchronised) and its INT8 operation count.
+int probe_mfma(hipStream_t s, int blocks, int iters, bool change, float* ms, double* ops);
 
 }  // namespace oz2

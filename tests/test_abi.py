@@ -253,3 +253,4 @@ def test_complex_planner_argument_errors():
 def test_mfma_probe_argument_errors():
     assert oz.ozaki2_debug_mfma_probe(0)[0] == oz.ERR_INVALID_ARG
     assert oz.ozaki2_debug_mfma_probe(2 ** 20 + 1)[0] == oz.ERR_INVALID_ARG
+    assert oz.ozaki2_debug_mfma_probe(16, 2)[0] == oz.ERR_INVALID_ARG

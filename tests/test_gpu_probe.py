@@ -15,6 +15,8 @@ def test_probe_rate_is_physical():
     rc, ms, ops = oz.ozaki2_debug_mfma_probe(512)
     assert rc == oz.OK and ms > 0
     assert ops == torch.cuda.get_device_properties(0).multi_processor_count * 8 * 512 * 8 * 65536
-    rc, ms, ops = oz.ozaki2_debug_mfma_probe(4096)
-    tops = ops / (ms * 1e-3) / 1e12
-    assert 100.0 < tops < 5000.0 * 1.05
+    for changing in (1, 0):
+        rc, ms, ops = oz.ozaki2_debug_mfma_probe(4096, changing)
+        assert rc == oz.OK
+        tops = ops / (ms * 1e-3) / 1e12
+        assert 100.0 < tops < 5000.0 * 1.05, (changing, tops)
