@@ -31,6 +31,7 @@ def delta(k):
     (70, 65, 200, 20, 2.0, np.float64),
     (60, 50, 150, 49, 4.0, np.float64),
     (64, 50, 150, 7, 0.5, np.float32),
+    (40, 30, 6000, 14, 1.0, np.float64),    # small output, long k: split residue products
 ])
 def test_certified_ratio_at_fixed_N(m, n, k, N, phi, dtype):
     announce(f"certified ratio m={m} n={n} k={k} N={N} phi={phi} {np.dtype(dtype).name}")
