@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--complex", type=int, default=0, metavar="SIZE",
                     help="only measure complex FP64 SIZE^3 (ozaki2_zgemm and ozaki2_zgemm3m, "
                          "N = 14..17, against native complex128) and print it as one JSON object")
+    ap.add_argument("--complex-single", action="store_true",
+                    help="with --complex: complex FP32 (ozaki2_cgemm, ozaki2_cgemm3m, N = 6..8, "
+                         "against native complex64)")
     ap.add_argument("--mfma-probe", action="store_true",
                     help="run the library's MFMA-rate probe (the residue products' INT8 MFMA on "
                          "changing operands, no memory traffic: the rate the chip sustains for that "
@@ -182,17 +185,20 @@ def extras_measurement(torch, oz) -> dict:
     return out
 
 
-def complex_measurement(torch, oz, rng, n: int = 4096) -> dict:
+def complex_measurement(torch, oz, rng, n: int = 4096, single: bool = False) -> dict:
     """Complex FP64 n^3 (ZGEMM emulation through the real embedding, and
-    the 3-product form) against native complex128 matmul: time, effective
-    TFLOPS (8 m n k / t, the real flops of a complex product) and sampled
-    error relative to (|Ar|+|Ai|)(|Br|+|Bi|) -- the real embedding's |A||B|
-    -- for N = 14..17, and the smallest N matching the native error."""
+    the 3-product form; with `single` complex FP32, CGEMM) against native
+    complex matmul: time, effective TFLOPS (8 m n k / t, the real flops of a
+    complex product) and sampled error relative to (|Ar|+|Ai|)(|Br|+|Bi|) --
+    the real embedding's |A||B| -- for N = 14..17 (FP32: 6..8), and the
+    smallest N matching the native error."""
     from workload import complex_gemm_inputs
     from workload.reference import ExactSamples
 
     dev = torch.device("cuda:0")
-    A, B = complex_gemm_inputs(n, n, n, phi=0.5, seed=0)
+    dt = np.complex64 if single else np.complex128
+    tdt = torch.complex64 if single else torch.complex128
+    A, B = complex_gemm_inputs(n, n, n, phi=0.5, seed=0, dtype=dt)
     rows = np.sort(rng.choice(n, 8, replace=False))
     cols = np.sort(rng.choice(n, 8, replace=False))
     # exact samples of the real embedding: rows of Re and of Im
@@ -202,7 +208,7 @@ def complex_measurement(torch, oz, rng, n: int = 4096) -> dict:
     dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
     del A, B, Bhat
     Acm, Bcm = oz.col_major(dA), oz.col_major(dB)
-    Ccm = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    Ccm = torch.empty((n, n), dtype=tdt, device=dev)
     ri, ci = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
 
     def sampled(Ct):
@@ -213,9 +219,11 @@ def complex_measurement(torch, oz, rng, n: int = 4096) -> dict:
     nat_ms = _time_ms(torch, lambda: torch.matmul(dA, dB), 3)
     nat_err = sampled(torch.matmul(dA, dB))
     res, res3 = {}, {}
-    for N in (14, 15, 16, 17):
-        for name, f, out in (("ozaki2_zgemm", oz.ozaki2_zgemm, res),
-                             ("ozaki2_zgemm3m", oz.ozaki2_zgemm3m, res3)):
+    calls = ((("ozaki2_cgemm", oz.ozaki2_cgemm, res), ("ozaki2_cgemm3m", oz.ozaki2_cgemm3m, res3))
+             if single else
+             (("ozaki2_zgemm", oz.ozaki2_zgemm, res), ("ozaki2_zgemm3m", oz.ozaki2_zgemm3m, res3)))
+    for N in ((6, 7, 8) if single else (14, 15, 16, 17)):
+        for name, f, out in calls:
             def emu():
                 r = f(n, n, n, Acm.data_ptr(), n, Bcm.data_ptr(), n, Ccm.data_ptr(), n, N)
                 if r != oz.OK:
@@ -228,7 +236,7 @@ def complex_measurement(torch, oz, rng, n: int = 4096) -> dict:
     matched3 = next((int(k) for k, v in res3.items() if v["rel_err_sampled"] <= nat_err), None)
     del dA, dB, Acm, Bcm, Ccm
     torch.cuda.empty_cache()
-    return {"workload": f"complex FP64 {n}^3, each part (U-0.5)exp(0.5 Z), seed 0",
+    return {"workload": f"complex FP{32 if single else 64} {n}^3, each part (U-0.5)exp(0.5 Z), seed 0",
             "native_ms": round(nat_ms, 3), "native_tflops": round(flops / (nat_ms * 1e-3) / 1e12, 2),
             "native_rel_err_sampled": nat_err, "emulated": res, "matched_N": matched,
             "emulated_3m": res3, "matched_N_3m": matched3}
@@ -506,7 +514,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.complex:
         oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
-        res = complex_measurement(torch, oz, np.random.default_rng(4321), args.complex)
+        torch.backends.cuda.matmul.allow_tf32 = False
+        res = complex_measurement(torch, oz, np.random.default_rng(4321), args.complex,
+                                  single=args.complex_single)
         print(json.dumps({"complex": res}), flush=True)
         return
     m = n = k = args.size
