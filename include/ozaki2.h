@@ -277,7 +277,9 @@ int ozaki2_sync_status(void);
  * The first call with a given batch (sizes, N, pointers, leading dimensions
  * and workspace) builds a device problem table, runs the batch once, times
  * the residue products under each tile split and form (one workgroup per
- * tile or persistent workgroups) on the residues that run produced,
+ * tile, persistent workgroups, and, in a batch of at most 64 problems of
+ * which some split k, one launch per problem) on the residues that run
+ * produced,
  * captures the launch sequence with the fastest into a hipGraph and
  * synchronises the stream; later calls with the same batch replay the graph
  * asynchronously and allocate nothing.  Up to eight batches stay cached per
@@ -372,7 +374,12 @@ const char *ozaki2_profile_name(int phase);
  *                                  (default), 0 = enqueue its kernels directly
  *   OZAKI2_KNOB_BATCH_PERSIST    : batched residue products: -1 = autotune
  *                                  (default), 0 = one workgroup per tile,
- *                                  1 = persistent workgroups
+ *                                  1 = persistent workgroups, 2 = one
+ *                                  launch per problem for the scaling and
+ *                                  residue products, splitting k where a
+ *                                  problem's output leaves the GPU idle
+ *                                  (split-k scratch is held for batches of
+ *                                  at most 64 problems)
  *   OZAKI2_KNOB_SPLIT_K          : single-problem products: 0 = split k
  *                                  when few output tiles would leave the
  *                                  compute units idle (default), 1 = never

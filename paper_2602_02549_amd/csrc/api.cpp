@@ -680,6 +680,14 @@ struct BatchEntry {
   size_t map_off[BS_COUNT] = {};         // byte offset of each slot's block map
   int split = 0;                         // problems with >= split 256x256 tiles use them
   bool persist = false;                  // residue products: persistent kernels
+  // One launch per problem for the scaling and residue products (the
+  // single-problem launcher, which splits k where a problem's output leaves
+  // the GPU idle), for batches of at most kPerProblemMax problems.
+  bool per_problem = false;
+  std::vector<ProbDesc> hd;              // host copies of the descriptors
+  std::vector<CrtConsts> hc;             // constants of each problem's N
+  std::vector<int8_t*> part;             // split-k scratch of each problem (may be empty)
+  std::vector<size_t> part_bytes;
   bool fold = false;                     // some k_pad > 2^17 (reduction mod p inside k)
   int pgrid[2] = {0, 0};                 // resident workgroups of the persistent kernels (256, 128)
   int res_path = -1;                     // residue path code for the grouped slice kernels
@@ -707,6 +715,7 @@ struct BatchEntry {
 std::atomic<int> g_batch_split{-1};
 std::atomic<int> g_batch_graph{1};
 std::atomic<int> g_batch_persist{-1};
+constexpr int kPerProblemMax = 64;   // batches up to this many problems may run per problem
 
 // Device table of CrtConsts indexed by N (entries below 2 unused).
 int get_ctab(int b, CrtConsts** out) {
@@ -807,6 +816,15 @@ bool table_fits(const int blocks[BS_COUNT]) {
 
 // The residue products of a batch, in the entry's form.
 void enqueue_residue_products(const BatchEntry& e, const CrtConsts* ctab, hipStream_t s) {
+  if (e.per_problem) {
+    for (size_t q = 0; q < e.hd.size(); ++q) {
+      const ProbDesc& d = e.hd[q];
+      launch_gemm_i8(s, 0, d.As, (size_t)d.mp * d.kp, d.Bs, (size_t)d.np * d.kp, d.mp, d.np, d.kp,
+                     d.N, e.hc[q], d.W, (size_t)d.np * d.mp, d.mp, nullptr, nullptr, e.part[q],
+                     e.part_bytes[q]);
+    }
+    return;
+  }
   const ProbDesc* D = reinterpret_cast<const ProbDesc*>(e.table);
   auto M = [&](int sl) { return reinterpret_cast<const BlockRef*>(e.table + e.map_off[sl]); };
   if (e.persist) {
@@ -834,8 +852,16 @@ void enqueue_batch(Prec pr, const BatchEntry& e, const CrtConsts* ctab, int* sta
   launch_group_scale(s, pr, GP_ABSBAR_B, D, M(BS_ABB), B(BS_ABB), ctab);
   launch_group_slices(s, pr, 0, true, -1, D, M(BS_SL_A), B(BS_SL_A), ctab);
   launch_group_slices(s, pr, 0, false, -1, D, M(BS_BAR_B), B(BS_BAR_B), ctab);
-  launch_group_gemm(s, 1, 256, D, M(BS_GS_BIG), B(BS_GS_BIG), ctab);
-  launch_group_gemm(s, 1, 128, D, M(BS_GS_SMALL), B(BS_GS_SMALL), ctab);
+  if (e.per_problem) {
+    for (size_t q = 0; q < e.hd.size(); ++q) {
+      const ProbDesc& d = e.hd[q];
+      launch_gemm_i8(s, 1, d.As, 0, d.Bs, 0, d.mp, d.np, d.kp, 1, e.hc[q], nullptr, 0, 0, d.rmax,
+                     d.cmax, e.part[q], e.part_bytes[q]);
+    }
+  } else {
+    launch_group_gemm(s, 1, 256, D, M(BS_GS_BIG), B(BS_GS_BIG), ctab);
+    launch_group_gemm(s, 1, 128, D, M(BS_GS_SMALL), B(BS_GS_SMALL), ctab);
+  }
   launch_group_scale(s, pr, GP_SHIFTS, D, M(BS_SHIFTS), B(BS_SHIFTS), ctab);
   launch_group_slices(s, pr, 1, true, e.res_path, D, M(BS_SL_A), B(BS_SL_A), ctab);
   launch_group_slices(s, pr, 1, false, e.res_path, D, M(BS_SL_B), B(BS_SL_B), ctab);
@@ -869,8 +895,12 @@ int tune_batch(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* c
                hipStream_t s, int forced_split, int forced_persist) {
   std::vector<int> splits = forced_split >= 0 ? std::vector<int>{forced_split}
                                               : std::vector<int>{1 << 30, 16, 4, 0};
+  // form 2 (one launch per problem) only where some problem splits its k
+  bool any_part = false;
+  for (size_t q = 0; q < e->part_bytes.size(); ++q) any_part = any_part || e->part_bytes[q] > 0;
   std::vector<int> forms = forced_persist >= 0 ? std::vector<int>{forced_persist}
-                                               : std::vector<int>{1, 0};
+                                               : (any_part ? std::vector<int>{1, 0, 2}
+                                                           : std::vector<int>{1, 0});
   float best_ms = 0.f;
   bool have = false;
   int best_split = splits[0], best_form = forms[0];
@@ -887,7 +917,9 @@ int tune_batch(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* c
     if (!table_fits(e->blocks)) continue;
     if ((rc = upload_table(e, host, s))) break;
     for (int form : forms) {
+      if (form == 2 && c > 0) continue;   // tile splits do not apply to the per-problem form
       e->persist = form == 1;
+      e->per_problem = form == 2;
       float ms = 0.f;
       for (int rep = 0; rep < 3; ++rep) {
         if (rep == 1) (void)hipEventRecord(a, s);
@@ -910,19 +942,35 @@ int tune_batch(const std::vector<ProbDesc>& D, BatchEntry* e, const CrtConsts* c
   (void)hipEventDestroy(b);
   e->split = best_split;
   e->persist = best_form == 1;
+  e->per_problem = best_form == 2;
   return rc;
 }
 
 // Workspace of a batch: the layouts of the active problems (m, n, k >= 1),
 // back to back; their indices and offsets go to act / off.
+// A batch of at most kPerProblemMax active problems also holds each
+// problem's split-k scratch (none for problems whose output fills the GPU),
+// for the per-problem form of the products.
+bool batch_per_problem_ok(int count, const int* mnkN) {
+  int active = 0;
+  for (int p = 0; p < count; ++p)
+    active += mnkN[4 * p] > 0 && mnkN[4 * p + 1] > 0 && mnkN[4 * p + 2] > 0;
+  return active <= kPerProblemMax;
+}
+
+Layout batch_problem_layout(int m, int n, int k, int N, bool per_problem) {
+  return layout(m, n, k, N, batch_row_pad(m, n), per_problem ? N : 0);
+}
+
 size_t batch_layout(int count, const int* mnkN, std::vector<int>* act, std::vector<size_t>* off) {
+  const bool pp = batch_per_problem_ok(count, mnkN);
   size_t total = 0;
   for (int p = 0; p < count; ++p) {
     const int m = mnkN[4 * p], n = mnkN[4 * p + 1], k = mnkN[4 * p + 2];
     if (m == 0 || n == 0 || k == 0) continue;
     if (act) act->push_back(p);
     if (off) off->push_back(total);
-    total += rup(layout(m, n, k, mnkN[4 * p + 3], batch_row_pad(m, n)).total, 256);
+    total += rup(batch_problem_layout(m, n, k, mnkN[4 * p + 3], pp).total, 256);
   }
   return total;
 }
@@ -940,6 +988,7 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
   std::vector<int> act;
   std::vector<size_t> off;
   const size_t total = batch_layout(count, mnkN, &act, &off);
+  const bool pp = batch_per_problem_ok(count, mnkN);
   char* ws = nullptr;
   int* status = nullptr;
   uint64_t gen = 0;
@@ -962,6 +1011,7 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
   key.push_back(forced);
   key.push_back(forced_persist);
   key.push_back(use_graph ? 1 : 0);
+  key.push_back(g_split_k.load(std::memory_order_relaxed));   // captured split-k choices
   for (int p = 0; p < count; ++p) {
     for (int q = 0; q < 4; ++q) key.push_back(mnkN[4 * p + q]);
     key.push_back(lda[p]);
@@ -989,8 +1039,10 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
     for (size_t q = 0; q < act.size(); ++q) {
       const int p = act[q];
       const int m = mnkN[4 * p], n = mnkN[4 * p + 1], k = mnkN[4 * p + 2], N = mnkN[4 * p + 3];
-      const Layout L = layout(m, n, k, N, batch_row_pad(m, n));
+      const Layout L = batch_problem_layout(m, n, k, N, pp);
       char* w = ws + off[q];
+      e->part.push_back(L.part_bytes ? at<int8_t>(w, L.part) : nullptr);
+      e->part_bytes.push_back(L.part_bytes);
       ProbDesc& d = D[q];
       d.m = m, d.n = n, d.k = k, d.N = N;
       d.mp = L.mp, d.np = L.np, d.kp = L.kp;
@@ -1006,7 +1058,10 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
       d.As = at<int8_t>(w, L.A);
       d.Bs = at<int8_t>(w, L.B);
       d.W = at<int8_t>(w, L.W);
+      e->hc.emplace_back();
+      if ((rc = get_consts(N, b, &e->hc.back()))) return rc;
     }
+    e->hd = D;
     {
       // one residue kernel for the whole batch when every N takes the same path
       std::vector<CrtConsts> cs;
@@ -1026,7 +1081,8 @@ int batched_impl(Prec pr, int count, const int* mnkN, const void* const* A, cons
     e->pgrid[1] = persist_grid(128);
     std::vector<char> host;
     e->split = forced >= 0 ? forced : 1 << 30;
-    e->persist = forced_persist != 0;
+    e->persist = forced_persist == 1 || forced_persist < 0;
+    e->per_problem = forced_persist == 2;
     if ((forced < 0 || forced_persist < 0) && e->active > 0) {
       // One eager pass of the whole batch first, so that the tuner times the
       // residue products on this batch's own residues.
@@ -1573,7 +1629,7 @@ int ozaki2_debug_tuning(int knob, int value, int* previous) {
       k = &g_batch_graph;
       break;
     case OZAKI2_KNOB_BATCH_PERSIST:
-      if (value < -1 || value > 1) return OZAKI2_ERR_INVALID_ARG;
+      if (value < -1 || value > 2) return OZAKI2_ERR_INVALID_ARG;
       k = &g_batch_persist;
       break;
     case OZAKI2_KNOB_SPLIT_K:

@@ -212,6 +212,9 @@ def test_tuning_knobs():
     assert t(oz.KNOB_GEMM_TILE, 3)[0] == oz.ERR_INVALID_ARG
     assert t(oz.KNOB_BATCH_SPLIT, -2)[0] == oz.ERR_INVALID_ARG
     assert t(oz.KNOB_BATCH_GRAPH, 2)[0] == oz.ERR_INVALID_ARG
+    assert t(oz.KNOB_BATCH_PERSIST, 3)[0] == oz.ERR_INVALID_ARG
+    with oz.tuning(oz.KNOB_BATCH_PERSIST, 2):
+        assert t(oz.KNOB_BATCH_PERSIST, 2) == (oz.OK, 2)
     assert t(99, 0)[0] == oz.ERR_INVALID_ARG
     with oz.tuning(oz.KNOB_BATCH_SPLIT, 4):
         assert t(oz.KNOB_BATCH_SPLIT, 4) == (oz.OK, 4)
@@ -237,6 +240,26 @@ def test_split_k_scratch_in_workspace():
     # an output that fills the GPU does not split: no region
     assert with_split[1] == without[1]
     assert oz.ozaki2_debug_tuning(oz.KNOB_SPLIT_K, 7)[0] == oz.ERR_INVALID_ARG
+
+
+def test_batched_split_k_scratch():
+    # A batch of at most 64 active problems holds each long-k problem's
+    # split-k scratch (the same region as the single call's) for the
+    # per-problem form; a larger batch holds none.
+    q = oz.ozaki2_batched_workspace_bytes
+    shape = [64, 64, 262144, 14]
+    one = q(64, shape)
+    rc, prev = oz.ozaki2_debug_tuning(oz.KNOB_SPLIT_K, 1)
+    assert rc == oz.OK
+    try:
+        one_plain = q(64, shape)
+    finally:
+        oz.ozaki2_debug_tuning(oz.KNOB_SPLIT_K, prev)
+    assert one - one_plain == 36 * 14 * 128 * 128
+    assert q(64, shape * 64) == 64 * one
+    assert q(64, shape * 65) == 65 * one_plain
+    # degenerate problems do not count towards the 64
+    assert q(64, shape * 64 + [5, 4, 0, 10]) == 64 * one
 
 
 def test_complex_planner_argument_errors():

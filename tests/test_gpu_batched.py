@@ -89,13 +89,13 @@ def test_batched_one_residue_path(N, dtype):
                 assert np.array_equal(got, os_ii(A, B, Nq)), f"problem {q} vs oracle"
 
 
-@pytest.mark.parametrize("persist", [1, 0])
+@pytest.mark.parametrize("persist", [1, 0, 2])
 @pytest.mark.parametrize("split", [0, 1000000, 4])
 def test_batched_tile_splits_and_eager(split, persist):
-    # Every tile split (all 256x256, all 128x128, mixed), both forms of the
-    # residue products (persistent workgroups walking the block map, one
-    # workgroup per tile) and the eager (uncaptured) launch sequence give the
-    # same bits.
+    # Every tile split (all 256x256, all 128x128, mixed), the three forms of
+    # the residue products (persistent workgroups walking the block map, one
+    # workgroup per tile, one launch per problem) and the eager (uncaptured)
+    # launch sequence give the same bits.
     announce(f"batched split={split} persist={persist}")
     cases = SMALL[:6] + SMALL[9:]
     As, Bs = make_batch(cases, np.float64, seed=300)
@@ -127,6 +127,34 @@ def test_batched_persistent_many_problems_and_long_k():
     q = len(cases) - 2
     rows, cols = np.array([0, 11, 23]), np.array([0, 19])
     assert np.array_equal(host(Ccm[q]).T[np.ix_(rows, cols)],
+                          os_ii(As[q], Bs[q], Ns[q], rows=rows, cols=cols))
+
+
+@pytest.mark.parametrize("persist", [2, -1])
+def test_batched_per_problem_split_k(persist):
+    # Small outputs with long k: in the per-problem form each problem's
+    # scaling and residue products split k (partials summed exactly, mod p for
+    # the residues) as the single-problem call does.  Forced (2) and chosen by
+    # the tuner (-1), the bits are those of the single calls and the oracle.
+    cases = [(64, 48, 32768, 14), (30, 70, 20000, 12), (130, 5, 65536, 16), (1, 1, 40000, 7),
+             (200, 180, 3000, 14), (17, 9, 2 ** 17 + 1000, 20)]
+    announce(f"batched per-problem split-k, persist={persist}: {len(cases)} problems")
+    As, Bs = make_batch(cases, np.float64, seed=900)
+    Ns = [c[3] for c in cases]
+    with oz.tuning(oz.KNOB_BATCH_PERSIST, persist):
+        _, _, C1, _ = run_batched(As, Bs, Ns)
+        with oz.tuning(oz.KNOB_BATCH_GRAPH, 0):
+            _, _, C2, _ = run_batched(As, Bs, Ns)
+    assert oz.ozaki2_sync_status() == oz.OK
+    for q, (A, B, N) in enumerate(zip(As, Bs, Ns)):
+        ref = single(A, B, N)
+        assert np.array_equal(host(C1[q]).T, ref), f"graph, problem {q} {cases[q]}"
+        assert np.array_equal(host(C2[q]).T, ref), f"eager, problem {q} {cases[q]}"
+    for q in (1, 3):
+        assert np.array_equal(host(C1[q]).T, os_ii(As[q], Bs[q], Ns[q])), f"problem {q} vs oracle"
+    rows, cols = np.array([0, 16]), np.array([0, 8])
+    q = 5
+    assert np.array_equal(host(C1[q]).T[np.ix_(rows, cols)],
                           os_ii(As[q], Bs[q], Ns[q], rows=rows, cols=cols))
 
 
