@@ -886,8 +886,9 @@ int upload_table(BatchEntry* e, const std::vector<char>& host, hipStream_t s) {
 }
 
 // Autotuner: times the residue products (the dominant phase) under each
-// candidate tile split and form (one workgroup per tile, or persistent) and
-// keeps the fastest.  The caller has run the whole batch once, so the
+// candidate tile split and form (one workgroup per tile, persistent, or,
+// where some problem has split-k scratch, one launch per problem) and keeps
+// the fastest; the form chosen also applies to the scaling products.  The caller has run the whole batch once, so the
 // operand slices in the workspace are this batch's own residues; the split
 // does not move them (the padding of every problem is fixed).  A forced
 // split or form (forced_split >= 0, forced_persist >= 0) is not tuned.
