@@ -65,5 +65,55 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer: the flags apply
+# to the host pass only (device code is built as usual and never launched by
+# the host-only checks that load this variant).
+HOST_SANITIZE = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined".split()
+
+
+def build_host_sanitized(out_dir: str) -> str:
+    """Build a copy of the library whose host code (argument checks, layouts,
+    constant tables, workspace queries, caches) carries ASan and UBSan, into
+    out_dir/libozaki2_hostsan.so.  Loading it needs the clang ASan runtime
+    preloaded (asan_runtime()).  A test aid: the product build is build()."""
+    os.makedirs(out_dir, exist_ok=True)
+    cc = hipcc()
+    flags = ["--offload-arch=gfx950", "-O1", "-g", "-fPIC", "-std=c++17", "-ffp-contract=off",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-w",
+             "-fno-omit-frame-pointer", *HOST_SANITIZE]
+    procs, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(out_dir, src + ".san.o")
+        objs.append(obj)
+        cmd = [cc, *flags] + (["-x", "hip"] if src.endswith(".hip") else [])
+        cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    for src, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"sanitized build of {src} failed:\n" + out.decode(errors="replace"))
+    lib = os.path.join(out_dir, "libozaki2_hostsan.so")
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-shared-libasan", *HOST_SANITIZE,
+           *objs, "-o", lib]
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if p.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + p.stdout.decode(errors="replace"))
+    return lib
+
+
+def asan_runtime() -> str:
+    """Path of the clang ASan runtime that the sanitized library links to."""
+    out = subprocess.run([hipcc(), "--print-file-name=libclang_rt.asan-x86_64.so"],
+                         stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True).stdout.strip()
+    if out and os.path.isabs(out) and os.path.exists(out):
+        return out
+    base = "/opt/rocm/llvm/lib/clang"
+    for ver in sorted(os.listdir(base)) if os.path.isdir(base) else []:
+        cand = os.path.join(base, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(cand):
+            return cand
+    raise RuntimeError("clang ASan runtime not found")
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

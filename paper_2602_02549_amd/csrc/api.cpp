@@ -141,7 +141,7 @@ Layout layout(int m, int n, int k, int N, int pad, int split_nz = 0) {
   L.nu_p = take(4ull * L.np);
   L.mu = take(4ull * L.mp);
   L.nu = take(4ull * L.np);
-  L.ef = take(4ull * (L.mp + L.np));
+  L.ef = take(4ull * ((size_t)L.mp + L.np));
   L.flag = take(4);
   L.A = take((size_t)N * L.mp * L.kp);
   L.B = take((size_t)N * L.np * L.kp);
