@@ -130,26 +130,35 @@ def test_batched_persistent_many_problems_and_long_k():
                           os_ii(As[q], Bs[q], Ns[q], rows=rows, cols=cols))
 
 
-@pytest.mark.parametrize("persist", [2, -1])
-def test_batched_per_problem_split_k(persist):
+@pytest.mark.parametrize("persist,dtype", [(2, np.float64), (-1, np.float64), (2, np.float32)])
+def test_batched_per_problem_split_k(persist, dtype):
     # Small outputs with long k: in the per-problem form each problem's
     # scaling and residue products split k (partials summed exactly, mod p for
     # the residues) as the single-problem call does.  Forced (2) and chosen by
     # the tuner (-1), the bits are those of the single calls and the oracle.
     cases = [(64, 48, 32768, 14), (30, 70, 20000, 12), (130, 5, 65536, 16), (1, 1, 40000, 7),
              (200, 180, 3000, 14), (17, 9, 2 ** 17 + 1000, 20)]
-    announce(f"batched per-problem split-k, persist={persist}: {len(cases)} problems")
-    As, Bs = make_batch(cases, np.float64, seed=900)
+    if dtype == np.float32:
+        cases = [(m, n, k, min(N, 16)) for m, n, k, N in cases]
+    announce(f"batched per-problem split-k, persist={persist} {np.dtype(dtype).name}")
+    As, Bs = make_batch(cases, dtype, seed=900)
     Ns = [c[3] for c in cases]
     with oz.tuning(oz.KNOB_BATCH_PERSIST, persist):
-        _, _, C1, _ = run_batched(As, Bs, Ns)
+        A1, B1, C1, shapes = run_batched(As, Bs, Ns)
+        first = [host(c).T for c in C1]
         with oz.tuning(oz.KNOB_BATCH_GRAPH, 0):
             _, _, C2, _ = run_batched(As, Bs, Ns)
+        # the same buffers again: a replay of the captured graph, after other
+        # work on the stream (the eager batch) and with C reset
+        for c in C1:
+            c.fill_(np.nan)
+        oz.gemm_batched_cm(A1, B1, C1, shapes, Ns)
     assert oz.ozaki2_sync_status() == oz.OK
     for q, (A, B, N) in enumerate(zip(As, Bs, Ns)):
         ref = single(A, B, N)
-        assert np.array_equal(host(C1[q]).T, ref), f"graph, problem {q} {cases[q]}"
+        assert np.array_equal(first[q], ref), f"first call, problem {q} {cases[q]}"
         assert np.array_equal(host(C2[q]).T, ref), f"eager, problem {q} {cases[q]}"
+        assert np.array_equal(host(C1[q]).T, ref), f"replay, problem {q} {cases[q]}"
     for q in (1, 3):
         assert np.array_equal(host(C1[q]).T, os_ii(As[q], Bs[q], Ns[q])), f"problem {q} vs oracle"
     rows, cols = np.array([0, 16]), np.array([0, 8])
