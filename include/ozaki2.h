@@ -279,9 +279,8 @@ int ozaki2_sync_status(void);
  * the residue products under each tile split and form (one workgroup per
  * tile, persistent workgroups, and, in a batch of at most 64 problems of
  * which some split k, one launch per problem) on the residues that run
- * produced,
- * captures the launch sequence with the fastest into a hipGraph and
- * synchronises the stream; later calls with the same batch replay the graph
+ * produced, captures the launch sequence with the fastest into a hipGraph
+ * and synchronises the stream; later calls with the same batch replay the graph
  * asynchronously and allocate nothing.  Up to eight batches stay cached per
  * device.  The workspace needed is ozaki2_batched_workspace_bytes.
  */
