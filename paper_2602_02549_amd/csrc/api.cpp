@@ -535,20 +535,18 @@ int zgemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void*
 // each part and the inverse scaling, written as complex pairs.  Workspace:
 // the four real planes, then the layout of the m x n x k problem with 3N
 // slices and 3N W (the three groups of N back to back).
+// The 3-product form reads the interleaved complex inputs directly: its
+// workspace is the real layout with 3N slices (three residue sets and three
+// W sets per modulus).
 struct Z3Layout {
-  size_t Ar, Ai, Br, Bi, real, total;
+  size_t total;
   Layout L;
 };
 
-Z3Layout z3layout(int m, int n, int k, int N, size_t s) {
+Z3Layout z3layout(int m, int n, int k, int N) {
   Z3Layout Z;
-  Z.Ar = 0;
-  Z.Ai = rup(Z.Ar + s * (size_t)m * k, 256);
-  Z.Br = rup(Z.Ai + s * (size_t)m * k, 256);
-  Z.Bi = rup(Z.Br + s * (size_t)k * n, 256);
-  Z.real = rup(Z.Bi + s * (size_t)k * n, 256);
   Z.L = layout(m, n, k, 3 * N, single_row_pad(m, n, N), N);
-  Z.total = Z.real + Z.L.total;
+  Z.total = Z.L.total;
   return Z;
 }
 
@@ -566,14 +564,12 @@ int zgemm3m_impl(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   }
   CrtConsts cc;
   if ((rc = get_consts(N, b, &cc))) return rc;
-  const size_t es = pr == Prec::F64 ? 8 : 4;
-  const Z3Layout Z = z3layout(m, n, k, N, es);
+  const Z3Layout Z = z3layout(m, n, k, N);
   char* ws;
   int* status;
   if ((rc = get_workspace(Z.total, &ws, &status))) return rc;
   const Layout& L = Z.L;
-  char* w = ws + Z.real;
-  void *Ar = ws + Z.Ar, *Ai = ws + Z.Ai, *Br = ws + Z.Br, *Bi = ws + Z.Bi;
+  char* w = ws;
   uint64_t* rowbits = at<uint64_t>(w, L.rowbits);
   uint64_t* colbits = at<uint64_t>(w, L.colbits);
   int* rmax = at<int>(w, L.rmax);
@@ -585,38 +581,26 @@ int zgemm3m_impl(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   int8_t* X[3] = {at<int8_t>(w, L.A), at<int8_t>(w, L.A) + N * sa, at<int8_t>(w, L.A) + 2 * N * sa};
   int8_t* Y[3] = {at<int8_t>(w, L.B), at<int8_t>(w, L.B) + N * sb, at<int8_t>(w, L.B) + 2 * N * sb};
   int8_t* W[3] = {at<int8_t>(w, L.W), at<int8_t>(w, L.W) + N * sw, at<int8_t>(w, L.W) + 2 * N * sw};
-  launch_split_complex(s, pr, A, lda, m, k, Ar, Ai);
-  launch_split_complex(s, pr, B, ldb, k, n, Br, Bi);
-  // Algorithm 2 on the complex matrices: abs-max over both parts (the two
-  // passes share the atomic maxima), bars summed over the parts.
+  // Algorithm 2 on the complex matrices, read in place: abs-max over both
+  // parts, and Abar = bar(Ar) + bar(Ai) (Bbar alike) into the third set.
   launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
-  launch_absmax_rows(s, pr, Ar, m, m, k, rowbits, flag);
-  launch_absmax_rows(s, pr, Ai, m, m, k, rowbits, flag);
-  launch_absmax_cols(s, pr, Br, k, k, n, colbits, flag, true);
-  launch_absmax_cols(s, pr, Bi, k, k, n, colbits, flag, true);
-  launch_slices(s, pr, 2, true, Ar, m, m, k, L.mp, L.kp, rowbits, nullptr, cc, X[0]);
-  launch_slices(s, pr, 2, true, Ai, m, m, k, L.mp, L.kp, rowbits, nullptr, cc, X[1]);
-  launch_add_bars(s, X[0], X[1], X[2], sa);
-  launch_slices(s, pr, 2, false, Br, k, n, k, L.np, L.kp, colbits, nullptr, cc, Y[0]);
-  launch_slices(s, pr, 2, false, Bi, k, n, k, L.np, L.kp, colbits, nullptr, cc, Y[1]);
-  launch_add_bars(s, Y[0], Y[1], Y[2], sb);
+  launch_absmax_rows(s, pr, A, lda, m, k, rowbits, flag, true);
+  launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag, true);
+  launch_slices_complex(s, pr, 2, true, A, lda, m, k, L.mp, L.kp, rowbits, nullptr, cc, X[2]);
+  launch_slices_complex(s, pr, 2, false, B, ldb, n, k, L.np, L.kp, colbits, nullptr, cc, Y[2]);
   launch_gemm_i8(s, 1, X[2], 0, Y[2], 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax,
                  at<int8_t>(w, L.part), L.part_bytes);
   launch_shifts(s, rowbits, rmax, m, colbits, cmax, n, cc.Pprime, cc.c, at<int>(w, L.mu_p),
                 at<int>(w, L.nu_p), mu, nu, nullptr, -1);
-  // Algorithm 3: residues of A'r, A'i and A'r + A'i (and of B), three
-  // residue products per modulus, the real and imaginary residues.
-  launch_slices(s, pr, 1, true, Ar, m, m, k, L.mp, L.kp, nullptr, mu, cc, X[0]);
-  launch_slices(s, pr, 1, true, Ai, m, m, k, L.mp, L.kp, nullptr, mu, cc, X[1]);
-  launch_sum_residues(s, X[0], X[1], X[2], sa, cc);
-  launch_slices(s, pr, 1, false, Br, k, n, k, L.np, L.kp, nullptr, nu, cc, Y[0]);
-  launch_slices(s, pr, 1, false, Bi, k, n, k, L.np, L.kp, nullptr, nu, cc, Y[1]);
-  launch_sum_residues(s, Y[0], Y[1], Y[2], sb, cc);
+  // Algorithm 3: residues of A'r, A'i and A'r + A'i (and of B) in one pass
+  // per operand, three residue products per modulus, and the CRT of the real
+  // and imaginary residues formed from the three W.
+  launch_slices_complex(s, pr, 1, true, A, lda, m, k, L.mp, L.kp, nullptr, mu, cc, X[0]);
+  launch_slices_complex(s, pr, 1, false, B, ldb, n, k, L.np, L.kp, nullptr, nu, cc, Y[0]);
   for (int q = 0; q < 3; ++q)
     launch_gemm_i8(s, 0, X[q], sa, Y[q], sb, L.mp, L.np, L.kp, N, cc, W[q], sw, L.mp, nullptr,
                    nullptr, at<int8_t>(w, L.part), L.part_bytes);
-  launch_combine_w(s, W[0], W[1], W[2], sw, cc);
-  launch_crt_complex(s, pr, W[0], W[1], sw, L.mp, mu, mu, nu, m, n, cc, flag, C, ldc);
+  launch_crt_3m(s, pr, W[0], W[1], W[2], sw, L.mp, mu, nu, m, n, cc, flag, C, ldc);
   launch_or_status(s, flag, status);
   return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
 }
@@ -1178,7 +1162,7 @@ size_t ozaki2_complex_workspace_bytes(int prec, int m, int n, int k, int N) {
   if (m > kMaxDim / 2 || n > kMaxDim || k > kMaxK || check_N(N, prec) != OZAKI2_OK) return 0;
   if (m == 0 || n == 0 || k == 0) return 0;
   const size_t s = prec == 64 ? 8 : 4;
-  const size_t t3 = z3layout(m, n, k, N, s).total;
+  const size_t t3 = z3layout(m, n, k, N).total;
   if (k > kMaxK / 2) return t3;   // only the 3-product form takes such k
   const size_t t4 = zlayout(m, n, k, N, s).total;
   return t3 > t4 ? t3 : t4;

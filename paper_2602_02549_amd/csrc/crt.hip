@@ -155,6 +155,37 @@ __device__ __forceinline__ void crt_body(const int8_t* __restrict__ W, size_t sw
 // loads of a partial last chunk read up to row rup(m, R) - 1 past Wr and Wi,
 // inside the padded column (the embedding's column holds 2m rows padded to a
 // multiple of 128, at least m + rup(m, R)).
+// R consecutive complex entries (rows i0.., column j) as interleaved pairs,
+// with 2-element vector stores when the address allows.
+template <typename T, int R>
+__device__ __forceinline__ void store_complex(T* __restrict__ C, int ldc, int j, int i0, int m,
+                                              const T (&re)[R], const T (&im)[R]) {
+  T* cp = C + 2 * ((size_t)j * ldc + i0);
+  if (i0 + R <= m && ((uintptr_t)cp & (2 * sizeof(T) - 1)) == 0) {
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+      if (sizeof(T) == 8) {
+        double2 v;
+        v.x = (double)re[e];
+        v.y = (double)im[e];
+        *reinterpret_cast<double2*>(cp + 2 * e) = v;
+      } else {
+        float2 v;
+        v.x = (float)re[e];
+        v.y = (float)im[e];
+        *reinterpret_cast<float2*>(cp + 2 * e) = v;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+      if (i0 + e < m) {
+        cp[2 * e] = re[e];
+        cp[2 * e + 1] = im[e];
+      }
+  }
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void crt_complex_body(const int8_t* __restrict__ Wr,
                                                  const int8_t* __restrict__ Wi, size_t sw, int ldw,
@@ -184,30 +215,107 @@ __device__ __forceinline__ void crt_complex_body(const int8_t* __restrict__ Wr,
 #pragma unroll
   for (int e = 0; e < R; ++e)
     im[e] = crt_value<T>(c1[e], c2[e], cc, -mui[min(i0 + e, m - 1)] - nuj, bad, &q, &cppd);
-  T* cp = C + 2 * ((size_t)j * ldc + i0);
-  if (i0 + R <= m && ((uintptr_t)cp & (2 * sizeof(T) - 1)) == 0) {
+  store_complex<T, R>(C, ldc, j, i0, m, re, im);
+}
+
+// The 3-product form (reading R25 of the complex GEMM): per modulus l the
+// real and imaginary residues are mod(W1 - W2, p_l) and mod(W3 - W1 - W2,
+// p_l) of the three products' bytes, formed here and summed into C'(1),
+// C'(2) of both parts with the l-ordered fma chains of crt_sums.  The bytes
+// lie in [lo, hi] = [(1-p)/2, (p-1)/2] (odd p) or [-128, 127] (p = 256), so
+// a difference or sum of two lies in [-(p-1), p-1] and one correction by p
+// brings it back into [lo, hi]: W1 - W2 directly, W3 - W1 - W2 as W3 minus
+// the corrected W1 + W2.  Moduli in groups of 4, loads first; a modulus past
+// N gets weight 0 (fma(0, w, c) = c).  W1, W2, W3 are whole planes
+// (tile-aligned), so each R-byte load is aligned.
+template <typename T, int R>
+__device__ __forceinline__ void crt_sums_3m(const int8_t* __restrict__ w1,
+                                            const int8_t* __restrict__ w2,
+                                            const int8_t* __restrict__ w3, size_t sw,
+                                            const CrtConsts& cc, double (&c1r)[R], double (&c2r)[R],
+                                            double (&c1i)[R], double (&c2i)[R]) {
+  typedef typename std::conditional<R == 2, uint16_t,
+                                    typename std::conditional<R == 4, uint32_t, uint64_t>::type>::type
+      WordT;
 #pragma unroll
-    for (int e = 0; e < R; ++e) {
-      if (sizeof(T) == 8) {
-        double2 v;
-        v.x = (double)re[e];
-        v.y = (double)im[e];
-        *reinterpret_cast<double2*>(cp + 2 * e) = v;
-      } else {
-        float2 v;
-        v.x = (float)re[e];
-        v.y = (float)im[e];
-        *reinterpret_cast<float2*>(cp + 2 * e) = v;
+  for (int e = 0; e < R; ++e) c1r[e] = c2r[e] = c1i[e] = c2i[e] = 0.0;
+  for (int l0 = 0; l0 < cc.N; l0 += 4) {
+    uint64_t a[4], b[4], c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const size_t off = (size_t)min(l0 + u, cc.N - 1) * sw;
+      a[u] = *reinterpret_cast<const WordT*>(w1 + off);
+      b[u] = *reinterpret_cast<const WordT*>(w2 + off);
+      c[u] = *reinterpret_cast<const WordT*>(w3 + off);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int l = min(l0 + u, cc.N - 1);
+      const bool in = l0 + u < cc.N;
+      const double s1 = in ? cc.s1[l] : 0.0, s2 = in ? cc.s2[l] : 0.0;
+      const int p = cc.p[l], hi = (p - 1) / 2, lo = hi + 1 - p;
+      auto fix = [&](int x) {
+        x -= x > hi ? p : 0;
+        return x + (x < lo ? p : 0);
+      };
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        const int t1 = (int)(int8_t)(a[u] >> (8 * e)), t2 = (int)(int8_t)(b[u] >> (8 * e)),
+                  t3 = (int)(int8_t)(c[u] >> (8 * e));
+        // w in [-128, 127] becomes a double without the convert instruction,
+        // as in crt_sums: 0x43300000:(w + 128) is 2^52 + w + 128
+        const double wr =
+            __hiloint2double(0x43300000, fix(t1 - t2) + 128) - 4503599627370624.0;
+        const double wi =
+            __hiloint2double(0x43300000, fix(t3 - fix(t1 + t2)) + 128) - 4503599627370624.0;
+        c1r[e] = fma(s1, wr, c1r[e]);
+        c1i[e] = fma(s1, wi, c1i[e]);
+        if (sizeof(T) == 8) {
+          c2r[e] = fma(s2, wr, c2r[e]);
+          c2i[e] = fma(s2, wi, c2i[e]);
+        }
       }
     }
-  } else {
-#pragma unroll
-    for (int e = 0; e < R; ++e)
-      if (i0 + e < m) {
-        cp[2 * e] = re[e];
-        cp[2 * e + 1] = im[e];
-      }
   }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void crt_3m_body(const int8_t* __restrict__ W1,
+                                            const int8_t* __restrict__ W2,
+                                            const int8_t* __restrict__ W3, size_t sw, int ldw,
+                                            const int* __restrict__ mu, const int* __restrict__ nu,
+                                            int m, int n, const CrtConsts& cc,
+                                            const int* __restrict__ flag, T* __restrict__ C,
+                                            int ldc, int64_t g) {
+  const int chunks = cdiv_i(m, R);
+  const int j = (int)(g / chunks);
+  if (j >= n) return;
+  const int i0 = (int)(g - (int64_t)j * chunks) * R;
+  const bool bad = *flag != 0;
+  const int nuj = nu[j];
+  const size_t o = (size_t)j * ldw + i0;
+  double c1r[R], c2r[R], c1i[R], c2i[R], q, cppd;
+  crt_sums_3m<T, R>(W1 + o, W2 + o, W3 + o, sw, cc, c1r, c2r, c1i, c2i);
+  T re[R], im[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const int ex = -mu[min(i0 + e, m - 1)] - nuj;
+    re[e] = crt_value<T>(c1r[e], c2r[e], cc, ex, bad, &q, &cppd);
+    im[e] = crt_value<T>(c1i[e], c2i[e], cc, ex, bad, &q, &cppd);
+  }
+  store_complex<T, R>(C, ldc, j, i0, m, re, im);
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_crt_3m(const int8_t* __restrict__ W1,
+                                                const int8_t* __restrict__ W2,
+                                                const int8_t* __restrict__ W3, size_t sw, int ldw,
+                                                const int* __restrict__ mu,
+                                                const int* __restrict__ nu, int m, int n,
+                                                CrtConsts cc, const int* __restrict__ flag,
+                                                T* __restrict__ C, int ldc) {
+  crt_3m_body<T, R>(W1, W2, W3, sw, ldw, mu, nu, m, n, cc, flag, C, ldc,
+                    (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 template <typename T, int R>
@@ -304,6 +412,18 @@ void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, con
     launch_crt_t<double>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
   else
     launch_crt_t<float>(s, W, sw, ldw, mu, nu, m, n, cc, flag, C, ldc);
+}
+
+void launch_crt_3m(hipStream_t s, Prec pr, const int8_t* W1, const int8_t* W2, const int8_t* W3,
+                   size_t sw, int ldw, const int* mu, const int* nu, int m, int n,
+                   const CrtConsts& cc, const int* flag, void* C, int ldc) {
+  const dim3 grid((unsigned)crt_blocks(m, n)), block(256);
+  if (pr == Prec::F64)
+    hipLaunchKernelGGL((k_crt_3m<double, kCrtRows>), grid, block, 0, s, W1, W2, W3, sw, ldw, mu, nu,
+                       m, n, cc, flag, (double*)C, ldc);
+  else
+    hipLaunchKernelGGL((k_crt_3m<float, kCrtRows>), grid, block, 0, s, W1, W2, W3, sw, ldw, mu, nu,
+                       m, n, cc, flag, (float*)C, ldc);
 }
 
 void launch_crt_complex(hipStream_t s, Prec pr, const int8_t* Wr, const int8_t* Wi, size_t sw,

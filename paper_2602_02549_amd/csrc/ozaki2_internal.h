@@ -153,12 +153,12 @@ enum class Prec { F64, F32 };
 // scale.hip
 void launch_init(hipStream_t s, uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pad,
                  int* rmax, int* cmax, int* flag);
+// cx: the matrix holds interleaved (re, im) pairs (leading dimension in
+// complex elements) and each maximum runs over both parts.
 void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, int k,
-                        uint64_t* rowbits, int* flag);
-// accumulate: merge into the maxima already in colbits (atomicMax) instead of
-// storing them.
+                        uint64_t* rowbits, int* flag, bool cx = false);
 void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,
-                        uint64_t* colbits, int* flag, bool accumulate = false);
+                        uint64_t* colbits, int* flag, bool cx = false);
 // Abs-max of the columns of B and Bbar (slice 0, K-major [n_pad][k_pad]) in
 // one read of B; for k_pad <= kAbsBarMaxK.
 constexpr int kAbsBarMaxK = 8192;
@@ -194,6 +194,14 @@ void init_slice_launch(int dev);
 void launch_slices(hipStream_t s, Prec pr, int mode, bool trans, const void* src, int ld, int rows,
                    int k, int rows_pad, int k_pad, const uint64_t* bits, const int* shift,
                    const CrtConsts& cc, int8_t* out);
+// The same passes over an interleaved complex source (the 3-product form),
+// each reading the complex matrix once:
+//   mode 2: one slice at out, byte = ceil(2^(mu'-1) |re|) + ceil(2^(mu'-1) |im|);
+//   mode 1: 3 N slices from out: the residues of the real parts, of the
+//           imaginary parts, and of their sums (mod p_l of the two bytes).
+void launch_slices_complex(hipStream_t s, Prec pr, int mode, bool trans, const void* src, int ld,
+                           int rows, int k, int rows_pad, int k_pad, const uint64_t* bits,
+                           const int* shift, const CrtConsts& cc, int8_t* out);
 
 // Planner operands (BF16, K-major [rows_pad][k_pad]) and per-64-k-tile row
 // sums partial[k_pad/64][rows_pad] of |x| 2^-alpha.
@@ -278,6 +286,13 @@ void launch_crt(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, con
 void launch_crt_complex(hipStream_t s, Prec pr, const int8_t* Wr, const int8_t* Wi, size_t sw,
                         int ldw, const int* mur, const int* mui, const int* nu, int m, int n,
                         const CrtConsts& cc, const int* flag, void* C, int ldc);
+// The CRT of the 3-product form: the real and imaginary residues of modulus l
+// are mod(W1 - W2, p_l) and mod(W3 - W1 - W2, p_l), formed per byte from the
+// three products' W; shifts mu (rows) and nu (columns) for both parts;
+// interleaved complex output as launch_crt_complex.
+void launch_crt_3m(hipStream_t s, Prec pr, const int8_t* W1, const int8_t* W2, const int8_t* W3,
+                   size_t sw, int ldw, const int* mu, const int* nu, int m, int n,
+                   const CrtConsts& cc, const int* flag, void* C, int ldc);
 // launch_crt plus C'(1), C'(2), Q, C'' as FP64 [4][n][m] into dbg (stage dumps).
 void launch_crt_debug(hipStream_t s, Prec pr, const int8_t* W, size_t sw, int ldw, const int* mu,
                       const int* nu, int m, int n, const CrtConsts& cc, const int* flag, void* C,
@@ -292,18 +307,6 @@ void launch_or_status(hipStream_t s, const int* flag, int* status);
 // (2k x n, ld 2k).
 void launch_embed_complex(hipStream_t s, Prec pr, const void* A, int lda, const void* B, int ldb,
                           int m, int n, int k, void* Ah, void* Bh);
-// The 3-product form: real and imaginary planes of an interleaved matrix
-// (leading dimension `rows` each); Abar as the sum of two INT8 bars (count a
-// multiple of 16); slice l of x3 = mod(x1 + x2, p_l) over N slices of `per`
-// bytes; and the real and imaginary residues from the three products,
-// W1 <- mod(W1 - W2, p_l), W2 <- mod(W3 - W1 - W2, p_l), in place.
-void launch_split_complex(hipStream_t s, Prec pr, const void* X, int ld, int rows, int cols,
-                          void* re, void* im);
-void launch_add_bars(hipStream_t s, const int8_t* a, const int8_t* b, int8_t* out, size_t count);
-void launch_sum_residues(hipStream_t s, const int8_t* x1, const int8_t* x2, int8_t* x3, size_t per,
-                         const CrtConsts& cc);
-void launch_combine_w(hipStream_t s, int8_t* w1, int8_t* w2, const int8_t* w3, size_t per,
-                      const CrtConsts& cc);
 
 // api.cpp: Algorithm 1 for one problem on a workspace of `cap` bytes that
 // `get` supplies, with its sticky status word; checks the arguments and the

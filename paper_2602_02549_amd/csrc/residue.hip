@@ -361,6 +361,186 @@ __global__ __launch_bounds__(256) void k_slices(const T* __restrict__ src, int l
   }
 }
 
+// ---- complex operands of the 3-product form (ozaki2_zgemm3m) -------------
+// The source holds interleaved (re, im) pairs, column-major, ld in complex
+// elements.  Both parts of a tile are loaded together (the complex matrix is
+// read once per pass) and staged one after the other through the one LDS
+// tile of k_slices, each thread taking its 16 values of each part into
+// registers:
+//   mode 2: Abar of the complex rows, ceil(2^(mu'-1) |re|) + ceil(2^(mu'-1) |im|)
+//     (each at most 32), one slice at out;
+//   mode 1: the residues of A'r, A'i and A'r + A'i, N slices each, at out,
+//     out + N slice and out + 2 N slice.  Per modulus the residues of the two
+//     parts come from the residue path's arithmetic, and the third is their
+//     sum brought back into the symmetric range by one correction.
+
+// Residue of one value for modulus (p, pd, pinv) on the residue path; the
+// limb paths split the value again for each modulus, which keeps no
+// per-value state across moduli (registers stay free for the next tile's
+// loads).  c1 = mod(2^s, p) and c2 = mod(2^80, p) of the limb paths.
+template <int PATH>
+__device__ __forceinline__ int residue_one(double v, int p, double pd, double pinv, double c1,
+                                           double c2) {
+  if constexpr (PATH == kLimbs2) {
+    const double mid = round_prod(v, 0x1p-48);
+    const double lo = fma(-mid, 0x1p48, v);            // exact, |lo| <= 2^47
+    return int_of(reduce_last(fma(mid, c1, lo), pd, pinv));
+  } else if constexpr (PATH == kLimbs3) {
+    const double hi = round_prod(v, 0x1p-80);
+    const double rem = fma(-hi, 0x1p80, v);            // exact, |rem| <= 2^79
+    const double mid = round_prod(rem, 0x1p-40);
+    const double lo = fma(-mid, 0x1p40, rem);          // exact, |lo| <= 2^39
+    return int_of(reduce_last(fma(hi, c2, fma(mid, c1, lo)), pd, pinv));
+  } else {
+    return residue_i8<PATH == kSteps1 ? 1 : PATH == kSteps3 ? 3 : 4>(v, p, pinv);
+  }
+}
+
+// The thread's 16 staged elements of its row (the order of tile_finish).
+__device__ __forceinline__ void tile_row16(const double* tile, double (&v)[16]) {
+  const int t = threadIdx.x;
+  const int r = t >> 3, c = t & 7;
+  const int g = ((c >> 1) ^ (r >> 3)) & 3;
+#pragma unroll
+  for (int el = 0; el < 4; ++el) {
+    const double* base = tile + r * kRS + 16 * c + (el ^ g);
+#pragma unroll
+    for (int eh = 0; eh < 4; ++eh) v[4 * eh + el] = base[4 * eh];
+  }
+}
+
+template <int MODE, int PATH>
+__device__ __forceinline__ void tile_finish_cx(double (&vr)[16], double (&vi)[16], int64_t aux,
+                                               int rows, int k_pad, size_t slice,
+                                               const CrtConsts& cc, int8_t* __restrict__ out,
+                                               int r0, int h0) {
+  const int t = threadIdx.x;
+  const int rg = r0 + (t >> 3);
+  int8_t* dst = out + (size_t)rg * k_pad + h0 + 16 * (t & 7);
+  if constexpr (MODE == 2) {
+    const int sh = rg < rows ? shift_prime_bits((uint64_t)aux) - 1 : 0;
+    auto bar = [&](double v) {
+      const double x = fabs(v);
+      const double cl = ceil(ldexp(x, sh));
+      return x == 0.0 ? 0 : (cl < 1.0 ? 1 : (int)cl);
+    };
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      w[q] = pack4(bar(vr[4 * q]) + bar(vi[4 * q]), bar(vr[4 * q + 1]) + bar(vi[4 * q + 1]),
+                   bar(vr[4 * q + 2]) + bar(vi[4 * q + 2]), bar(vr[4 * q + 3]) + bar(vi[4 * q + 3]));
+    *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else {
+    if (rg >= rows) return;
+    const int sh = (int)aux;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      vr[e] = trunc(ldexp(vr[e], sh));
+      vi[e] = trunc(ldexp(vi[e], sh));
+    }
+    const size_t set = (size_t)cc.N * slice;
+    for (int l = 0; l < cc.N; ++l) {
+      const int p = cc.p[l], hi = (p - 1) / 2, lo = hi + 1 - p;
+      const double pd = (double)p, pinv = cc.pinv[l];
+      double c1 = 0.0, c2 = 0.0;
+      if constexpr (PATH == kLimbs2) c1 = reduce_last(0x1p48, pd, pinv);
+      if constexpr (PATH == kLimbs3) {
+        c1 = reduce_last(0x1p40, pd, pinv);
+        c2 = reduce_last(c1 * c1, pd, pinv);
+      }
+      // residues of the parts in [-(p-1)/2, (p-1)/2] (odd p) or [-128, 128]
+      // (p = 256, stored as bytes mod 256): one correction puts their sum in
+      // the range
+      uint32_t wr[4], wi[4], ws[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int br[4], bi[4], bs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          br[u] = residue_one<PATH>(vr[4 * q + u], p, pd, pinv, c1, c2);
+          bi[u] = residue_one<PATH>(vi[4 * q + u], p, pd, pinv, c1, c2);
+          int x = br[u] + bi[u];
+          x -= x > hi ? p : 0;
+          bs[u] = x + (x < lo ? p : 0);
+        }
+        wr[q] = pack4(br[0], br[1], br[2], br[3]);
+        wi[q] = pack4(bi[0], bi[1], bi[2], bi[3]);
+        ws[q] = pack4(bs[0], bs[1], bs[2], bs[3]);
+      }
+      int8_t* d = dst + (size_t)l * slice;
+      *reinterpret_cast<uint4*>(d) = make_uint4(wr[0], wr[1], wr[2], wr[3]);
+      *reinterpret_cast<uint4*>(d + set) = make_uint4(wi[0], wi[1], wi[2], wi[3]);
+      *reinterpret_cast<uint4*>(d + 2 * set) = make_uint4(ws[0], ws[1], ws[2], ws[3]);
+    }
+  }
+}
+
+template <typename T, bool TRANS>
+__device__ __forceinline__ void tile_loads_cx(const T* __restrict__ src, int ld, int rows, int k,
+                                              int r0, int h0, T (&x)[16], T (&y)[16]) {
+  const int t = threadIdx.x;
+  if (TRANS) {  // element (r, h) at src[2 (r + h ld)]: as tile_loads, pairs
+    const T* a = src + 2 * (size_t)min(r0 + (t & 31), rows - 1);
+    const int hb = h0 + (t >> 5);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const T* e = a + 2 * ((size_t)min(hb + 8 * q, k - 1) * ld);
+      x[q] = e[0];
+      y[q] = e[1];
+    }
+  } else {      // element (h, r) at src[2 (h + r ld)]
+    const T* a = src + 2 * (size_t)min(h0 + (t & 127), k - 1);
+    const int rb = r0 + (t >> 7);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const T* e = a + 2 * ((size_t)min(rb + 2 * q, rows - 1) * ld);
+      x[q] = e[0];
+      y[q] = e[1];
+    }
+  }
+}
+
+// The grid-stride loop of k_slices over complex tiles: the real parts are
+// staged and read back, then the imaginary parts, then the next tile's loads
+// go out before the arithmetic of this one.
+template <typename T, bool TRANS, int MODE, int PATH>
+__global__ __launch_bounds__(256) void k_slices_cx(const T* __restrict__ src, int ld, int rows,
+                                                   int k, int k_pad, int gy, int tiles,
+                                                   size_t slice, const void* __restrict__ aux,
+                                                   CrtConsts cc, int8_t* __restrict__ out) {
+  __shared__ double tile[kTR * kRS];
+  int i = blockIdx.x;
+  if (i >= tiles) return;
+  int kx, ry;
+  slice_tile<TRANS>(i, k_pad, gy, &kx, &ry);
+  T x[16], y[16];
+  tile_loads_cx<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x, y);
+  int64_t xa = row_aux<MODE>(aux, rows, ry * kTR);
+  for (;;) {
+    const int r0 = ry * kTR, h0 = kx * kTK;
+    double vr[16], vi[16];
+    lds_barrier();                 // every wave is done with the previous tile
+    tile_stage<T, TRANS>(x, rows, k, r0, h0, tile);
+    lds_barrier();
+    tile_row16(tile, vr);
+    lds_barrier();
+    tile_stage<T, TRANS>(y, rows, k, r0, h0, tile);
+    __asm__ volatile("" ::: "memory");  // x, y are free: the next loads reuse their registers
+    const int64_t a = xa;
+    const int ni = i + (int)gridDim.x;
+    if (ni < tiles) {
+      slice_tile<TRANS>(ni, k_pad, gy, &kx, &ry);
+      tile_loads_cx<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x, y);
+      xa = row_aux<MODE>(aux, rows, ry * kTR);
+    }
+    lds_barrier();
+    tile_row16(tile, vi);
+    tile_finish_cx<MODE, PATH>(vr, vi, a, rows, k_pad, slice, cc, out, r0, h0);
+    if (ni >= tiles) break;
+    i = ni;
+  }
+}
+
 // One tile of the grouped launch: which problem side and where.
 struct TileJob {
   const void* src;
@@ -513,6 +693,7 @@ constexpr int kGrouped = 2 + kAnyPath;
 constexpr int kVariants = 2 * kGrouped;
 std::atomic<int> g_cus[kMaxDevices];
 std::atomic<int> g_occ[2][2][kVariants];
+std::atomic<int> g_occ_cx[2][2][kGrouped];   // k_slices_cx: variant 0 = mode 2, 1 + path
 
 template <typename K>
 int resident_per_cu(K* kern) {
@@ -540,18 +721,27 @@ void fill_occ() {
   o[kGrouped + 1 + kSteps3] = resident_per_cu(kg_slices<T, TR, 1, kSteps3>);
   o[kGrouped + 1 + kSteps4] = resident_per_cu(kg_slices<T, TR, 1, kSteps4>);
   o[kGrouped + 1 + kAnyPath] = resident_per_cu(kg_slices<T, TR, 1, kAnyPath>);
+  std::atomic<int>* c = g_occ_cx[std::is_same<T, float>::value ? 1 : 0][TR ? 1 : 0];
+  c[0] = resident_per_cu(k_slices_cx<T, TR, 2, kAnyPath>);
+  c[1 + kLimbs2] = resident_per_cu(k_slices_cx<T, TR, 1, kLimbs2>);
+  c[1 + kLimbs3] = resident_per_cu(k_slices_cx<T, TR, 1, kLimbs3>);
+  c[1 + kSteps1] = resident_per_cu(k_slices_cx<T, TR, 1, kSteps1>);
+  c[1 + kSteps3] = resident_per_cu(k_slices_cx<T, TR, 1, kSteps3>);
+  c[1 + kSteps4] = resident_per_cu(k_slices_cx<T, TR, 1, kSteps4>);
 }
 
 // Workgroups for `tiles` tiles: all resident slots of the device, or one per
 // tile if the device's figures are unknown.  A positive g_slice_cap (a test
 // knob set through ozaki2_debug_tuning) caps the count, so that each
 // workgroup walks many tiles.
-int slice_grid(bool f32, bool trans, int variant, int tiles) {
+int slice_grid(bool f32, bool trans, int variant, int tiles, bool cx = false) {
   int grid = tiles;
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
     const int cus = g_cus[dev].load(std::memory_order_relaxed);
-    const int occ = g_occ[f32 ? 1 : 0][trans ? 1 : 0][variant].load(std::memory_order_relaxed);
+    const int a = f32 ? 1 : 0, b = trans ? 1 : 0;
+    const int occ = (cx ? g_occ_cx[a][b][variant] : g_occ[a][b][variant])
+                        .load(std::memory_order_relaxed);
     if (cus > 0 && occ > 0) grid = (int)std::min<int64_t>(tiles, (int64_t)cus * occ);
   }
   const int cap = g_slice_cap.load(std::memory_order_relaxed);
@@ -595,10 +785,33 @@ void launch_side(hipStream_t s, int mode, const SliceLaunch<T>& L, const CrtCons
   }
 }
 
+template <typename T, bool TR, int MODE, int PATH>
+void launch_one_cx(hipStream_t s, const SliceLaunch<T>& L, const CrtConsts& cc) {
+  const int variant = MODE != 1 ? 0 : 1 + PATH;
+  const dim3 grid((unsigned)slice_grid(std::is_same<T, float>::value, TR, variant, L.tiles, true));
+  hipLaunchKernelGGL((k_slices_cx<T, TR, MODE, PATH>), grid, dim3(256), 0, s, L.src, L.ld, L.rows,
+                     L.k, L.k_pad, L.gy, L.tiles, L.slice, L.aux, cc, L.out);
+}
+
+template <typename T, bool TR>
+void launch_side_cx(hipStream_t s, int mode, const SliceLaunch<T>& L, const CrtConsts& cc) {
+  if (mode == 2) {
+    launch_one_cx<T, TR, 2, kAnyPath>(s, L, cc);
+    return;
+  }
+  switch (residue_path(cc)) {
+    case kLimbs2: launch_one_cx<T, TR, 1, kLimbs2>(s, L, cc); break;
+    case kLimbs3: launch_one_cx<T, TR, 1, kLimbs3>(s, L, cc); break;
+    case kSteps1: launch_one_cx<T, TR, 1, kSteps1>(s, L, cc); break;
+    case kSteps3: launch_one_cx<T, TR, 1, kSteps3>(s, L, cc); break;
+    default: launch_one_cx<T, TR, 1, kSteps4>(s, L, cc); break;
+  }
+}
+
 template <typename T>
 void launch_t(hipStream_t s, int mode, bool trans, const T* src, int ld, int rows, int k,
               int rows_pad, int k_pad, const uint64_t* bits, const int* shift, const CrtConsts& cc,
-              int8_t* out) {
+              int8_t* out, bool cx = false) {
   SliceLaunch<T> L;
   L.src = src;
   L.ld = ld;
@@ -611,10 +824,16 @@ void launch_t(hipStream_t s, int mode, bool trans, const T* src, int ld, int row
   L.aux = mode != 1 ? (const void*)bits : (const void*)shift;
   L.out = out;
   if (L.tiles <= 0) return;
-  if (trans)
+  if (cx) {
+    if (trans)
+      launch_side_cx<T, true>(s, mode, L, cc);
+    else
+      launch_side_cx<T, false>(s, mode, L, cc);
+  } else if (trans) {
     launch_side<T, true>(s, mode, L, cc);
-  else
+  } else {
     launch_side<T, false>(s, mode, L, cc);
+  }
 }
 
 template <typename T, bool TR, int MODE, int PATH>
@@ -722,6 +941,18 @@ void launch_slices(hipStream_t s, Prec pr, int mode, bool trans, const void* src
   else
     launch_t<float>(s, mode, trans, (const float*)src, ld, rows, k, rows_pad, k_pad, bits, shift,
                     cc, out);
+}
+
+void launch_slices_complex(hipStream_t s, Prec pr, int mode, bool trans, const void* src, int ld,
+                           int rows, int k, int rows_pad, int k_pad, const uint64_t* bits,
+                           const int* shift, const CrtConsts& cc, int8_t* out) {
+  if (mode != 1 && mode != 2) return;
+  if (pr == Prec::F64)
+    launch_t<double>(s, mode, trans, (const double*)src, ld, rows, k, rows_pad, k_pad, bits, shift,
+                     cc, out, true);
+  else
+    launch_t<float>(s, mode, trans, (const float*)src, ld, rows, k, rows_pad, k_pad, bits, shift,
+                    cc, out, true);
 }
 
 }  // namespace oz2

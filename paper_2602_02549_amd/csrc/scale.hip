@@ -33,26 +33,43 @@ __global__ void k_init(uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pa
             gridDim.x * blockDim.x);
 }
 
+// Bit pattern of |x| as FP64 (unsigned order = numeric order).
+template <typename T>
+__device__ __forceinline__ uint64_t abs_bits(T x) {
+  return (uint64_t)__double_as_longlong(fabs((double)x));
+}
+
 // A column-major (m x k): one thread per row, a workgroup covers 256 rows and
 // a chunk of 64 columns (workgroup bx + gx * by); consecutive threads read
 // consecutive rows.  Loads go out 16 at a time from clamped (always valid)
-// addresses; a repeated element does not change a maximum.
-template <typename T>
+// addresses; a repeated element does not change a maximum.  CX: A holds
+// interleaved (re, im) pairs (lda in complex elements) and the maximum runs
+// over both parts (the complex 3-product form's shared row shift).
+template <typename T, bool CX = false>
 __device__ __forceinline__ void absmax_rows_body(const T* __restrict__ A, int lda, int m, int k,
                                         uint64_t* __restrict__ rowbits, int* __restrict__ flag,
                                         int bx, int by) {
   const int i = bx * 256 + threadIdx.x;
-  const T* a = A + min(i, m - 1);
+  constexpr int E = CX ? 2 : 1;   // T values per element
+  const T* a = A + (size_t)E * min(i, m - 1);
   const int h0 = by * 64;
   uint64_t mx = 0;
 #pragma unroll
   for (int q0 = 0; q0 < 64; q0 += 16) {
-    T x[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) x[u] = a[(size_t)min(h0 + q0 + u, k - 1) * lda];
+    T x[16], y[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const uint64_t b = (uint64_t)__double_as_longlong(fabs((double)x[u]));
+      const T* e = a + (size_t)E * ((size_t)min(h0 + q0 + u, k - 1) * lda);
+      x[u] = e[0];
+      if (CX) y[u] = e[1];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      uint64_t b = abs_bits(x[u]);
+      if (CX) {
+        const uint64_t c = abs_bits(y[u]);
+        b = c > b ? c : b;
+      }
       mx = b > mx ? b : mx;
     }
   }
@@ -61,35 +78,43 @@ __device__ __forceinline__ void absmax_rows_body(const T* __restrict__ A, int ld
   if (mx) atomicMax((unsigned long long*)&rowbits[i], (unsigned long long)mx);
 }
 
-template <typename T>
+template <typename T, bool CX>
 __global__ __launch_bounds__(256) void k_absmax_rows(const T* __restrict__ A, int lda, int m, int k,
                                                      uint64_t* __restrict__ rowbits,
                                                      int* __restrict__ flag) {
   const int gx = cdiv_i(m, 256);
-  absmax_rows_body<T>(A, lda, m, k, rowbits, flag, blockIdx.x % gx, blockIdx.x / gx);
+  absmax_rows_body<T, CX>(A, lda, m, k, rowbits, flag, blockIdx.x % gx, blockIdx.x / gx);
 }
 
 // B column-major (k x n): one wave per column j (four columns per
-// workgroup), 16 loads in flight per lane; the wave's maximum is stored
-// directly (the wave owns the column), or with ACC merged into the maximum
-// already there (atomicMax: the complex 3-product form takes one maximum
-// over the real and the imaginary part in two passes).
-template <typename T, bool ACC = false>
+// workgroup), 16 loads in flight per lane; the wave owns the column and
+// stores its maximum.  CX: interleaved (re, im) pairs, maximum over both
+// parts, as for the rows.
+template <typename T, bool CX = false>
 __device__ __forceinline__ void absmax_cols_body(const T* __restrict__ B, int ldb, int k, int n,
                                         uint64_t* __restrict__ colbits, int* __restrict__ flag,
                                         int wg) {
   const int lane = threadIdx.x & 63;
   const int j = wg * 4 + (threadIdx.x >> 6);
   if (j >= n) return;   // whole wave
-  const T* col = B + (size_t)j * ldb;
+  constexpr int E = CX ? 2 : 1;
+  const T* col = B + (size_t)E * ((size_t)j * ldb);
   uint64_t mx = 0;
   for (int h0 = 0; h0 < k; h0 += 1024) {
-    T x[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) x[q] = col[min(h0 + lane + 64 * q, k - 1)];
+    T x[16], y[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const uint64_t b = (uint64_t)__double_as_longlong(fabs((double)x[q]));
+      const T* e = col + (size_t)E * min(h0 + lane + 64 * q, k - 1);
+      x[q] = e[0];
+      if (CX) y[q] = e[1];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      uint64_t b = abs_bits(x[q]);
+      if (CX) {
+        const uint64_t c = abs_bits(y[q]);
+        b = c > b ? c : b;
+      }
       mx = b > mx ? b : mx;
     }
   }
@@ -99,19 +124,15 @@ __device__ __forceinline__ void absmax_cols_body(const T* __restrict__ B, int ld
   }
   if (lane == 0) {
     if ((mx & kExpMask) == kExpMask) atomicOr(flag, 1);
-    if constexpr (ACC) {
-      if (mx) atomicMax((unsigned long long*)&colbits[j], (unsigned long long)mx);
-    } else {
-      colbits[j] = mx;
-    }
+    colbits[j] = mx;
   }
 }
 
-template <typename T, bool ACC>
+template <typename T, bool CX>
 __global__ __launch_bounds__(256) void k_absmax_cols(const T* __restrict__ B, int ldb, int k, int n,
                                                      uint64_t* __restrict__ colbits,
                                                      int* __restrict__ flag) {
-  absmax_cols_body<T, ACC>(B, ldb, k, n, colbits, flag, blockIdx.x);
+  absmax_cols_body<T, CX>(B, ldb, k, n, colbits, flag, blockIdx.x);
 }
 
 // B column-major (k x n) with k_pad <= kAbsBarMaxK: the abs-max pass and the
@@ -397,35 +418,40 @@ void launch_init(hipStream_t s, uint64_t* rowbits, int m_pad, uint64_t* colbits,
                      cmax, flag);
 }
 
+template <typename T, bool CX>
+void absmax_rows_t(hipStream_t s, const void* A, int lda, int m, int k, uint64_t* rowbits,
+                   int* flag) {
+  const dim3 grid((unsigned)(cdiv(m, 256) * cdiv(k, 64)));
+  hipLaunchKernelGGL((k_absmax_rows<T, CX>), grid, dim3(256), 0, s, (const T*)A, lda, m, k,
+                     rowbits, flag);
+}
+
+template <typename T, bool CX>
+void absmax_cols_t(hipStream_t s, const void* B, int ldb, int k, int n, uint64_t* colbits,
+                   int* flag) {
+  const dim3 grid((unsigned)absmax_cols_blocks(n));
+  hipLaunchKernelGGL((k_absmax_cols<T, CX>), grid, dim3(256), 0, s, (const T*)B, ldb, k, n,
+                     colbits, flag);
+}
+
 void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, int k,
-                        uint64_t* rowbits, int* flag) {
-  dim3 grid((unsigned)(cdiv(m, 256) * cdiv(k, 64)));
+                        uint64_t* rowbits, int* flag, bool cx) {
   if (pr == Prec::F64)
-    hipLaunchKernelGGL(k_absmax_rows<double>, grid, dim3(256), 0, s, (const double*)A, lda, m, k,
-                       rowbits, flag);
+    cx ? absmax_rows_t<double, true>(s, A, lda, m, k, rowbits, flag)
+       : absmax_rows_t<double, false>(s, A, lda, m, k, rowbits, flag);
   else
-    hipLaunchKernelGGL(k_absmax_rows<float>, grid, dim3(256), 0, s, (const float*)A, lda, m, k,
-                       rowbits, flag);
+    cx ? absmax_rows_t<float, true>(s, A, lda, m, k, rowbits, flag)
+       : absmax_rows_t<float, false>(s, A, lda, m, k, rowbits, flag);
 }
 
 void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,
-                        uint64_t* colbits, int* flag, bool accumulate) {
-  dim3 grid((unsigned)absmax_cols_blocks(n));
-  if (pr == Prec::F64) {
-    if (accumulate)
-      hipLaunchKernelGGL((k_absmax_cols<double, true>), grid, dim3(256), 0, s, (const double*)B,
-                         ldb, k, n, colbits, flag);
-    else
-      hipLaunchKernelGGL((k_absmax_cols<double, false>), grid, dim3(256), 0, s, (const double*)B,
-                         ldb, k, n, colbits, flag);
-  } else {
-    if (accumulate)
-      hipLaunchKernelGGL((k_absmax_cols<float, true>), grid, dim3(256), 0, s, (const float*)B, ldb,
-                         k, n, colbits, flag);
-    else
-      hipLaunchKernelGGL((k_absmax_cols<float, false>), grid, dim3(256), 0, s, (const float*)B,
-                         ldb, k, n, colbits, flag);
-  }
+                        uint64_t* colbits, int* flag, bool cx) {
+  if (pr == Prec::F64)
+    cx ? absmax_cols_t<double, true>(s, B, ldb, k, n, colbits, flag)
+       : absmax_cols_t<double, false>(s, B, ldb, k, n, colbits, flag);
+  else
+    cx ? absmax_cols_t<float, true>(s, B, ldb, k, n, colbits, flag)
+       : absmax_cols_t<float, false>(s, B, ldb, k, n, colbits, flag);
 }
 
 int absbar_group_blocks(int n_pad, int k_pad) { return absbar_blocks(n_pad, k_pad); }

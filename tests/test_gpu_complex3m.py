@@ -24,6 +24,8 @@ import paper_2602_02549_amd as oz  # noqa: E402
     (129, 70, 65, 20, 2.0, np.complex128),
     (64, 257, 60, 49, 1.0, np.complex128),
     (260, 33, 700, 2, 0.5, np.complex128),
+    (70, 50, 90, 28, 1.0, np.complex128),
+    (40, 35, 130, 36, 0.5, np.complex128),
     (200, 150, 130, 7, 0.5, np.complex64),
     (33, 40, 300, 16, 1.0, np.complex64),
 ])
