@@ -532,12 +532,10 @@ int zgemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void*
 // column of B for both parts (Algorithm 2 on Abar = bar(Ar) + bar(Ai) with
 // mu' one lower), residues of A'r, A'i and A'r + A'i, three residue products
 // per modulus, W_re = mod(T1 - T2), W_im = mod(T3 - T1 - T2), the CRT on
-// each part and the inverse scaling, written as complex pairs.  Workspace:
-// the four real planes, then the layout of the m x n x k problem with 3N
-// slices and 3N W (the three groups of N back to back).
-// The 3-product form reads the interleaved complex inputs directly: its
-// workspace is the real layout with 3N slices (three residue sets and three
-// W sets per modulus).
+// each part and the inverse scaling, written as complex pairs.  The kernels
+// read the interleaved complex inputs in place, so the workspace is the
+// layout of the m x n x k problem with 3N slices and 3N W (the three groups
+// of N back to back).
 struct Z3Layout {
   size_t total;
   Layout L;
