@@ -288,21 +288,11 @@ struct PreScale {
   int* flag;
 };
 
-// Output of the real embedding of a complex product (m even): rows i and
-// m/2 + i of the real result are the real and imaginary parts of row i of
-// the complex C (ldc in complex elements), which the CRT writes as pairs.
-struct ComplexOut {
-  void* C;
-  int ldc;
-};
-
 // The launch sequence of Algorithm 1 for one problem (m, n, k >= 1).  With
-// `pre`, the scaling pass is taken from there and not run again; with `zc`,
-// the result goes to the complex C described there (C, ldc unused).
+// `pre`, the scaling pass is taken from there and not run again.
 int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
                  void* C, int ldc, const CrtConsts& cc, const Layout& L, char* ws, int* status,
-                 hipStream_t s, bool want_ef, const PreScale* pre = nullptr,
-                 const ComplexOut* zc = nullptr) {
+                 hipStream_t s, bool want_ef, const PreScale* pre = nullptr) {
   uint64_t* rowbits = at<uint64_t>(ws, L.rowbits);
   uint64_t* colbits = at<uint64_t>(ws, L.colbits);
   int* rmax = at<int>(ws, L.rmax);
@@ -374,11 +364,7 @@ int run_pipeline(Prec pr, int m, int n, int k, const void* A, int lda, const voi
   }
   {
     Scope sc(PH_CRT, s);
-    if (zc)
-      launch_crt_complex(s, pr, W, W + m / 2, (size_t)L.np * L.mp, L.mp, mu, mu + m / 2, nu, m / 2,
-                         n, cc, flag, zc->C, zc->ldc);
-    else
-      launch_crt(s, pr, W, (size_t)L.np * L.mp, L.mp, mu, nu, m, n, cc, flag, C, ldc);
+    launch_crt(s, pr, W, (size_t)L.np * L.mp, L.mp, mu, nu, m, n, cc, flag, C, ldc);
   }
   launch_or_status(s, flag, status);
   return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
@@ -473,18 +459,22 @@ int gemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void* 
 // whose product holds Re AB in rows 1..m and Im AB in rows m+1..2m; the CRT
 // writes the two halves as complex pairs.  The workspace holds Ahat and
 // Bhat, then the real layout of the 2m x n x 2k problem.
+// The real embedding of a complex product, formed in place by the slice
+// kernels: Ahat = [[Ar, -Ai], [Ai, Ar]] with its k halves kh = rup(k, 128)
+// apart and its row halves half = mp / 2 apart (zero rows and columns
+// between them change no product, maximum or shift), Bhat = [[Br], [Bi]]
+// with the same k halves.  The layout is the real one of the
+// 2 half x n x 2 kh problem.
 struct ZLayout {
-  size_t Ah, Bh, real, total;
+  int kh, half;
   Layout L;
 };
 
-ZLayout zlayout(int m, int n, int k, int N, size_t s) {
+ZLayout zlayout(int m, int n, int k, int N) {
   ZLayout Z;
-  Z.Ah = 0;
-  Z.Bh = rup(Z.Ah + s * 4 * (size_t)m * k, 256);
-  Z.real = rup(Z.Bh + s * 2 * (size_t)k * n, 256);
-  Z.L = layout(2 * m, n, 2 * k, N, single_row_pad(2 * m, n, N), N);
-  Z.total = Z.real + Z.L.total;
+  Z.kh = (int)rup((size_t)k, 128);
+  Z.L = layout(2 * m, n, 2 * Z.kh, N, single_row_pad(2 * m, n, N), N);
+  Z.half = Z.L.mp / 2;
   return Z;
 }
 
@@ -517,15 +507,45 @@ int zgemm_impl(Prec pr, int m, int n, int k, const void* A, int lda, const void*
   }
   CrtConsts cc;
   if ((rc = get_consts(N, b, &cc))) return rc;
-  const size_t es = pr == Prec::F64 ? 8 : 4;
-  const ZLayout Z = zlayout(m, n, k, N, es);
+  const ZLayout Z = zlayout(m, n, k, N);
+  const Layout& L = Z.L;
   char* ws;
   int* status;
-  if ((rc = get_workspace(Z.total, &ws, &status))) return rc;
-  launch_embed_complex(s, pr, A, lda, B, ldb, m, n, k, ws + Z.Ah, ws + Z.Bh);
-  const ComplexOut zc{C, ldc};
-  return run_pipeline(pr, 2 * m, n, 2 * k, ws + Z.Ah, 2 * m, ws + Z.Bh, 2 * k, nullptr, 0, cc, Z.L,
-                      ws + Z.real, status, s, false, nullptr, &zc);
+  if ((rc = get_workspace(L.total, &ws, &status))) return rc;
+  uint64_t* rowbits = at<uint64_t>(ws, L.rowbits);
+  uint64_t* colbits = at<uint64_t>(ws, L.colbits);
+  int* rmax = at<int>(ws, L.rmax);
+  int* cmax = at<int>(ws, L.cmax);
+  int* flag = at<int>(ws, L.flag);
+  int* mu = at<int>(ws, L.mu);
+  int* nu = at<int>(ws, L.nu);
+  int8_t* As = at<int8_t>(ws, L.A);
+  int8_t* Bs = at<int8_t>(ws, L.B);
+  int8_t* W = at<int8_t>(ws, L.W);
+  const int H = Z.half;
+  // Algorithm 2 on the embedding: the row maxima of Ahat's rows i and H + i
+  // are both the complex row's maximum over its two parts; a column of Bhat
+  // holds both parts of a column of B.
+  launch_init(s, rowbits, L.mp, colbits, L.np, rmax, cmax, flag);
+  launch_absmax_rows(s, pr, A, lda, m, k, rowbits, flag, true, H);
+  launch_absmax_cols(s, pr, B, ldb, k, n, colbits, flag, true);
+  launch_slices_embed(s, pr, 0, true, A, lda, m, k, Z.kh, L.mp, H, rowbits, nullptr, cc, As);
+  launch_slices_embed(s, pr, 0, false, B, ldb, n, k, Z.kh, L.np, 0, colbits, nullptr, cc, Bs);
+  launch_gemm_i8(s, 1, As, 0, Bs, 0, L.mp, L.np, L.kp, 1, cc, nullptr, 0, 0, rmax, cmax,
+                 at<int8_t>(ws, L.part), L.part_bytes);
+  launch_shifts(s, rowbits, rmax, L.mp, colbits, cmax, n, cc.Pprime, cc.c, at<int>(ws, L.mu_p),
+                at<int>(ws, L.nu_p), mu, nu, nullptr);
+  // Algorithm 3 on the embedding, its residues formed from the complex
+  // source; the CRT writes rows i (real) and H + i (imaginary) as pairs.
+  launch_slices_embed(s, pr, 1, true, A, lda, m, k, Z.kh, L.mp, H, nullptr, mu, cc, As);
+  launch_slices_embed(s, pr, 1, false, B, ldb, n, k, Z.kh, L.np, 0, nullptr, nu, cc, Bs);
+  launch_gemm_i8(s, 0, As, (size_t)L.mp * L.kp, Bs, (size_t)L.np * L.kp, L.mp, L.np, L.kp, N, cc,
+                 W, (size_t)L.np * L.mp, L.mp, nullptr, nullptr, at<int8_t>(ws, L.part),
+                 L.part_bytes);
+  launch_crt_complex(s, pr, W, W + H, (size_t)L.np * L.mp, L.mp, mu, mu + H, nu, m, n, cc, flag, C,
+                     ldc);
+  launch_or_status(s, flag, status);
+  return hipGetLastError() == hipSuccess ? OZAKI2_OK : OZAKI2_ERR_HIP;
 }
 
 // The complex 3-product form (reading R25): one shift per row of A and per
@@ -1162,7 +1182,7 @@ size_t ozaki2_complex_workspace_bytes(int prec, int m, int n, int k, int N) {
   const size_t s = prec == 64 ? 8 : 4;
   const size_t t3 = z3layout(m, n, k, N).total;
   if (k > kMaxK / 2) return t3;   // only the 3-product form takes such k
-  const size_t t4 = zlayout(m, n, k, N, s).total;
+  const size_t t4 = zlayout(m, n, k, N).L.total;
   return t3 > t4 ? t3 : t4;
 }
 

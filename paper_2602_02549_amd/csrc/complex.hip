@@ -1,4 +1,6 @@
-// Complex GEMM through the real embedding (ozaki2_zgemm / ozaki2_cgemm):
+// The real embedding of a complex product, written out (the complex planner
+// ozaki2_zrequired_moduli runs the real planner on it; the GEMM calls form
+// the embedding's slices in place instead):
 //
 //   Ahat = [[Ar, -Ai],      Bhat = [[Br],      Ahat Bhat = [[Re AB],
 //           [Ai,  Ar]]              [Bi]]                   [Im AB]]

@@ -154,9 +154,10 @@ enum class Prec { F64, F32 };
 void launch_init(hipStream_t s, uint64_t* rowbits, int m_pad, uint64_t* colbits, int n_pad,
                  int* rmax, int* cmax, int* flag);
 // cx: the matrix holds interleaved (re, im) pairs (leading dimension in
-// complex elements) and each maximum runs over both parts.
+// complex elements) and each maximum runs over both parts.  dup > 0: row i's
+// maximum also goes to row i + dup.
 void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, int k,
-                        uint64_t* rowbits, int* flag, bool cx = false);
+                        uint64_t* rowbits, int* flag, bool cx = false, int dup = 0);
 void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,
                         uint64_t* colbits, int* flag, bool cx = false);
 // Abs-max of the columns of B and Bbar (slice 0, K-major [n_pad][k_pad]) in
@@ -202,6 +203,18 @@ void launch_slices(hipStream_t s, Prec pr, int mode, bool trans, const void* src
 void launch_slices_complex(hipStream_t s, Prec pr, int mode, bool trans, const void* src, int ld,
                            int rows, int k, int rows_pad, int k_pad, const uint64_t* bits,
                            const int* shift, const CrtConsts& cc, int8_t* out);
+// The slices of the real embedding Ahat = [[Ar, -Ai], [Ai, Ar]],
+// Bhat = [[Br], [Bi]] of a complex product, read from the interleaved
+// complex source in place (modes 0 and 1 as launch_slices).  The embedding
+// is laid out with its halves at aligned offsets, zeros between: k-half kh
+// (a multiple of 128; slice rows are 2 kh long) and, on the A side, row half
+// `half` (rows i and half + i of the embedding come from complex row i;
+// rows_pad = 2 half).  Zero rows and columns change none of the embedding's
+// products, maxima or shifts.  Mode 1 on the A side takes the shifts of row
+// i from shift[i] and of row half + i from shift[half + i].
+void launch_slices_embed(hipStream_t s, Prec pr, int mode, bool aside, const void* src, int ld,
+                         int rows, int k, int kh, int rows_pad, int half, const uint64_t* bits,
+                         const int* shift, const CrtConsts& cc, int8_t* out);
 
 // Planner operands (BF16, K-major [rows_pad][k_pad]) and per-64-k-tile row
 // sums partial[k_pad/64][rows_pad] of |x| 2^-alpha.

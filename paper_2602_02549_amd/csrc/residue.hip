@@ -541,6 +541,141 @@ __global__ __launch_bounds__(256) void k_slices_cx(const T* __restrict__ src, in
   }
 }
 
+// ---- the real embedding of a complex product (ozaki2_zgemm) --------------
+// Ahat = [[Ar, -Ai], [Ai, Ar]] and Bhat = [[Br], [Bi]] written as slices
+// straight from the interleaved complex source: k-half kh (slice rows 2 kh
+// long), and on the A side row half `half`.  A complex element (i, h) of A
+// lands in Ahat at (i, h) as re, (i, kh + h) as -im, (half + i, h) as im and
+// (half + i, kh + h) as re; of B at row j of Bhat^T: (j, h) re, (j, kh + h) im.
+//   mode 0: the bars; rows i and half + i share mu'_i (the same maximum).
+//   mode 1: the residues; row i is scaled by shift[i], row half + i by
+//     shift[half + i] (their Cbar maxima differ).  The residue of -x is the
+//     negated residue of x (the reduction is odd-symmetric; for p = 256 the
+//     byte of -(-128) wraps to -128 as the real kernel's 128 does).
+template <int MODE, int PATH, bool ASIDE>
+__device__ __forceinline__ void tile_finish_emb(const double (&vr)[16], const double (&vi)[16],
+                                                const void* __restrict__ aux, int rows, int ldo,
+                                                int kh, int half, size_t slice,
+                                                const CrtConsts& cc, int8_t* __restrict__ out,
+                                                int r0, int h0) {
+  const int t = threadIdx.x;
+  const int rg = r0 + (t >> 3);
+  int8_t* d0 = out + (size_t)rg * ldo + h0 + 16 * (t & 7);    // (rg, h)
+  int8_t* d1 = d0 + kh;                                         // (rg, kh + h)
+  const size_t dh = (size_t)half * ldo;                         // to row half + rg
+  if constexpr (MODE == 0) {
+    const int sh = rg < rows
+                       ? shift_prime_bits(static_cast<const uint64_t*>(aux)[min(rg, rows - 1)])
+                       : 0;
+    auto bar = [&](double v) {
+      const double x = fabs(v);
+      const double cl = ceil(ldexp(x, sh));
+      return x == 0.0 ? 0 : (cl < 1.0 ? 1 : (int)cl);
+    };
+    uint32_t wr[4], wi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      wr[q] = pack4(bar(vr[4 * q]), bar(vr[4 * q + 1]), bar(vr[4 * q + 2]), bar(vr[4 * q + 3]));
+      wi[q] = pack4(bar(vi[4 * q]), bar(vi[4 * q + 1]), bar(vi[4 * q + 2]), bar(vi[4 * q + 3]));
+    }
+    const uint4 ur = make_uint4(wr[0], wr[1], wr[2], wr[3]), ui = make_uint4(wi[0], wi[1], wi[2], wi[3]);
+    *reinterpret_cast<uint4*>(d0) = ur;
+    *reinterpret_cast<uint4*>(d1) = ui;
+    if (ASIDE) {
+      *reinterpret_cast<uint4*>(d0 + dh) = ui;
+      *reinterpret_cast<uint4*>(d1 + dh) = ur;
+    }
+  } else {
+    if (rg >= rows) return;
+    const int* sh = static_cast<const int*>(aux);
+    // block 0: rows rg (A side) or the only row (B side); block 1: row half + rg
+    for (int blk = 0; blk < (ASIDE ? 2 : 1); ++blk) {
+      const int e2 = sh[rg + blk * half];
+      double xr[16], xi[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        xr[e] = trunc(ldexp(vr[e], e2));
+        xi[e] = trunc(ldexp(vi[e], e2));
+      }
+      int8_t* b0 = d0 + blk * dh;
+      int8_t* b1 = d1 + blk * dh;
+      for (int l = 0; l < cc.N; ++l) {
+        const int p = cc.p[l];
+        const double pd = (double)p, pinv = cc.pinv[l];
+        double c1 = 0.0, c2 = 0.0;
+        if constexpr (PATH == kLimbs2) c1 = reduce_last(0x1p48, pd, pinv);
+        if constexpr (PATH == kLimbs3) {
+          c1 = reduce_last(0x1p40, pd, pinv);
+          c2 = reduce_last(c1 * c1, pd, pinv);
+        }
+        uint32_t first[4], second[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int br[4], bi[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            br[u] = residue_one<PATH>(xr[4 * q + u], p, pd, pinv, c1, c2);
+            bi[u] = residue_one<PATH>(xi[4 * q + u], p, pd, pinv, c1, c2);
+          }
+          // A side: row rg holds [re, -im], row half + rg [im, re]; B side [re, im]
+          if (!ASIDE) {
+            first[q] = pack4(br[0], br[1], br[2], br[3]);
+            second[q] = pack4(bi[0], bi[1], bi[2], bi[3]);
+          } else if (blk == 0) {
+            first[q] = pack4(br[0], br[1], br[2], br[3]);
+            second[q] = pack4(-bi[0], -bi[1], -bi[2], -bi[3]);
+          } else {
+            first[q] = pack4(bi[0], bi[1], bi[2], bi[3]);
+            second[q] = pack4(br[0], br[1], br[2], br[3]);
+          }
+        }
+        *reinterpret_cast<uint4*>(b0 + (size_t)l * slice) =
+            make_uint4(first[0], first[1], first[2], first[3]);
+        *reinterpret_cast<uint4*>(b1 + (size_t)l * slice) =
+            make_uint4(second[0], second[1], second[2], second[3]);
+      }
+    }
+  }
+}
+
+// Grid-stride loop as k_slices_cx over the complex source's tiles (kh / 128
+// k tiles by gy row tiles).
+template <typename T, bool TRANS, int MODE, int PATH>
+__global__ __launch_bounds__(256) void k_slices_emb(const T* __restrict__ src, int ld, int rows,
+                                                    int k, int kh, int gy, int tiles, int half,
+                                                    size_t slice, const void* __restrict__ aux,
+                                                    CrtConsts cc, int8_t* __restrict__ out) {
+  __shared__ double tile[kTR * kRS];
+  int i = blockIdx.x;
+  if (i >= tiles) return;
+  int kx, ry;
+  slice_tile<TRANS>(i, kh, gy, &kx, &ry);
+  T x[16], y[16];
+  tile_loads_cx<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x, y);
+  for (;;) {
+    const int r0 = ry * kTR, h0 = kx * kTK;
+    double vr[16], vi[16];
+    lds_barrier();                 // every wave is done with the previous tile
+    tile_stage<T, TRANS>(x, rows, k, r0, h0, tile);
+    lds_barrier();
+    tile_row16(tile, vr);
+    lds_barrier();
+    tile_stage<T, TRANS>(y, rows, k, r0, h0, tile);
+    __asm__ volatile("" ::: "memory");  // x, y are free: the next loads reuse their registers
+    const int ni = i + (int)gridDim.x;
+    if (ni < tiles) {
+      slice_tile<TRANS>(ni, kh, gy, &kx, &ry);
+      tile_loads_cx<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x, y);
+    }
+    lds_barrier();
+    tile_row16(tile, vi);
+    tile_finish_emb<MODE, PATH, TRANS>(vr, vi, aux, rows, 2 * kh, kh, half, slice, cc, out, r0,
+                                       h0);
+    if (ni >= tiles) break;
+    i = ni;
+  }
+}
+
 // One tile of the grouped launch: which problem side and where.
 struct TileJob {
   const void* src;
@@ -694,6 +829,7 @@ constexpr int kVariants = 2 * kGrouped;
 std::atomic<int> g_cus[kMaxDevices];
 std::atomic<int> g_occ[2][2][kVariants];
 std::atomic<int> g_occ_cx[2][2][kGrouped];   // k_slices_cx: variant 0 = mode 2, 1 + path
+std::atomic<int> g_occ_emb[2][2][kGrouped];  // k_slices_emb: variant 0 = mode 0, 1 + path
 
 template <typename K>
 int resident_per_cu(K* kern) {
@@ -728,19 +864,29 @@ void fill_occ() {
   c[1 + kSteps1] = resident_per_cu(k_slices_cx<T, TR, 1, kSteps1>);
   c[1 + kSteps3] = resident_per_cu(k_slices_cx<T, TR, 1, kSteps3>);
   c[1 + kSteps4] = resident_per_cu(k_slices_cx<T, TR, 1, kSteps4>);
+  std::atomic<int>* b = g_occ_emb[std::is_same<T, float>::value ? 1 : 0][TR ? 1 : 0];
+  b[0] = resident_per_cu(k_slices_emb<T, TR, 0, kAnyPath>);
+  b[1 + kLimbs2] = resident_per_cu(k_slices_emb<T, TR, 1, kLimbs2>);
+  b[1 + kLimbs3] = resident_per_cu(k_slices_emb<T, TR, 1, kLimbs3>);
+  b[1 + kSteps1] = resident_per_cu(k_slices_emb<T, TR, 1, kSteps1>);
+  b[1 + kSteps3] = resident_per_cu(k_slices_emb<T, TR, 1, kSteps3>);
+  b[1 + kSteps4] = resident_per_cu(k_slices_emb<T, TR, 1, kSteps4>);
 }
 
 // Workgroups for `tiles` tiles: all resident slots of the device, or one per
 // tile if the device's figures are unknown.  A positive g_slice_cap (a test
 // knob set through ozaki2_debug_tuning) caps the count, so that each
 // workgroup walks many tiles.
-int slice_grid(bool f32, bool trans, int variant, int tiles, bool cx = false) {
+// kind: 0 = k_slices, 1 = k_slices_cx, 2 = k_slices_emb.
+int slice_grid(bool f32, bool trans, int variant, int tiles, int kind = 0) {
   int grid = tiles;
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
     const int cus = g_cus[dev].load(std::memory_order_relaxed);
     const int a = f32 ? 1 : 0, b = trans ? 1 : 0;
-    const int occ = (cx ? g_occ_cx[a][b][variant] : g_occ[a][b][variant])
+    const int occ = (kind == 1   ? g_occ_cx[a][b][variant]
+                     : kind == 2 ? g_occ_emb[a][b][variant]
+                                 : g_occ[a][b][variant])
                         .load(std::memory_order_relaxed);
     if (cus > 0 && occ > 0) grid = (int)std::min<int64_t>(tiles, (int64_t)cus * occ);
   }
@@ -788,7 +934,7 @@ void launch_side(hipStream_t s, int mode, const SliceLaunch<T>& L, const CrtCons
 template <typename T, bool TR, int MODE, int PATH>
 void launch_one_cx(hipStream_t s, const SliceLaunch<T>& L, const CrtConsts& cc) {
   const int variant = MODE != 1 ? 0 : 1 + PATH;
-  const dim3 grid((unsigned)slice_grid(std::is_same<T, float>::value, TR, variant, L.tiles, true));
+  const dim3 grid((unsigned)slice_grid(std::is_same<T, float>::value, TR, variant, L.tiles, 1));
   hipLaunchKernelGGL((k_slices_cx<T, TR, MODE, PATH>), grid, dim3(256), 0, s, L.src, L.ld, L.rows,
                      L.k, L.k_pad, L.gy, L.tiles, L.slice, L.aux, cc, L.out);
 }
@@ -941,6 +1087,63 @@ void launch_slices(hipStream_t s, Prec pr, int mode, bool trans, const void* src
   else
     launch_t<float>(s, mode, trans, (const float*)src, ld, rows, k, rows_pad, k_pad, bits, shift,
                     cc, out);
+}
+
+namespace {
+
+template <typename T, bool TR, int MODE, int PATH>
+void emb_one(hipStream_t s, const T* src, int ld, int rows, int k, int kh, int gy, int tiles,
+             int half, size_t slice, const void* aux, const CrtConsts& cc, int8_t* out) {
+  const int variant = MODE == 0 ? 0 : 1 + PATH;
+  const dim3 grid((unsigned)slice_grid(std::is_same<T, float>::value, TR, variant, tiles, 2));
+  hipLaunchKernelGGL((k_slices_emb<T, TR, MODE, PATH>), grid, dim3(256), 0, s, src, ld, rows, k,
+                     kh, gy, tiles, half, slice, aux, cc, out);
+}
+
+template <typename T, bool TR>
+void emb_side(hipStream_t s, int mode, const T* src, int ld, int rows, int k, int kh, int rows_pad,
+              int half, const uint64_t* bits, const int* shift, const CrtConsts& cc, int8_t* out) {
+  // mode 0 covers the padding rows (their bars must be zero); mode 1 only
+  // the tiles of real rows.  On the A side the tiles cover the first half.
+  const int span = TR ? half : rows_pad;
+  const int gy = mode == 0 ? span / kTR : cdiv_i(rows, kTR);
+  const int tiles = (kh / kTK) * gy;
+  const size_t slice = (size_t)rows_pad * 2 * kh;
+  if (tiles <= 0) return;
+  if (mode == 0) {
+    emb_one<T, TR, 0, kAnyPath>(s, src, ld, rows, k, kh, gy, tiles, half, slice, bits, cc, out);
+    return;
+  }
+  switch (residue_path(cc)) {
+    case kLimbs2: emb_one<T, TR, 1, kLimbs2>(s, src, ld, rows, k, kh, gy, tiles, half, slice, shift, cc, out); break;
+    case kLimbs3: emb_one<T, TR, 1, kLimbs3>(s, src, ld, rows, k, kh, gy, tiles, half, slice, shift, cc, out); break;
+    case kSteps1: emb_one<T, TR, 1, kSteps1>(s, src, ld, rows, k, kh, gy, tiles, half, slice, shift, cc, out); break;
+    case kSteps3: emb_one<T, TR, 1, kSteps3>(s, src, ld, rows, k, kh, gy, tiles, half, slice, shift, cc, out); break;
+    default: emb_one<T, TR, 1, kSteps4>(s, src, ld, rows, k, kh, gy, tiles, half, slice, shift, cc, out); break;
+  }
+}
+
+}  // namespace
+
+void launch_slices_embed(hipStream_t s, Prec pr, int mode, bool aside, const void* src, int ld,
+                         int rows, int k, int kh, int rows_pad, int half, const uint64_t* bits,
+                         const int* shift, const CrtConsts& cc, int8_t* out) {
+  if (mode != 0 && mode != 1) return;
+  if (pr == Prec::F64) {
+    if (aside)
+      emb_side<double, true>(s, mode, (const double*)src, ld, rows, k, kh, rows_pad, half, bits,
+                             shift, cc, out);
+    else
+      emb_side<double, false>(s, mode, (const double*)src, ld, rows, k, kh, rows_pad, 0, bits,
+                              shift, cc, out);
+  } else {
+    if (aside)
+      emb_side<float, true>(s, mode, (const float*)src, ld, rows, k, kh, rows_pad, half, bits,
+                            shift, cc, out);
+    else
+      emb_side<float, false>(s, mode, (const float*)src, ld, rows, k, kh, rows_pad, 0, bits, shift,
+                             cc, out);
+  }
 }
 
 void launch_slices_complex(hipStream_t s, Prec pr, int mode, bool trans, const void* src, int ld,

@@ -48,7 +48,7 @@ __device__ __forceinline__ uint64_t abs_bits(T x) {
 template <typename T, bool CX = false>
 __device__ __forceinline__ void absmax_rows_body(const T* __restrict__ A, int lda, int m, int k,
                                         uint64_t* __restrict__ rowbits, int* __restrict__ flag,
-                                        int bx, int by) {
+                                        int bx, int by, int dup = 0) {
   const int i = bx * 256 + threadIdx.x;
   constexpr int E = CX ? 2 : 1;   // T values per element
   const T* a = A + (size_t)E * min(i, m - 1);
@@ -75,15 +75,20 @@ __device__ __forceinline__ void absmax_rows_body(const T* __restrict__ A, int ld
   }
   if (i >= m) return;
   if ((mx & kExpMask) == kExpMask) atomicOr(flag, 1);
-  if (mx) atomicMax((unsigned long long*)&rowbits[i], (unsigned long long)mx);
+  if (mx) {
+    atomicMax((unsigned long long*)&rowbits[i], (unsigned long long)mx);
+    // dup > 0: the same maximum for row i + dup (the two row blocks of the
+    // real embedding of a complex matrix)
+    if (dup) atomicMax((unsigned long long*)&rowbits[i + dup], (unsigned long long)mx);
+  }
 }
 
 template <typename T, bool CX>
 __global__ __launch_bounds__(256) void k_absmax_rows(const T* __restrict__ A, int lda, int m, int k,
                                                      uint64_t* __restrict__ rowbits,
-                                                     int* __restrict__ flag) {
+                                                     int* __restrict__ flag, int dup) {
   const int gx = cdiv_i(m, 256);
-  absmax_rows_body<T, CX>(A, lda, m, k, rowbits, flag, blockIdx.x % gx, blockIdx.x / gx);
+  absmax_rows_body<T, CX>(A, lda, m, k, rowbits, flag, blockIdx.x % gx, blockIdx.x / gx, dup);
 }
 
 // B column-major (k x n): one wave per column j (four columns per
@@ -420,10 +425,10 @@ void launch_init(hipStream_t s, uint64_t* rowbits, int m_pad, uint64_t* colbits,
 
 template <typename T, bool CX>
 void absmax_rows_t(hipStream_t s, const void* A, int lda, int m, int k, uint64_t* rowbits,
-                   int* flag) {
+                   int* flag, int dup) {
   const dim3 grid((unsigned)(cdiv(m, 256) * cdiv(k, 64)));
   hipLaunchKernelGGL((k_absmax_rows<T, CX>), grid, dim3(256), 0, s, (const T*)A, lda, m, k,
-                     rowbits, flag);
+                     rowbits, flag, dup);
 }
 
 template <typename T, bool CX>
@@ -435,13 +440,13 @@ void absmax_cols_t(hipStream_t s, const void* B, int ldb, int k, int n, uint64_t
 }
 
 void launch_absmax_rows(hipStream_t s, Prec pr, const void* A, int lda, int m, int k,
-                        uint64_t* rowbits, int* flag, bool cx) {
+                        uint64_t* rowbits, int* flag, bool cx, int dup) {
   if (pr == Prec::F64)
-    cx ? absmax_rows_t<double, true>(s, A, lda, m, k, rowbits, flag)
-       : absmax_rows_t<double, false>(s, A, lda, m, k, rowbits, flag);
+    cx ? absmax_rows_t<double, true>(s, A, lda, m, k, rowbits, flag, dup)
+       : absmax_rows_t<double, false>(s, A, lda, m, k, rowbits, flag, dup);
   else
-    cx ? absmax_rows_t<float, true>(s, A, lda, m, k, rowbits, flag)
-       : absmax_rows_t<float, false>(s, A, lda, m, k, rowbits, flag);
+    cx ? absmax_rows_t<float, true>(s, A, lda, m, k, rowbits, flag, dup)
+       : absmax_rows_t<float, false>(s, A, lda, m, k, rowbits, flag, dup);
 }
 
 void launch_absmax_cols(hipStream_t s, Prec pr, const void* B, int ldb, int k, int n,

@@ -21,6 +21,9 @@ import paper_2602_02549_amd as oz  # noqa: E402
     (1, 1, 1, 7, 0.5, np.complex128),
     (129, 70, 65, 20, 2.0, np.complex128),
     (64, 257, 100, 49, 1.0, np.complex128),
+    (65, 33, 256, 28, 1.0, np.complex128),    # three limbs; k a multiple of 128
+    (40, 35, 129, 36, 0.5, np.complex128),    # three exact steps; k just past 128
+    (70, 20, 300, 2, 0.5, np.complex128),
     (200, 150, 130, 7, 0.5, np.complex64),
     (33, 40, 300, 16, 1.0, np.complex64),
 ])
