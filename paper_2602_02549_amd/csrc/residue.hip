@@ -645,16 +645,21 @@ __global__ __launch_bounds__(256) void k_slices_emb(const T* __restrict__ src, i
                                                     int k, int kh, int gy, int tiles, int half,
                                                     size_t slice, const void* __restrict__ aux,
                                                     CrtConsts cc, int8_t* __restrict__ out) {
+  // The A side's residues (two row blocks, four stores per modulus) hold
+  // the most registers: there the next tile's loads are not issued early,
+  // which lets two workgroups share a CU instead of one.
+  constexpr bool kPrefetch = !(TRANS && MODE == 1);
   __shared__ double tile[kTR * kRS];
   int i = blockIdx.x;
   if (i >= tiles) return;
   int kx, ry;
   slice_tile<TRANS>(i, kh, gy, &kx, &ry);
   T x[16], y[16];
-  tile_loads_cx<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x, y);
+  if (kPrefetch) tile_loads_cx<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x, y);
   for (;;) {
     const int r0 = ry * kTR, h0 = kx * kTK;
     double vr[16], vi[16];
+    if (!kPrefetch) tile_loads_cx<T, TRANS>(src, ld, rows, k, r0, h0, x, y);
     lds_barrier();                 // every wave is done with the previous tile
     tile_stage<T, TRANS>(x, rows, k, r0, h0, tile);
     lds_barrier();
@@ -665,7 +670,7 @@ __global__ __launch_bounds__(256) void k_slices_emb(const T* __restrict__ src, i
     const int ni = i + (int)gridDim.x;
     if (ni < tiles) {
       slice_tile<TRANS>(ni, kh, gy, &kx, &ry);
-      tile_loads_cx<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x, y);
+      if (kPrefetch) tile_loads_cx<T, TRANS>(src, ld, rows, k, ry * kTR, kx * kTK, x, y);
     }
     lds_barrier();
     tile_row16(tile, vi);
