@@ -426,7 +426,7 @@ def vendor_int8(torch, dev, size: int, reps: int = 5) -> dict:
     b = torch.randint(-128, 128, (size, size), dtype=torch.int8, device=dev, generator=g)
     try:
         ms = _time_ms(torch, lambda: torch._int_mm(a, b), reps)
-    except RuntimeError as exc:      # not available in this build
+    except RuntimeError as exc:      # not available in this torch
         return {"error": str(exc)[:200]}
     ops = 2.0 * size ** 3
     return {"op": "torch._int_mm (hipBLASLt INT8 GEMM)", "size": size, "ms": round(ms, 4),
